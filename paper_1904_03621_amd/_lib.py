@@ -1,0 +1,148 @@
+"""ctypes binding of libsgpu.so (include/sg.h).  Argument marshalling only:
+every step of the search runs in the library's HIP kernels.
+
+The functions named ``sg_*`` mirror the C entry points one to one and take
+torch tensors that already live on the GPU (the library reads and writes
+them through their device pointers, on the current HIP stream).
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsgpu.so")
+
+SG_OK, SG_EINVAL, SG_ENONFINITE, SG_EOVERFLOW, SG_ENOMEM, SG_EHIP, \
+    SG_EUNSUPPORTED, SG_EDRIFT, SG_ECAPACITY = range(9)
+STATUS_NAMES = {
+    0: "SG_OK", 1: "SG_EINVAL", 2: "SG_ENONFINITE", 3: "SG_EOVERFLOW", 4: "SG_ENOMEM",
+    5: "SG_EHIP", 6: "SG_EUNSUPPORTED", 7: "SG_EDRIFT", 8: "SG_ECAPACITY",
+}
+SG_MAX_N = 56
+SG_MAX_S = 1 << 20
+
+# every symbol include/sg.h declares
+EXPORTS = [
+    "sg_low_spectrum_f32", "sg_low_spectrum_i32",
+    "sg_low_spectrum_range_f32", "sg_low_spectrum_range_i32",
+    "sg_get_error", "sg_last_error", "sg_get_run_info", "sg_debug_plan",
+]
+
+
+class SgError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        self.status = status
+        super().__init__("%s: %s (%s)" % (where, STATUS_NAMES.get(status, status), msg))
+
+
+class RunInfo(ctypes.Structure):
+    _fields_ = [
+        ("chunks", ctypes.c_int64),
+        ("candidates", ctypes.c_int64),
+        ("slow_blocks", ctypes.c_int64),
+        ("margin", ctypes.c_double),
+        ("max_drift", ctypes.c_double),
+        ("prefix_bits_max", ctypes.c_int32),
+        ("free_bits_max", ctypes.c_int32),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                "libsgpu.so is not built (%s); run __graft_entry__.build() or "
+                "python paper_1904_03621_amd/build.py" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, u64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64
+        for name in ("sg_low_spectrum_f32", "sg_low_spectrum_i32"):
+            f = getattr(L, name)
+            f.restype = i32
+            f.argtypes = [i32, vp, vp, i32, vp, vp, vp]
+        for name in ("sg_low_spectrum_range_f32", "sg_low_spectrum_range_i32"):
+            f = getattr(L, name)
+            f.restype = i32
+            f.argtypes = [i32, vp, vp, i32, u64, u64, vp, vp, vp]
+        L.sg_get_error.restype = i32
+        L.sg_get_error.argtypes = [vp]
+        L.sg_last_error.restype = ctypes.c_char_p
+        L.sg_last_error.argtypes = []
+        L.sg_get_run_info.restype = i32
+        L.sg_get_run_info.argtypes = [vp, ctypes.POINTER(RunInfo)]
+        L.sg_debug_plan.restype = i32
+        L.sg_debug_plan.argtypes = [i32, i32, u64, u64, ctypes.c_int64,
+                                    ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_int32),
+                                    ctypes.POINTER(ctypes.c_int64), i32]
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().sg_last_error().decode()
+
+
+def check(status: int, where: str) -> None:
+    if status != SG_OK:
+        raise SgError(status, where, last_error())
+
+
+def _ptr(t) -> int:
+    return t.data_ptr()
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return int(getattr(stream, "cuda_stream", stream) or 0)
+
+
+def sg_low_spectrum_f32(N, J, h, S, states_out, energies_out, stream=None) -> int:
+    return lib().sg_low_spectrum_f32(N, _ptr(J), _ptr(h), S, _ptr(states_out),
+                                     _ptr(energies_out), _stream(stream))
+
+
+def sg_low_spectrum_i32(N, J, h, S, states_out, energies_out, stream=None) -> int:
+    return lib().sg_low_spectrum_i32(N, _ptr(J), _ptr(h), S, _ptr(states_out),
+                                     _ptr(energies_out), _stream(stream))
+
+
+def sg_low_spectrum_range_f32(N, J, h, S, lo, hi, states_out, energies_out, stream=None) -> int:
+    return lib().sg_low_spectrum_range_f32(N, _ptr(J), _ptr(h), S, lo, hi, _ptr(states_out),
+                                           _ptr(energies_out), _stream(stream))
+
+
+def sg_low_spectrum_range_i32(N, J, h, S, lo, hi, states_out, energies_out, stream=None) -> int:
+    return lib().sg_low_spectrum_range_i32(N, _ptr(J), _ptr(h), S, lo, hi, _ptr(states_out),
+                                           _ptr(energies_out), _stream(stream))
+
+
+def sg_get_error(stream=None) -> int:
+    return lib().sg_get_error(_stream(stream))
+
+
+def sg_get_run_info(stream=None) -> dict:
+    info = RunInfo()
+    check(lib().sg_get_run_info(_stream(stream), ctypes.byref(info)), "sg_get_run_info")
+    return info.as_dict()
+
+
+def sg_debug_plan(N, S, lo, hi, lanes_fill, cap=100000):
+    fm = (ctypes.c_uint64 * cap)()
+    nb = (ctypes.c_int32 * cap)()
+    ln = (ctypes.c_int64 * cap)()
+    k = lib().sg_debug_plan(N, S, lo, hi, lanes_fill, fm, nb, ln, cap)
+    if k < 0:
+        raise SgError(SG_EINVAL, "sg_debug_plan", "bad arguments")
+    k = min(k, cap)
+    return [(int(fm[i]), int(nb[i]), int(ln[i])) for i in range(k)]

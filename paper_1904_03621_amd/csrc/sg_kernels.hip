@@ -1,0 +1,771 @@
+// sg_kernels.hip -- gfx950 kernels of the exhaustive low-spectrum search.
+//
+// Pipeline per search (all on one stream, no host round trip):
+//   k_prep      instance checks, |J|+|h| bound, pruning margin, Q tables
+//   k_tables    per-block records of every free-spin count n in use
+//   per chunk (Sec. 3, Algorithm 1, one chunk of the state space):
+//     k_enum    Gray-code enumeration, one lane per prefix; candidates out
+//     k_score   exact energy of every candidate, keep those beating the
+//               current S-th key
+//     k_merge   sort the survivors, merge them into the running top-S record,
+//               update the threshold
+//   k_finalize  record -> caller's output arrays
+//
+// Energy of Eq. (1), mask bit i <-> spin i, bit set <-> s_i = +1.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sg_internal.h"
+
+namespace sg {
+
+// ------------------------------------------------------------------ helpers
+
+__device__ inline float jf(const float* J, int N, int a, int b) {
+  return a < b ? J[a * N + b] : J[b * N + a];
+}
+__device__ inline int32_t ji(const int32_t* J, int N, int a, int b) {
+  return a < b ? J[a * N + b] : J[b * N + a];
+}
+
+__device__ inline uint32_t gray32(uint32_t t) { return t ^ (t >> 1); }
+
+// Energy of one state from scratch, Eq. (1), fixed i<j order.
+__device__ inline double energy_f64(const float* J, const float* h, int N, uint64_t m) {
+  double e = 0.0;
+  for (int i = 0; i < N; ++i) {
+    const double si = ((m >> i) & 1ull) ? 1.0 : -1.0;
+    double f = (double)h[i];
+    for (int j = i + 1; j < N; ++j) {
+      const double sj = ((m >> j) & 1ull) ? 1.0 : -1.0;
+      f += (double)J[i * N + j] * sj;
+    }
+    e -= si * f;
+  }
+  return e;
+}
+
+__device__ inline int32_t energy_i32(const int32_t* J, const int32_t* h, int N, uint64_t m) {
+  int32_t e = 0;
+  for (int i = 0; i < N; ++i) {
+    const int32_t si = ((m >> i) & 1ull) ? 1 : -1;
+    int32_t f = h[i];
+    for (int j = i + 1; j < N; ++j) {
+      const int32_t sj = ((m >> j) & 1ull) ? 1 : -1;
+      f += J[i * N + j] * sj;
+    }
+    e -= si * f;
+  }
+  return e;
+}
+
+// float nearest to x from below / above (x finite)
+__device__ inline float f32_down(double x) {
+  float f = (float)x;
+  if ((double)f > x) f = __uint_as_float(f > 0.0f ? __float_as_uint(f) - 1u
+                                          : (f == 0.0f ? 0x80000001u : __float_as_uint(f) + 1u));
+  return f;
+}
+__device__ inline float f32_up(double x) {
+  float f = (float)x;
+  if ((double)f < x) f = __uint_as_float(f < 0.0f ? __float_as_uint(f) - 1u
+                                          : (f == 0.0f ? 0x00000001u : __float_as_uint(f) + 1u));
+  return f;
+}
+
+__device__ inline uint32_t key_f32(float e) {
+  if (e == 0.0f) e = 0.0f;  // -0 -> +0
+  return key_of_f32_bits(__float_as_uint(e));
+}
+
+__device__ inline bool key_less(uint32_t ka, uint64_t ma, uint32_t kb, uint64_t mb) {
+  return ka < kb || (ka == kb && ma < mb);
+}
+
+// Wave-aggregated append of one mask per active lane.
+__device__ inline void append_mask(uint64_t mask, Params* P, uint64_t* cand, uint32_t cap) {
+  const uint64_t act = __ballot(1);
+  const int lid = __lane_id();
+  const int leader = __ffsll((unsigned long long)act) - 1;
+  const uint32_t cnt = (uint32_t)__popcll(act);
+  uint32_t base = 0;
+  if (lid == leader) base = atomicAdd(&P->cand_count, cnt);
+  base = __shfl(base, leader);
+  const uint64_t below = act & ((1ull << lid) - 1ull);
+  const uint32_t slot = base + (uint32_t)__popcll(below);
+  if (slot < cap) {
+    cand[slot] = mask;
+  } else {
+    atomicOr(&P->err, kErrCapacity);
+  }
+}
+
+// ------------------------------------------------------------------ k_prep
+// One workgroup.  Writes the Q tables (low-spin coupling energy for both
+// block parities), their minimum, the pruning margin, the error flags and the
+// initial (empty) record state.
+
+template <bool kInt>
+__global__ void k_prep(const void* Jv, const void* hv, int N, int S, Params* P,
+                       uint32_t* qtab) {
+  __shared__ double s_sum[256];
+  __shared__ int s_bad[256];
+  const int tid = threadIdx.x;
+  double acc = 0.0;
+  int bad = 0;
+  for (int idx = tid; idx < N * N + N; idx += blockDim.x) {
+    double v;
+    bool use;
+    if (idx < N * N) {
+      const int i = idx / N, j = idx % N;
+      use = i < j;
+      v = kInt ? (double)((const int32_t*)Jv)[idx] : (double)((const float*)Jv)[idx];
+    } else {
+      use = true;
+      v = kInt ? (double)((const int32_t*)hv)[idx - N * N] : (double)((const float*)hv)[idx - N * N];
+    }
+    if (use) {
+      if (!kInt && !isfinite(v)) bad = 1;
+      else acc += fabs(v);
+    }
+  }
+  s_sum[tid] = acc;
+  s_bad[tid] = bad;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (tid < st) {
+      s_sum[tid] += s_sum[tid + st];
+      s_bad[tid] |= s_bad[tid + st];
+    }
+    __syncthreads();
+  }
+  const double Bv = s_sum[0];
+  const int anybad = s_bad[0];
+
+  // Q tables: Q(x) = -sum_{f<f'<U} J_ff' s_f s_f' over the low configuration
+  // x = gray(i) ^ (par << (U-1)) of step i in a block of parity par.
+  const int U = kU;
+  __shared__ double s_q[2 * kBlockSteps];
+  if (tid < 2 * kBlockSteps) {
+    const int par = tid / kBlockSteps, i = tid % kBlockSteps;
+    const uint32_t x = gray32((uint32_t)i) ^ ((uint32_t)par << (U - 1));
+    double q = 0.0;
+    for (int a = 0; a < U && a < N; ++a)
+      for (int b = a + 1; b < U && b < N; ++b) {
+        const double sa = ((x >> a) & 1u) ? 1.0 : -1.0, sb = ((x >> b) & 1u) ? 1.0 : -1.0;
+        const double jv = kInt ? (double)((const int32_t*)Jv)[a * N + b]
+                               : (double)((const float*)Jv)[a * N + b];
+        q -= jv * sa * sb;
+      }
+    s_q[tid] = q;
+    if (kInt) qtab[tid] = (uint32_t)(int32_t)q;
+    else qtab[tid] = __float_as_uint((float)q);
+  }
+  __syncthreads();
+  for (int st = kBlockSteps; st > 0; st >>= 1) {
+    if (tid < st) s_q[tid] = fmin(s_q[tid], s_q[tid + st]);
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const double qmin = s_q[0];
+    uint32_t err = 0;
+    if (anybad) err |= kErrNonFinite;
+    if (kInt && Bv >= 268435456.0) err |= kErrOverflow;  // 2^28
+    // Margin (fp32): a bound on |computed G - exact G| + the rounding of the
+    // rescored key.  Exact G, W, Y, boundary constants and energies are all
+    // bounded by 2 Bv; the computed ones stay below 2 Bv + margin < 2.1 Bv
+    // (margin < 0.03 Bv below), so each fp32 rounding is at most
+    // uH = H 2^-24 with H the power of two above 2.1 Bv.  Between two
+    // re-anchors a lane crosses at most R = 2^16 / 2^U block boundaries, and
+    // per block G takes 63 rounded inner adds, 2 rounded boundary adds and a
+    // rounded boundary constant; the block's W values carry three roundings
+    // each and enter the block's sum with net weight at most 1 (a spin's
+    // flips alternate in sign).  Add the anchor (2 + n/2 roundings), the
+    // high fields (net weight <= 1 each over any stretch, n of them), the
+    // final E = G + Q (2) and the key rounding (2).
+    double margin = 0.0;
+    if (!kInt) {
+      double H = 1.0;
+      while (H <= 2.1 * Bv) H *= 2.0;
+      const double uH = H * 5.9604644775390625e-08;  // 2^-24
+      const double R = (double)kReanchorBlocks;
+      const double rounds = R * (63.0 + 3.0 * U + 3.0) + (2.0 + kMaxFree * 0.5) + kMaxFree + 4.0;
+      margin = rounds * uH;
+    }
+    P->thr_key = 0xFFFFFFFFu;
+    P->rec_count = 0;
+    P->thr_mask = ~0ull;
+    P->margin = (float)margin;
+    P->qmin_f = f32_down(qmin);
+    P->qmin_i = (int32_t)qmin;
+    P->err = err;
+    P->cand_count = 0;
+    P->surv_count = 0;
+    P->stat_candidates = 0;
+    P->stat_slow = 0;
+    P->max_drift_bits = 0;
+    (void)S;
+  }
+}
+
+// ---------------------------------------------------------------- k_tables
+// Record of block T for n free spins (spins 0..n-1; low = 0..U-1,
+// high = U..n-1), free configuration x = gray(T << U) at the block start:
+//   w[0] cB(T)  = 2 sigma_g (h_g + sum_{j<n, j!=g} J_gj s_j), the uniform
+//                 part of the energy change when the boundary step flips the
+//                 high spin g = U + ctz(T) whose old value is sigma_g (T >= 1)
+//   w[1] R(T)   = E_FF(x) - Q(x_low): energy of the free spins alone minus
+//                 the low-low part (used by the fp32 re-anchor)
+//   w[2+f]      = Wu_f(T) = 2 (h_f + sum_{g high} J_fg s_g) for low f < U-1,
+//                 and sigma_T Wu_{U-1}(T) for f = U-1 with sigma_T = +1 for
+//                 odd T, -1 for even T (old value of spin U-1 when the inner
+//                 step 2^(U-1) flips it).
+// Tables for n = U .. nmax are concatenated; the table of n starts at record
+// 2^(n-U) - 1.
+
+template <bool kInt>
+__global__ void k_tables(const void* Jv, const void* hv, int N, int nmax, uint32_t* table) {
+  const int64_t total = ((int64_t)1 << (nmax - kU + 1)) - 1;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= total) return;
+  // which n: records of n occupy [2^(n-U) - 1, 2^(n-U+1) - 1)
+  int n = kU;
+  while (((int64_t)1 << (n - kU + 1)) - 1 <= r) ++n;
+  const uint32_t T = (uint32_t)(r - (((int64_t)1 << (n - kU)) - 1));
+  const int U = kU;
+  const uint32_t x = gray32(T << U);
+  auto J = [&](int a, int b) -> double {
+    return kInt ? (double)ji((const int32_t*)Jv, N, a, b) : (double)jf((const float*)Jv, N, a, b);
+  };
+  auto H = [&](int a) -> double {
+    return kInt ? (double)((const int32_t*)hv)[a] : (double)((const float*)hv)[a];
+  };
+  auto S = [&](int j) -> double { return ((x >> j) & 1u) ? 1.0 : -1.0; };
+
+  double cB = 0.0;
+  if (T >= 1) {
+    const int c = __builtin_ctz(T);
+    const int g = U + c;
+    const double sig = ((T >> (c + 1)) & 1u) ? 1.0 : -1.0;
+    double fld = H(g);
+    for (int j = 0; j < n; ++j)
+      if (j != g) fld += J(g, j) * S(j);
+    cB = 2.0 * sig * fld;
+  }
+  double eff = 0.0;
+  for (int a = 0; a < n; ++a) {
+    double f = H(a);
+    for (int b = a + 1; b < n; ++b) f += J(a, b) * S(b);
+    eff -= S(a) * f;
+  }
+  double q = 0.0;
+  for (int a = 0; a < U; ++a)
+    for (int b = a + 1; b < U; ++b) q -= J(a, b) * S(a) * S(b);
+  const double R = eff - q;
+  double wu[kU];
+  for (int f = 0; f < U; ++f) {
+    double s = H(f);
+    for (int g = U; g < n; ++g) s += J(f, g) * S(g);
+    wu[f] = 2.0 * s;
+  }
+  wu[U - 1] *= (T & 1u) ? 1.0 : -1.0;
+
+  uint32_t* rec = table + (size_t)r * kRecWords;
+  if (kInt) {
+    rec[0] = (uint32_t)(int32_t)cB;
+    rec[1] = (uint32_t)(int32_t)R;
+    for (int f = 0; f < U; ++f) rec[2 + f] = (uint32_t)(int32_t)wu[f];
+  } else {
+    rec[0] = __float_as_uint((float)cB);
+    rec[1] = __float_as_uint((float)R);
+    for (int f = 0; f < U; ++f) rec[2 + f] = __float_as_uint((float)wu[f]);
+  }
+}
+
+// ------------------------------------------------------------------ k_enum
+// One lane per prefix p (spins n..N-1 fixed to the bits of p); the lane walks
+// all 2^n configurations of the free spins in reflected Gray-code order,
+// blocks of 2^U steps at a time.  G (the energy minus the low-low part) is
+// updated by one add per state; the block's minimum of G plus the smallest
+// low-low energy is a lower bound on every energy in the block, so a block
+// whose bound exceeds the threshold is skipped without looking at its states
+// one by one.  Otherwise the block is walked again (same arithmetic) and every
+// state at or below the threshold is appended as a candidate mask.
+
+template <typename V>
+struct Num;
+template <>
+struct Num<float> {
+  static __device__ inline float mn(float a, float b) { return fminf(a, b); }
+  static __device__ inline float big() { return __int_as_float(0x7f800000); }
+};
+template <>
+struct Num<int32_t> {
+  static __device__ inline int32_t mn(int32_t a, int32_t b) { return min(a, b); }
+  static __device__ inline int32_t big() { return 1 << 29; }
+};
+
+template <bool kInt>
+__global__ __launch_bounds__(kEnumBlock, 8) void k_enum(
+    const void* __restrict__ Jv, const void* __restrict__ hv, int N, Chunk ch,
+    const uint32_t* __restrict__ table, const uint32_t* __restrict__ qtab,
+    Params* __restrict__ P, uint64_t* __restrict__ cand, uint32_t cand_cap) {
+  using V = typename std::conditional<kInt, int32_t, float>::type;
+  using A = typename std::conditional<kInt, int64_t, double>::type;  // exact init
+  constexpr int U = kU;
+
+  // Q tables of both parities, and the lane's high-spin fields Y_g (index
+  // [g - U][thread]): read once per block boundary, so they live in LDS
+  // rather than in registers.
+  __shared__ V s_q[2 * kBlockSteps];
+  __shared__ V s_y[kMaxHigh * kEnumBlock];
+  for (int k = threadIdx.x; k < 2 * kBlockSteps; k += blockDim.x) {
+    const uint32_t b = qtab[k];
+    s_q[k] = kInt ? (V)(int32_t)b : (V)__uint_as_float(b);
+  }
+
+  const uint32_t err0 = P->err;
+  if (err0 & (kErrNonFinite | kErrOverflow)) return;
+
+  const int tid = threadIdx.x;
+  const int n = ch.n;
+  const int64_t lane = (int64_t)blockIdx.x * kEnumBlock + tid;
+  const bool valid = lane < ch.lanes;
+  const uint64_t p = ch.prefix_base + (uint64_t)(valid ? lane : 0);
+  const uint32_t* tab = table + (size_t)ch.table_offset * kRecWords;
+
+  const V* Jt = (const V*)Jv;
+  const V* ht = (const V*)hv;
+
+  // ---- per-lane init (exact in int64 / fp64) --------------------------------
+  // y_f = sum_{q >= n} J_fq s_q (field on free spin f from the prefix);
+  // E_P = energy of the prefix spins alone.  WL_f = 2 y_f for the low spins,
+  // Y_g = 2 y_g for the high ones.
+  V WL[U];
+  A ysum = 0;
+#pragma unroll
+  for (int f = 0; f < U; ++f) {
+    A acc = 0;
+    for (int q = n; q < N; ++q) {
+      const A jq = (A)Jt[f * N + q];
+      acc += ((p >> (q - n)) & 1ull) ? jq : -jq;
+    }
+    ysum += acc;
+    WL[f] = valid ? (V)(2 * acc) : (V)0;
+  }
+  for (int f = U; f < n; ++f) {
+    A acc = 0;
+    for (int q = n; q < N; ++q) {
+      const A jq = (A)Jt[f * N + q];
+      acc += ((p >> (q - n)) & 1ull) ? jq : -jq;
+    }
+    ysum += acc;
+    s_y[(f - U) * kEnumBlock + tid] = valid ? (V)(2 * acc) : (V)0;
+  }
+  A EP = 0;
+  for (int q = n; q < N; ++q) {
+    const A sq = ((p >> (q - n)) & 1ull) ? (A)1 : (A)-1;
+    A f = (A)ht[q];
+    for (int r = q + 1; r < N; ++r) {
+      const A jr = (A)Jt[q * N + r];
+      f += ((p >> (r - n)) & 1ull) ? jr : -jr;
+    }
+    EP -= sq * f;
+  }
+  V G;
+  {
+    const uint32_t r0 = tab[1];
+    const A R0 = kInt ? (A)(int32_t)r0 : (A)__uint_as_float(r0);
+    G = valid ? (V)(EP + ysum + R0) : Num<V>::big();
+  }
+  __syncthreads();  // s_q, s_y visible
+
+  // ---- thresholds ------------------------------------------------------------
+  const uint32_t thr_key = P->thr_key;
+  const uint64_t thr_mask = P->thr_mask;
+  const bool full = P->rec_count != 0 && thr_key != 0xFFFFFFFFu;
+  V thrE, fastThr;
+  if (kInt) {
+    int64_t t = full ? (int64_t)i32_of_key(thr_key) : (int64_t)(1 << 29);
+    // chunks ascend in mask order: once the record is full every state here
+    // has a larger mask than the S-th entry, so a tie with it cannot enter
+    if (full && ch.first_mask > thr_mask) t -= 1;
+    thrE = (V)t;
+    fastThr = (V)(t - (int64_t)P->qmin_i);
+  } else {
+    if (full) {
+      const double t = (double)__uint_as_float(bits_of_f32_key(thr_key)) + (double)P->margin;
+      thrE = (V)f32_up(t);
+      fastThr = (V)f32_up(t - (double)P->qmin_f);
+    } else {
+      thrE = Num<V>::big();
+      fastThr = Num<V>::big();
+    }
+  }
+
+  const uint32_t nblocks = 1u << (n - U);
+  float drift = 0.0f;
+  uint32_t slow = 0;
+  V ynext = nblocks > 1 ? s_y[tid] : (V)0;  // block 1 flips high spin U
+
+  for (uint32_t T = 0; T < nblocks; ++T) {
+    const uint32_t* rec = tab + (size_t)T * kRecWords;
+    V rw[kRecWords];
+#pragma unroll
+    for (int k = 0; k < kRecWords; ++k)
+      rw[k] = kInt ? (V)(int32_t)rec[k] : (V)__uint_as_float(rec[k]);
+    const V ycur = ynext;
+    if (T + 1 < nblocks) ynext = s_y[__builtin_ctz(T + 1) * kEnumBlock + tid];
+
+    if (T != 0) {
+      // boundary step: flip high spin g = U + c whose old value is +1 iff bit
+      // c+1 of T is set
+      const int c = __builtin_ctz(T);
+      const bool up = (T >> (c + 1)) & 1u;
+      G = up ? G + ycur : G - ycur;
+      G = G + rw[0];
+      if (!kInt && (T & (kReanchorBlocks - 1)) == 0) {
+        // fresh G = E_P - sum_f s_f y_f + R(T), with y = WL/2 and Y/2
+        const uint32_t x = gray32(T << U);
+        double a = (double)EP + (double)rw[1];
+#pragma unroll
+        for (int f = 0; f < U; ++f) {
+          float wl = (float)WL[f];
+          asm volatile("" : "+v"(wl));  // keep the conversion inside this rare path
+          const double yf = 0.5 * (double)wl;
+          a += ((x >> f) & 1u) ? -yf : yf;
+        }
+        for (int k = 0; k < n - U; ++k) {
+          const double yg = 0.5 * (double)s_y[k * kEnumBlock + tid];
+          a += ((x >> (U + k)) & 1u) ? -yg : yg;
+        }
+        const float fresh = valid ? (float)a : (float)G;
+        drift = fmaxf(drift, fabsf((float)G - fresh));
+        G = (V)fresh;
+      }
+    }
+
+    V W[U];
+#pragma unroll
+    for (int f = 0; f < U - 1; ++f) W[f] = WL[f] + rw[2 + f];
+    W[U - 1] = ((T & 1u) ? WL[U - 1] : -WL[U - 1]) + rw[2 + U - 1];
+
+    // 63 inner steps: one add per state, one 3-input min per two states
+    const V Gs = G;
+    V m = G;
+#pragma unroll
+    for (int i = 1; i < kBlockSteps; i += 2) {
+      // odd step i flips spin 0; its old value is bit 1 of i
+      G = ((i >> 1) & 1) ? G + W[0] : G - W[0];
+      const V Ga = G;
+      if (i + 1 < kBlockSteps) {
+        const int f = __builtin_ctz(i + 1);
+        if (f == U - 1) G = G + W[f];
+        else G = (((i + 1) >> (f + 1)) & 1) ? G + W[f] : G - W[f];
+        m = Num<V>::mn(Num<V>::mn(m, Ga), G);
+      } else {
+        m = Num<V>::mn(m, Ga);
+      }
+    }
+
+    if (m <= fastThr) {
+      // re-walk of this block for the lanes whose bound passed, testing every
+      // state; the opaque copy keeps the compiler from holding the 64 values
+      // of the fast walk live across the branch
+      ++slow;
+      const V* q = s_q + (T & 1u) * kBlockSteps;
+      V g2 = Gs;
+      asm volatile("" : "+v"(g2));
+      uint64_t hits = 0;
+      if (g2 + q[0] <= thrE) hits |= 1ull;
+#pragma unroll
+      for (int i = 1; i < kBlockSteps; ++i) {
+        const int f = __builtin_ctz(i);
+        if (f == U - 1) g2 = g2 + W[f];
+        else g2 = ((i >> (f + 1)) & 1) ? g2 + W[f] : g2 - W[f];
+        if (g2 + q[i] <= thrE) hits |= (1ull << i);
+      }
+      if (!valid) hits = 0;
+      while (hits) {
+        const int i = __builtin_ctzll(hits);
+        hits &= hits - 1ull;
+        const uint64_t t = ((uint64_t)T << U) | (uint64_t)i;
+        const uint64_t mask = (p << n) | (t ^ (t >> 1));
+        append_mask(mask, P, cand, cand_cap);
+      }
+    }
+  }
+
+  // statistics: one atomic per wave
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    slow += __shfl_xor(slow, o);
+    drift = fmaxf(drift, __shfl_xor(drift, o));
+  }
+  if (__lane_id() == 0) {
+    if (slow) atomicAdd(&P->stat_slow, (unsigned long long)slow);
+    if (!kInt && drift > 0.0f) atomicMax(&P->max_drift_bits, __float_as_uint(drift));
+  }
+}
+
+// Tiny instances (N < U): one thread per state, every state a candidate.
+__global__ void k_direct(int N, uint64_t lo, uint64_t hi, Params* P, uint64_t* cand,
+                         uint32_t cap) {
+  const uint64_t m = lo + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= hi) return;
+  const uint32_t slot = atomicAdd(&P->cand_count, 1u);
+  if (slot < cap) cand[slot] = m;
+  else atomicOr(&P->err, kErrCapacity);
+}
+
+// ----------------------------------------------------------------- k_score
+// Exact energy of each candidate (fp64 for float instances, rounded to fp32;
+// int32 for integer ones), kept if its key (E, mask) is below the S-th key of
+// the record.  Survivors are compacted into (skey, smask).
+
+template <bool kInt>
+__global__ void k_score(const void* Jv, const void* hv, int N, Params* P, const uint64_t* cand,
+                        uint32_t cap, uint32_t* skey, uint64_t* smask) {
+  extern __shared__ unsigned char s_raw[];
+  float* sJf = (float*)s_raw;
+  int32_t* sJi = (int32_t*)s_raw;
+  for (int k = threadIdx.x; k < N * N + N; k += blockDim.x) {
+    if (kInt) sJi[k] = k < N * N ? ((const int32_t*)Jv)[k] : ((const int32_t*)hv)[k - N * N];
+    else sJf[k] = k < N * N ? ((const float*)Jv)[k] : ((const float*)hv)[k - N * N];
+  }
+  __syncthreads();
+  const uint32_t cnt = min(P->cand_count, cap);
+  const uint32_t thr_key = P->thr_key;
+  const uint64_t thr_mask = P->thr_mask;
+  const bool full = P->rec_count != 0 && thr_key != 0xFFFFFFFFu;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  const uint32_t nround = (cnt + stride - 1) / stride;
+  for (uint32_t r = 0; r < nround; ++r) {
+    const uint32_t j = r * stride + blockIdx.x * blockDim.x + threadIdx.x;
+    bool keep = false;
+    uint64_t m = 0;
+    uint32_t key = 0;
+    if (j < cnt) {
+      m = cand[j];
+      if (kInt) key = key_of_i32(energy_i32(sJi, sJi + N * N, N, m));
+      else key = key_f32((float)energy_f64(sJf, sJf + N * N, N, m));
+      keep = !full || key_less(key, m, thr_key, thr_mask);
+    }
+    if (keep) {
+      const uint64_t act = __ballot(1);
+      const int lid = __lane_id();
+      const int leader = __ffsll((unsigned long long)act) - 1;
+      uint32_t base = 0;
+      if (lid == leader) base = atomicAdd(&P->surv_count, (uint32_t)__popcll(act));
+      base = __shfl(base, leader);
+      const uint32_t slot = base + (uint32_t)__popcll(act & ((1ull << lid) - 1ull));
+      skey[slot] = key;
+      smask[slot] = m;
+    }
+  }
+}
+
+// ----------------------------------------------------------------- k_merge
+// One workgroup of kMergeThreads.  Sorts the survivors by (key, mask) --
+// bitonic sort in LDS when they fit, in global memory otherwise -- then
+// merges them with the sorted record (rank of each element = its index plus
+// the number of smaller elements in the other list; keys are distinct because
+// masks are), keeps the first S, and publishes the S-th key as the threshold.
+
+__device__ inline void cmp_swap(uint32_t* k, uint64_t* m, uint32_t a, uint32_t b, bool asc) {
+  const uint32_t ka = k[a], kb = k[b];
+  const uint64_t ma = m[a], mb = m[b];
+  const bool gt = key_less(kb, mb, ka, ma);  // a > b
+  if (gt == asc) {
+    k[a] = kb; k[b] = ka;
+    m[a] = mb; m[b] = ma;
+  }
+}
+
+__device__ inline void bitonic_sort(uint32_t* k, uint64_t* m, uint32_t P2) {
+  for (uint32_t size = 2; size <= P2; size <<= 1) {
+    for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+      for (uint32_t t = threadIdx.x; t < P2 / 2; t += blockDim.x) {
+        const uint32_t a = 2 * t - (t & (stride - 1));
+        const uint32_t b = a + stride;
+        const bool asc = (a & size) == 0;
+        cmp_swap(k, m, a, b, asc);
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// number of entries of sorted (k, m)[0..n) strictly less than (kx, mx)
+__device__ inline uint32_t rank_in(const uint32_t* k, const uint64_t* m, uint32_t n, uint32_t kx,
+                                   uint64_t mx) {
+  uint32_t lo = 0, hi = n;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (key_less(k[mid], m[mid], kx, mx)) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(kMergeThreads) void k_merge(Params* P, int S, uint32_t cap,
+                                                         uint32_t* skey, uint64_t* smask,
+                                                         uint32_t* rkey, uint64_t* rmask,
+                                                         uint32_t* tkey, uint64_t* tmask) {
+  __shared__ uint32_t l_key[kLdsSortCap];
+  __shared__ uint64_t l_mask[kLdsSortCap];
+  const uint32_t ns = P->surv_count;
+  const uint32_t rn = P->rec_count;
+  const uint32_t cc = P->cand_count;
+  __syncthreads();
+  if (ns > 0) {
+    uint32_t P2 = 1;
+    while (P2 < ns) P2 <<= 1;
+    uint32_t* ks;
+    uint64_t* ms;
+    if (P2 <= (uint32_t)kLdsSortCap) {
+      for (uint32_t t = threadIdx.x; t < P2; t += blockDim.x) {
+        l_key[t] = t < ns ? skey[t] : 0xFFFFFFFFu;
+        l_mask[t] = t < ns ? smask[t] : ~0ull;
+      }
+      ks = l_key;
+      ms = l_mask;
+    } else {
+      for (uint32_t t = ns + threadIdx.x; t < P2; t += blockDim.x) {
+        skey[t] = 0xFFFFFFFFu;
+        smask[t] = ~0ull;
+      }
+      ks = skey;
+      ms = smask;
+    }
+    __syncthreads();
+    bitonic_sort(ks, ms, P2);
+    const uint32_t nn = min((uint32_t)S, rn + ns);
+    for (uint32_t a = threadIdx.x; a < rn; a += blockDim.x) {
+      const uint32_t r = a + rank_in(ks, ms, ns, rkey[a], rmask[a]);
+      if (r < nn) { tkey[r] = rkey[a]; tmask[r] = rmask[a]; }
+    }
+    for (uint32_t b = threadIdx.x; b < ns; b += blockDim.x) {
+      const uint32_t r = b + rank_in(rkey, rmask, rn, ks[b], ms[b]);
+      if (r < nn) { tkey[r] = ks[b]; tmask[r] = ms[b]; }
+    }
+    __syncthreads();
+    for (uint32_t a = threadIdx.x; a < nn; a += blockDim.x) {
+      rkey[a] = tkey[a];
+      rmask[a] = tmask[a];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      P->rec_count = nn;
+      if (nn == (uint32_t)S) {
+        P->thr_key = rkey[S - 1];
+        P->thr_mask = rmask[S - 1];
+      }
+    }
+  }
+  if (threadIdx.x == 0) {
+    if (cc > cap) P->err |= kErrCapacity;
+    P->stat_candidates += cc;
+    P->cand_count = 0;
+    P->surv_count = 0;
+  }
+}
+
+// -------------------------------------------------------------- k_finalize
+
+template <bool kInt>
+__global__ void k_finalize(const Params* P, int S, const uint32_t* rkey, const uint64_t* rmask,
+                           uint64_t* states_out, void* energies_out, uint32_t* sticky) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k == 0) atomicOr(sticky, P->err);
+  if (k >= S) return;
+  const bool have = (uint32_t)k < P->rec_count;
+  states_out[k] = have ? rmask[k] : ~0ull;
+  if (kInt) ((int32_t*)energies_out)[k] = have ? i32_of_key(rkey[k]) : 0;
+  else ((float*)energies_out)[k] = have ? __uint_as_float(bits_of_f32_key(rkey[k])) : 0.0f;
+}
+
+// ---------------------------------------------------------------- launchers
+
+hipError_t launch_prep(bool isint, const void* J, const void* h, int N, int S, Params* P,
+                       uint32_t* qtab, hipStream_t st) {
+  if (isint) hipLaunchKernelGGL(k_prep<true>, dim3(1), dim3(256), 0, st, J, h, N, S, P, qtab);
+  else hipLaunchKernelGGL(k_prep<false>, dim3(1), dim3(256), 0, st, J, h, N, S, P, qtab);
+  return hipGetLastError();
+}
+
+hipError_t launch_tables(bool isint, const void* J, const void* h, int N, int nmax,
+                         uint32_t* table, hipStream_t st) {
+  const int64_t total = ((int64_t)1 << (nmax - kU + 1)) - 1;
+  const dim3 grid((unsigned)((total + 255) / 256));
+  if (isint) hipLaunchKernelGGL(k_tables<true>, grid, dim3(256), 0, st, J, h, N, nmax, table);
+  else hipLaunchKernelGGL(k_tables<false>, grid, dim3(256), 0, st, J, h, N, nmax, table);
+  return hipGetLastError();
+}
+
+hipError_t launch_enum(bool isint, const void* J, const void* h, int N, const Chunk& ch,
+                       const uint32_t* table, const uint32_t* qtab, Params* P, uint64_t* cand,
+                       uint32_t cap, hipStream_t st) {
+  const dim3 grid((unsigned)((ch.lanes + kEnumBlock - 1) / kEnumBlock));
+  if (isint)
+    hipLaunchKernelGGL(k_enum<true>, grid, dim3(kEnumBlock), 0, st, J, h, N, ch, table, qtab, P,
+                       cand, cap);
+  else
+    hipLaunchKernelGGL(k_enum<false>, grid, dim3(kEnumBlock), 0, st, J, h, N, ch, table, qtab,
+                       P, cand, cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_direct(int N, uint64_t lo, uint64_t hi, Params* P, uint64_t* cand, uint32_t cap,
+                         hipStream_t st) {
+  const uint64_t cnt = hi - lo;
+  hipLaunchKernelGGL(k_direct, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, N, lo, hi,
+                     P, cand, cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_score(bool isint, const void* J, const void* h, int N, Params* P,
+                        const uint64_t* cand, uint32_t cap, uint32_t* skey, uint64_t* smask,
+                        int grid, hipStream_t st) {
+  const size_t shm = (size_t)(N * N + N) * 4;
+  if (isint)
+    hipLaunchKernelGGL(k_score<true>, dim3(grid), dim3(256), shm, st, J, h, N, P, cand, cap, skey,
+                       smask);
+  else
+    hipLaunchKernelGGL(k_score<false>, dim3(grid), dim3(256), shm, st, J, h, N, P, cand, cap,
+                       skey, smask);
+  return hipGetLastError();
+}
+
+hipError_t launch_merge(Params* P, int S, uint32_t cap, uint32_t* skey, uint64_t* smask,
+                        uint32_t* rkey, uint64_t* rmask, uint32_t* tkey, uint64_t* tmask,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_merge, dim3(1), dim3(kMergeThreads), 0, st, P, S, cap, skey, smask, rkey,
+                     rmask, tkey, tmask);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(bool isint, const Params* P, int S, const uint32_t* rkey,
+                           const uint64_t* rmask, uint64_t* states_out, void* energies_out,
+                           uint32_t* sticky, hipStream_t st) {
+  const dim3 grid((unsigned)((S + 255) / 256));
+  if (isint)
+    hipLaunchKernelGGL(k_finalize<true>, grid, dim3(256), 0, st, P, S, rkey, rmask, states_out,
+                       energies_out, sticky);
+  else
+    hipLaunchKernelGGL(k_finalize<false>, grid, dim3(256), 0, st, P, S, rkey, rmask, states_out,
+                       energies_out, sticky);
+  return hipGetLastError();
+}
+
+int enum_occupancy(bool isint) {
+  int blocks = 0;
+  hipError_t e;
+  if (isint)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_enum<true>, kEnumBlock, 0);
+  else
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_enum<false>, kEnumBlock, 0);
+  return e == hipSuccess ? blocks : 0;
+}
+
+}  // namespace sg
