@@ -57,6 +57,8 @@ typedef enum {
 #define SG_MAX_N 56
 /* Largest S accepted by the single-instance search. */
 #define SG_MAX_S (1 << 20)
+/* Largest S accepted by the batched search. */
+#define SG_MAX_S_BATCHED 4096
 
 /*
  * sg_low_spectrum_f32 -- the S lowest states of a float32 instance
@@ -105,6 +107,89 @@ sg_status sg_low_spectrum_range_i32(int N, const int32_t *J, const int32_t *h, i
                                     uint64_t *states_out, int32_t *energies_out,
                                     void *stream);
 
+/*
+ * Batched search: the S lowest states of each of B independent instances of
+ * uneven size, in one sequence of launches on `stream` (about 2 log2(2^N_max)
+ * kernels for the whole batch, whatever B is).  Every instance runs the same
+ * search as sg_low_spectrum_f32 / _i32 and gets the same result.
+ *
+ *   B            number of instances, >= 1
+ *   N_dev        device int32[B]: spins of instance b, 6 <= N_b <= N_max
+ *   N_max        largest N_b (row stride of J), 6 <= N_max <= 40
+ *   J            device float[B][N_max][N_max] (int32 for _i32); instance b
+ *                uses its leading N_b x N_b block, strict upper triangle
+ *   h            device float[B][N_max]; instance b uses its first N_b
+ *   S            states per instance, 1 <= S <= SG_MAX_S_BATCHED, S <= 2^N_b
+ *   states_out   device uint64[B][S], energies_out device float[B][S]
+ *
+ * The instance sizes are read on the device only, so the enqueued work
+ * depends on (B, N_max, S) alone: one capture into a HIP graph serves every
+ * batch of that shape.  Bad N_b or S > 2^N_b are reported as SG_EINVAL by
+ * sg_get_error.  The workspace must already be large enough before a graph
+ * capture (run one call of the same shape first).
+ */
+sg_status sg_low_spectrum_batched_f32(int B, const int32_t *N_dev, int N_max, const float *J,
+                                      const float *h, int S, uint64_t *states_out,
+                                      float *energies_out, void *stream);
+sg_status sg_low_spectrum_batched_i32(int B, const int32_t *N_dev, int N_max, const int32_t *J,
+                                      const int32_t *h, int S, uint64_t *states_out,
+                                      int32_t *energies_out, void *stream);
+
+/*
+ * Exact log partition function of B instances of N spins (fp32 couplings):
+ *   Z_b(beta) = sum over all 2^N states s of exp(-beta E_b(s)),
+ * the normaliser of the Boltzmann distribution at inverse temperature beta
+ * (Sec. 5.2, Eq. 8) for the energy of Eq. (1).  The S lowest states are found
+ * first (the batched search); log Z is then computed as
+ *   log Z = -beta E0 + log sum_s exp(-beta (E(s) - E0)),
+ * with E0 the lowest energy, so that no weight exceeds 1.
+ *
+ *   B            number of instances, >= 1
+ *   N            spins of every instance, 6 <= N <= 40
+ *   J            device float[B][N][N], strict upper triangle read
+ *   h            device float[B][N]
+ *   n_beta       number of inverse temperatures, 1 <= n_beta <= 4
+ *   beta         device float[n_beta], each finite and > 0 (else SG_EINVAL
+ *                via sg_get_error)
+ *   S            lowest states returned per instance, 1 <= S <=
+ *                SG_MAX_S_BATCHED, S <= 2^N
+ *   logz_out     device double[B][n_beta]
+ *   e0_out       device float[B]: the lowest energy E0 (= energies_out[b][0])
+ *   states_out   device uint64[B][S], energies_out device float[B][S]: the
+ *                result of sg_low_spectrum_batched_f32 on the same batch
+ *
+ * The walk keeps its energy chain in fp64 and evaluates each weight in fp32
+ * (shifted energy rounded to fp32, hardware exp2); block sums of 64 weights are
+ * fp32, every longer sum is fp64.  Relative error of log Z: about 1e-7.  All
+ * buffers are caller-owned; work is enqueued on `stream`.
+ */
+sg_status sg_logz_forward_f32(int B, int N, const float *J, const float *h, int n_beta,
+                              const float *beta, int S, double *logz_out, float *e0_out,
+                              uint64_t *states_out, float *energies_out, void *stream);
+
+/*
+ * Gradient of L = sum_{b,k} g[b][k] log Z_b(beta_k) with respect to J and h:
+ *   dL/dJ_ij = sum_k g[b][k] beta_k <s_i s_j>_k   (i < j)
+ *   dL/dh_i  = sum_k g[b][k] beta_k <s_i>_k
+ * with <.>_k the average under the Boltzmann distribution at beta_k (Sec. 5.2,
+ * Eq. 8).  The enumeration is walked again (no per-state storage) with the
+ * combined weight sum_k (g[b][k] beta_k / Z_k) exp(-beta_k E(s)).
+ *
+ *   B, N, J, h, n_beta, beta  as for sg_logz_forward_f32
+ *   e0           device float[B]: e0_out of the forward call
+ *   logz         device double[B][n_beta]: logz_out of the forward call
+ *   grad_logz    device double[B][n_beta]: g, the incoming gradient
+ *   grad_J       device float[B][N][N]: written for i < j, zeros elsewhere
+ *   grad_h       device float[B][N]
+ *
+ * Moments are summed in fp32 inside a 64-state block and in fp64 beyond it.
+ * All buffers are caller-owned; work is enqueued on `stream`.
+ */
+sg_status sg_logz_backward_f32(int B, int N, const float *J, const float *h, int n_beta,
+                               const float *beta, const float *e0, const double *logz,
+                               const double *grad_logz, float *grad_J, float *grad_h,
+                               void *stream);
+
 /* Waits for `stream`, then returns and clears the sticky device error of the
  * calls enqueued on it (SG_OK if none). */
 sg_status sg_get_error(void *stream);
@@ -121,8 +206,30 @@ typedef struct {
     double  max_drift;       /* largest |incremental - fresh| at re-anchors   */
     int32_t prefix_bits_max; /* largest k = N - n used                        */
     int32_t free_bits_max;   /* largest n used                                */
+    int64_t enum_launches;   /* enumeration kernel launches                   */
+    double  enum_states;     /* states covered by those launches              */
+    double  enum_ms;         /* their summed duration (HIP events; 0 unless
+                                kernel timing is on)                          */
+    int64_t max_chunk_candidates; /* most candidates one chunk produced       */
 } sg_run_info;
 sg_status sg_get_run_info(void *stream, sg_run_info *out);
+
+/* Kernel timing switch (process-wide, default off): when on, each
+ * enumeration launch is bracketed by HIP events on its stream and
+ * sg_get_run_info reports their summed duration. */
+void sg_set_kernel_timing(int enable);
+
+/*
+ * Measurement hook: issue rate of one VALU instruction kind on the current
+ * device, in lane-instructions per second (0 v_add_f32, 1 v_min3_f32,
+ * 2 v_add_u32, 3 v_min3_i32, 4 v_fma_f32, 5 v_min_f32, 6 v_or_b32,
+ * 7 v_or3_b32, 8 v_add3_u32, 9 v_max3_f32, 10 v_min_i32, 11 v_sub_f32,
+ * 12 v_and_or_b32, 13 v_med3_f32), with `waves_per_simd` resident
+ * waves on every SIMD.  Synchronous (own stream); returns < 0 on error.  The
+ * benchmark uses it as the measured denominator of the enumeration kernel's
+ * roofline.
+ */
+double sg_probe_valu(int op, int waves_per_simd);
 
 /*
  * Test hook (not a compute call): the chunk plan the library would use for a

@@ -151,6 +151,16 @@ static int T##_cmp(const void *a, const void *b) {                             \
 DEFINE_HEAP(kd_t, kd_less)
 DEFINE_HEAP(ki_t, ki_less)
 
+/* Number of threads the parallel loops use when asked for 0 (all). */
+int oracle_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 static int oracle_threads(int req)
 {
 #ifdef _OPENMP

@@ -38,6 +38,8 @@ _lib = None
 
 def _load(path: str):
     L = ctypes.CDLL(path)
+    L.oracle_max_threads.restype = ctypes.c_int
+    L.oracle_max_threads.argtypes = []
     L.oracle_energy_f64.restype = ctypes.c_double
     L.oracle_energy_f64.argtypes = [ctypes.c_int, _c_dp, _c_dp, ctypes.c_uint64]
     L.oracle_energy_i64.restype = ctypes.c_int64
@@ -83,6 +85,11 @@ def swapped_library(path: str):
         yield
     finally:
         _lib = old
+
+
+def max_threads() -> int:
+    """Threads the oracle's parallel loops use by default."""
+    return int(lib().oracle_max_threads())
 
 
 def _f64(a):

@@ -22,13 +22,20 @@ STATUS_NAMES = {
 }
 SG_MAX_N = 56
 SG_MAX_S = 1 << 20
+SG_MAX_S_BATCHED = 4096
 
 # every symbol include/sg.h declares
 EXPORTS = [
     "sg_low_spectrum_f32", "sg_low_spectrum_i32",
     "sg_low_spectrum_range_f32", "sg_low_spectrum_range_i32",
+    "sg_low_spectrum_batched_f32", "sg_low_spectrum_batched_i32",
+    "sg_logz_forward_f32", "sg_logz_backward_f32",
     "sg_get_error", "sg_last_error", "sg_get_run_info", "sg_debug_plan",
+    "sg_set_kernel_timing", "sg_probe_valu",
 ]
+PROBE_OPS = {"v_add_f32": 0, "v_min3_f32": 1, "v_add_u32": 2, "v_min3_i32": 3, "v_fma_f32": 4,
+             "v_min_f32": 5, "v_or_b32": 6, "v_or3_b32": 7, "v_add3_u32": 8, "v_max3_f32": 9,
+             "v_min_i32": 10, "v_sub_f32": 11, "v_and_or_b32": 12, "v_med3_f32": 13}
 
 
 class SgError(RuntimeError):
@@ -46,6 +53,10 @@ class RunInfo(ctypes.Structure):
         ("max_drift", ctypes.c_double),
         ("prefix_bits_max", ctypes.c_int32),
         ("free_bits_max", ctypes.c_int32),
+        ("enum_launches", ctypes.c_int64),
+        ("enum_states", ctypes.c_double),
+        ("enum_ms", ctypes.c_double),
+        ("max_chunk_candidates", ctypes.c_int64),
     ]
 
     def as_dict(self):
@@ -73,12 +84,24 @@ def lib() -> ctypes.CDLL:
             f = getattr(L, name)
             f.restype = i32
             f.argtypes = [i32, vp, vp, i32, u64, u64, vp, vp, vp]
+        for name in ("sg_low_spectrum_batched_f32", "sg_low_spectrum_batched_i32"):
+            f = getattr(L, name)
+            f.restype = i32
+            f.argtypes = [i32, vp, i32, vp, vp, i32, vp, vp, vp]
+        L.sg_logz_forward_f32.restype = i32
+        L.sg_logz_forward_f32.argtypes = [i32, i32, vp, vp, i32, vp, i32, vp, vp, vp, vp, vp]
+        L.sg_logz_backward_f32.restype = i32
+        L.sg_logz_backward_f32.argtypes = [i32, i32, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]
         L.sg_get_error.restype = i32
         L.sg_get_error.argtypes = [vp]
         L.sg_last_error.restype = ctypes.c_char_p
         L.sg_last_error.argtypes = []
         L.sg_get_run_info.restype = i32
         L.sg_get_run_info.argtypes = [vp, ctypes.POINTER(RunInfo)]
+        L.sg_probe_valu.restype = ctypes.c_double
+        L.sg_probe_valu.argtypes = [i32, i32]
+        L.sg_set_kernel_timing.restype = None
+        L.sg_set_kernel_timing.argtypes = [i32]
         L.sg_debug_plan.restype = i32
         L.sg_debug_plan.argtypes = [i32, i32, u64, u64, ctypes.c_int64,
                                     ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_int32),
@@ -127,6 +150,34 @@ def sg_low_spectrum_range_i32(N, J, h, S, lo, hi, states_out, energies_out, stre
                                            _ptr(energies_out), _stream(stream))
 
 
+def sg_low_spectrum_batched_f32(B, N_dev, N_max, J, h, S, states_out, energies_out,
+                                stream=None) -> int:
+    return lib().sg_low_spectrum_batched_f32(B, _ptr(N_dev), N_max, _ptr(J), _ptr(h), S,
+                                             _ptr(states_out), _ptr(energies_out),
+                                             _stream(stream))
+
+
+def sg_low_spectrum_batched_i32(B, N_dev, N_max, J, h, S, states_out, energies_out,
+                                stream=None) -> int:
+    return lib().sg_low_spectrum_batched_i32(B, _ptr(N_dev), N_max, _ptr(J), _ptr(h), S,
+                                             _ptr(states_out), _ptr(energies_out),
+                                             _stream(stream))
+
+
+def sg_logz_forward_f32(B, N, J, h, n_beta, beta, S, logz_out, e0_out, states_out,
+                        energies_out, stream=None) -> int:
+    return lib().sg_logz_forward_f32(B, N, _ptr(J), _ptr(h), n_beta, _ptr(beta), S,
+                                     _ptr(logz_out), _ptr(e0_out), _ptr(states_out),
+                                     _ptr(energies_out), _stream(stream))
+
+
+def sg_logz_backward_f32(B, N, J, h, n_beta, beta, e0, logz, grad_logz, grad_J, grad_h,
+                         stream=None) -> int:
+    return lib().sg_logz_backward_f32(B, N, _ptr(J), _ptr(h), n_beta, _ptr(beta), _ptr(e0),
+                                      _ptr(logz), _ptr(grad_logz), _ptr(grad_J), _ptr(grad_h),
+                                      _stream(stream))
+
+
 def sg_get_error(stream=None) -> int:
     return lib().sg_get_error(_stream(stream))
 
@@ -135,6 +186,16 @@ def sg_get_run_info(stream=None) -> dict:
     info = RunInfo()
     check(lib().sg_get_run_info(_stream(stream), ctypes.byref(info)), "sg_get_run_info")
     return info.as_dict()
+
+
+def sg_set_kernel_timing(enable: bool) -> None:
+    lib().sg_set_kernel_timing(1 if enable else 0)
+
+
+def sg_probe_valu(op, waves_per_simd: int = 8) -> float:
+    """Measured lane-instructions/s of one VALU instruction kind (name or code)."""
+    code = PROBE_OPS[op] if isinstance(op, str) else int(op)
+    return float(lib().sg_probe_valu(code, waves_per_simd))
 
 
 def sg_debug_plan(N, S, lo, hi, lanes_fill, cap=100000):

@@ -55,5 +55,120 @@ def low_spectrum(J, h, S: int, stream=None, check: bool = True):
     return states, energies
 
 
+def low_spectrum_batched(Ns, J, h, S: int, stream=None, check: bool = True):
+    """S lowest states of each of B instances: Ns int32[B] (GPU), J [B, Nmax, Nmax],
+    h [B, Nmax] (float32 or int32, GPU).  Returns masks int64[B, S], energies [B, S]."""
+    import torch
+    if J.dim() != 3 or J.shape[1] != J.shape[2] or h.shape != J.shape[:2]:
+        raise ValueError("J must be B x Nmax x Nmax and h B x Nmax")
+    if Ns.dtype != torch.int32 or Ns.shape[0] != J.shape[0]:
+        raise ValueError("Ns must be int32 of length B")
+    if not (J.is_cuda and h.is_cuda and Ns.is_cuda):
+        raise ValueError("Ns, J and h must be GPU tensors")
+    if J.dtype != h.dtype or J.dtype not in (torch.float32, torch.int32):
+        raise ValueError("J and h must both be float32 or both int32")
+    J, h, Ns = J.contiguous(), h.contiguous(), Ns.contiguous()
+    B, Nmax = J.shape[0], J.shape[1]
+    states = torch.empty((B, S), dtype=torch.int64, device=J.device)
+    energies = torch.empty((B, S), dtype=J.dtype, device=J.device)
+    if J.dtype == torch.float32:
+        st = _lib.sg_low_spectrum_batched_f32(B, Ns, Nmax, J, h, S, states, energies, stream)
+    else:
+        st = _lib.sg_low_spectrum_batched_i32(B, Ns, Nmax, J, h, S, states, energies, stream)
+    _lib.check(st, "sg_low_spectrum_batched")
+    if check:
+        _lib.check(_lib.sg_get_error(stream), "device")
+    return states, energies
+
+
+def _prep_logz(J, h, beta):
+    import torch
+    if J.dim() != 3 or J.shape[1] != J.shape[2] or h.shape != J.shape[:2]:
+        raise ValueError("J must be B x N x N and h B x N")
+    if not (J.is_cuda and h.is_cuda and beta.is_cuda):
+        raise ValueError("J, h and beta must be GPU tensors")
+    if J.dtype != torch.float32 or h.dtype != torch.float32 or beta.dtype != torch.float32:
+        raise ValueError("J, h and beta must be float32")
+    if beta.dim() != 1:
+        raise ValueError("beta must be 1-D")
+    return J.contiguous(), h.contiguous(), beta.contiguous()
+
+
+def logz_forward(J, h, beta, S: int, stream=None, check: bool = True):
+    """log Z_b(beta_k) of B instances (J [B, N, N], h [B, N], beta [K], float32,
+    GPU).  Returns logz float64[B, K], e0 float32[B], states int64[B, S] and
+    energies float32[B, S] (the S lowest states)."""
+    import torch
+    J, h, beta = _prep_logz(J, h, beta)
+    B, N, K = J.shape[0], J.shape[1], beta.shape[0]
+    dev = J.device
+    logz = torch.empty((B, K), dtype=torch.float64, device=dev)
+    e0 = torch.empty(B, dtype=torch.float32, device=dev)
+    states = torch.empty((B, S), dtype=torch.int64, device=dev)
+    energies = torch.empty((B, S), dtype=torch.float32, device=dev)
+    st = _lib.sg_logz_forward_f32(B, N, J, h, K, beta, S, logz, e0, states, energies, stream)
+    _lib.check(st, "sg_logz_forward_f32")
+    if check:
+        _lib.check(_lib.sg_get_error(stream), "device")
+    return logz, e0, states, energies
+
+
+def logz_backward(J, h, beta, e0, logz, grad_logz, stream=None, check: bool = True):
+    """Gradients (grad_J [B, N, N], upper triangle; grad_h [B, N]) of
+    sum grad_logz * logz with respect to J and h."""
+    import torch
+    J, h, beta = _prep_logz(J, h, beta)
+    B, N, K = J.shape[0], J.shape[1], beta.shape[0]
+    if logz.shape != (B, K) or grad_logz.shape != (B, K) or e0.shape != (B,):
+        raise ValueError("e0 must be [B], logz and grad_logz [B, K]")
+    logz = logz.to(torch.float64).contiguous()
+    grad_logz = grad_logz.to(torch.float64).contiguous()
+    e0 = e0.to(torch.float32).contiguous()
+    gJ = torch.empty((B, N, N), dtype=torch.float32, device=J.device)
+    gh = torch.empty((B, N), dtype=torch.float32, device=J.device)
+    st = _lib.sg_logz_backward_f32(B, N, J, h, K, beta, e0, logz, grad_logz, gJ, gh, stream)
+    _lib.check(st, "sg_logz_backward_f32")
+    if check:
+        _lib.check(_lib.sg_get_error(stream), "device")
+    return gJ, gh
+
+
+def _logz_function():
+    import torch
+
+    class LogZ(torch.autograd.Function):
+        """log Z(beta) of a batch with exact gradients w.r.t. J and h; the
+        backward walks the enumeration again instead of storing weights."""
+
+        @staticmethod
+        def forward(ctx, J, h, beta, S):
+            logz, e0, states, energies = logz_forward(J, h, beta, S)
+            ctx.save_for_backward(J, h, beta, e0, logz)
+            ctx.mark_non_differentiable(states, energies)
+            return logz, states, energies
+
+        @staticmethod
+        def backward(ctx, g_logz, g_states, g_energies):
+            J, h, beta, e0, logz = ctx.saved_tensors
+            gJ = gh = None
+            if g_logz is not None and (ctx.needs_input_grad[0] or ctx.needs_input_grad[1]):
+                gJ, gh = logz_backward(J, h, beta, e0, logz, g_logz)
+            return gJ, gh, None, None
+
+    return LogZ
+
+
+_LOGZ = None
+
+
+def logz(J, h, beta, S: int = 32):
+    """Differentiable log Z: returns (logz float64[B, K], states int64[B, S],
+    energies float32[B, S]); gradients flow to J (upper triangle) and h."""
+    global _LOGZ
+    if _LOGZ is None:
+        _LOGZ = _logz_function()
+    return _LOGZ.apply(J, h, beta, S)
+
+
 def run_info(stream=None) -> dict:
     return _lib.sg_get_run_info(stream)

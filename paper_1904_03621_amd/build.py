@@ -9,7 +9,9 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsgpu.so")
-SOURCES = [os.path.join(CSRC, "sg_kernels.hip"), os.path.join(CSRC, "sg_api.cpp")]
+SOURCES = [os.path.join(CSRC, "sg_kernels.hip"), os.path.join(CSRC, "sg_logz.hip"),
+           os.path.join(CSRC, "sg_probe.hip"),
+           os.path.join(CSRC, "sg_api.cpp")]
 HEADERS = [os.path.join(CSRC, "sg_internal.h"),
            os.path.join(os.path.dirname(HERE), "include", "sg.h")]
 

@@ -15,25 +15,26 @@
 #include "sg_internal.h"
 
 namespace sg {
-hipError_t launch_prep(bool isint, const void* J, const void* h, int N, int S, Params* P,
-                       uint32_t* qtab, hipStream_t st);
-hipError_t launch_tables(bool isint, const void* J, const void* h, int N, int nmax,
-                         uint32_t* table, hipStream_t st);
-hipError_t launch_enum(bool isint, const void* J, const void* h, int N, const Chunk& ch,
-                       const uint32_t* table, const uint32_t* qtab, Params* P, uint64_t* cand,
-                       uint32_t cap, hipStream_t st);
-hipError_t launch_direct(int N, uint64_t lo, uint64_t hi, Params* P, uint64_t* cand, uint32_t cap,
-                         hipStream_t st);
-hipError_t launch_score(bool isint, const void* J, const void* h, int N, Params* P,
-                        const uint64_t* cand, uint32_t cap, uint32_t* skey, uint64_t* smask,
-                        int grid, hipStream_t st);
-hipError_t launch_merge(Params* P, int S, uint32_t cap, uint32_t* skey, uint64_t* smask,
-                        uint32_t* rkey, uint64_t* rmask, uint32_t* tkey, uint64_t* tmask,
-                        hipStream_t st);
-hipError_t launch_finalize(bool isint, const Params* P, int S, const uint32_t* rkey,
-                           const uint64_t* rmask, uint64_t* states_out, void* energies_out,
-                           uint32_t* sticky, hipStream_t st);
+hipError_t launch_prep(bool isint, const Batch& bt, hipStream_t st);
+hipError_t launch_tables(bool isint, const Batch& bt, int ncap, hipStream_t st);
+hipError_t launch_enum(bool isint, const Batch& bt, const Chunk& ch, int ninst, hipStream_t st);
+hipError_t launch_direct(const Batch& bt, uint64_t lo, uint64_t hi, hipStream_t st);
+hipError_t launch_score(bool isint, const Batch& bt, int b, int grid, int N, hipStream_t st);
+hipError_t launch_merge(const Batch& bt, int b, hipStream_t st);
+hipError_t launch_merge_batched(bool isint, const Batch& bt, uint64_t first_mask,
+                                hipStream_t st);
+hipError_t launch_finalize(bool isint, const Batch& bt, uint64_t* states_out, void* energies_out,
+                           hipStream_t st);
 int enum_occupancy(bool isint);
+double probe_valu(int op, int waves_per_simd);
+hipError_t launch_tables64(const Batch& bt, int ncap, double* out, hipStream_t st);
+hipError_t launch_lz_prep(int mode, const LzArgs& a, const float* J, double* q64,
+                          const float* energies, float* e0_out, const double* logz,
+                          const double* grad, hipStream_t st);
+hipError_t launch_logz(int mode, const LzArgs& a, const float* J, const float* h,
+                       const double* table64, const double* q64, hipStream_t st);
+hipError_t launch_lz_final(int mode, const LzArgs& a, double* logz, float* grad_J, float* grad_h,
+                           hipStream_t st);
 }  // namespace sg
 
 using namespace sg;
@@ -113,32 +114,81 @@ std::vector<PlanChunk> plan_chunks(int N, int S, uint64_t lo, uint64_t hi, int64
 
 // --------------------------------------------------------------- workspace
 
+// Device buffers of one (device, stream).  Each buffer only grows; growing
+// frees the old allocation (hipFree waits for the device), so it never races
+// work that earlier calls enqueued.
 struct Workspace {
   int device = -1;
-  Params* P = nullptr;
   uint32_t* sticky = nullptr;
+  Params* P = nullptr;
+  size_t nP = 0;
   uint32_t* qtab = nullptr;
+  size_t nq = 0;
   uint32_t* table = nullptr;
+  size_t ntable = 0;
   uint64_t* cand = nullptr;
   uint32_t* skey = nullptr;
   uint64_t* smask = nullptr;
-  uint32_t cap = 0;
+  size_t ncand = 0;
   uint32_t* rkey = nullptr;
   uint64_t* rmask = nullptr;
   uint32_t* tkey = nullptr;
   uint64_t* tmask = nullptr;
-  int rec_cap = 0;
+  size_t nrec = 0;
+  // log Z walk
+  double* table64 = nullptr;
+  size_t ntable64 = 0;
+  double* q64 = nullptr;
+  size_t nq64 = 0;
+  double* lz_acc = nullptr;
+  size_t nlz_acc = 0;
+  double* lz_coef = nullptr;
+  size_t nlz_coef = 0;
   int64_t fill[2] = {0, 0};
   int cus = 0;
   // last run
   int64_t last_chunks = 0;
   int last_kmax = 0, last_nmax = 0;
+  double last_states = 0.0;
+  // kernel timing: one event pair per enumeration launch of the last call
+  std::vector<hipEvent_t> ev;
+  int ev_used = 0;
 };
+
+bool g_timing = false;
+
+hipError_t ws_event_pair(Workspace* w, hipEvent_t* a, hipEvent_t* b) {
+  while ((int)w->ev.size() < 2 * (w->ev_used + 1)) {
+    hipEvent_t e;
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) return r;
+    w->ev.push_back(e);
+  }
+  *a = w->ev[2 * w->ev_used];
+  *b = w->ev[2 * w->ev_used + 1];
+  ++w->ev_used;
+  return hipSuccess;
+}
 
 std::mutex g_mu;
 std::map<std::pair<int, hipStream_t>, Workspace*> g_ws;
 
-constexpr uint32_t kCandCapMin = 1u << 22;
+constexpr uint32_t kCandCapMin = 1u << 22;     // single search
+constexpr uint32_t kBatchCandCapMin = 1u << 13;  // per instance of a batch
+
+template <typename T>
+hipError_t grow(T** p, size_t* have, size_t need) {
+  if (*have >= need) return hipSuccess;
+  if (*p) {
+    hipError_t e = hipFree(*p);
+    if (e != hipSuccess) return e;
+    *p = nullptr;
+    *have = 0;
+  }
+  hipError_t e = hipMalloc(p, need * sizeof(T));
+  if (e == hipSuccess) *have = need;
+  return e;
+}
 
 sg_status ws_create(int dev, Workspace* w) {
   w->device = dev;
@@ -152,19 +202,15 @@ sg_status ws_create(int dev, Workspace* w) {
     const int occ = enum_occupancy(k == 1);
     w->fill[k] = (int64_t)w->cus * std::max(occ, 1) * kEnumBlock;
   }
-  HIP_TRY(hipMalloc(&w->P, sizeof(Params)));
   HIP_TRY(hipMalloc(&w->sticky, sizeof(uint32_t)));
   HIP_TRY(hipMemset(w->sticky, 0, sizeof(uint32_t)));
-  HIP_TRY(hipMalloc(&w->qtab, 2 * kBlockSteps * sizeof(uint32_t)));
-  const size_t recs = ((size_t)1 << (kMaxFree - kU + 1)) - 1;
-  HIP_TRY(hipMalloc(&w->table, recs * kRecWords * sizeof(uint32_t)));
   return SG_OK;
 }
 
 // The workspace of (current device, stream), created on first use and grown
-// to hold S record entries and the candidate buffer.  Growing frees the old
-// buffers (hipFree waits for the device), so it never races earlier calls.
-sg_status ws_get(hipStream_t st, int S, Workspace** out) {
+// to hold B instances with `recs` table records, `cap` candidate slots and S
+// record entries each.
+sg_status ws_get(hipStream_t st, int B, size_t recs, size_t cap, int S, Workspace** out) {
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
   std::lock_guard<std::mutex> lk(g_mu);
@@ -177,45 +223,60 @@ sg_status ws_get(hipStream_t st, int S, Workspace** out) {
     w = new Workspace();
     const sg_status s = ws_create(dev, w);
     if (s != SG_OK) {
-      if (w->P) (void)hipFree(w->P);
       if (w->sticky) (void)hipFree(w->sticky);
-      if (w->qtab) (void)hipFree(w->qtab);
-      if (w->table) (void)hipFree(w->table);
       delete w;
       return s;
     }
     g_ws[key] = w;
   }
-  // candidate capacity: the first chunk (all candidates) has < 2 max(S, 4096)
-  uint32_t need = kCandCapMin;
-  while (need < 8u * (uint32_t)S) need <<= 1;
-  if (w->cap < need) {
-    if (w->cand) {
-      HIP_TRY(hipFree(w->cand));
-      HIP_TRY(hipFree(w->skey));
-      HIP_TRY(hipFree(w->smask));
-    }
-    HIP_TRY(hipMalloc(&w->cand, (size_t)need * sizeof(uint64_t)));
-    HIP_TRY(hipMalloc(&w->skey, (size_t)need * sizeof(uint32_t)));
-    HIP_TRY(hipMalloc(&w->smask, (size_t)need * sizeof(uint64_t)));
-    w->cap = need;
+  const size_t Bz = (size_t)B;
+  HIP_TRY(grow(&w->P, &w->nP, Bz));
+  HIP_TRY(grow(&w->qtab, &w->nq, Bz * 2 * kBlockSteps));
+  HIP_TRY(grow(&w->table, &w->ntable, Bz * recs * kRecWords));
+  if (w->ncand < Bz * cap) {
+    size_t have_s = w->ncand, have_m = w->ncand;
+    HIP_TRY(grow(&w->cand, &w->ncand, Bz * cap));
+    HIP_TRY(grow(&w->skey, &have_s, Bz * cap));
+    HIP_TRY(grow(&w->smask, &have_m, Bz * cap));
   }
-  if (w->rec_cap < S) {
-    if (w->rkey) {
-      HIP_TRY(hipFree(w->rkey));
-      HIP_TRY(hipFree(w->rmask));
-      HIP_TRY(hipFree(w->tkey));
-      HIP_TRY(hipFree(w->tmask));
-    }
-    HIP_TRY(hipMalloc(&w->rkey, (size_t)S * sizeof(uint32_t)));
-    HIP_TRY(hipMalloc(&w->rmask, (size_t)S * sizeof(uint64_t)));
-    HIP_TRY(hipMalloc(&w->tkey, (size_t)S * sizeof(uint32_t)));
-    HIP_TRY(hipMalloc(&w->tmask, (size_t)S * sizeof(uint64_t)));
-    w->rec_cap = S;
+  if (w->nrec < Bz * (size_t)S) {
+    size_t h1 = w->nrec, h2 = w->nrec, h3 = w->nrec;
+    HIP_TRY(grow(&w->rkey, &w->nrec, Bz * S));
+    HIP_TRY(grow(&w->rmask, &h1, Bz * S));
+    HIP_TRY(grow(&w->tkey, &h2, Bz * S));
+    HIP_TRY(grow(&w->tmask, &h3, Bz * S));
   }
   *out = w;
   return SG_OK;
 }
+
+Batch make_batch(Workspace* w, const void* J, const void* h, const int32_t* Ns, int N0, int ld,
+                 int B, int S, int64_t recs, uint32_t cap) {
+  Batch bt{};
+  bt.J = J;
+  bt.h = h;
+  bt.Ns = Ns;
+  bt.N0 = N0;
+  bt.ld = ld;
+  bt.B = B;
+  bt.S = S;
+  bt.P = w->P;
+  bt.qtab = w->qtab;
+  bt.table = w->table;
+  bt.table_recs = recs;
+  bt.cand = w->cand;
+  bt.skey = w->skey;
+  bt.smask = w->smask;
+  bt.cap = cap;
+  bt.rkey = w->rkey;
+  bt.rmask = w->rmask;
+  bt.tkey = w->tkey;
+  bt.tmask = w->tmask;
+  bt.sticky = w->sticky;
+  return bt;
+}
+
+size_t table_records(int ncap) { return ((size_t)1 << (ncap - kU + 1)) - 1; }
 
 // ------------------------------------------------------------------ search
 
@@ -232,30 +293,51 @@ sg_status validate(int N, const void* J, const void* h, int S, uint64_t lo, uint
   return SG_OK;
 }
 
+hipError_t enum_timed(Workspace* w, bool isint, const Batch& bt, const Chunk& ch, int ninst,
+                      hipStream_t st) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (g_timing) {
+    hipError_t r = ws_event_pair(w, &e0, &e1);
+    if (r != hipSuccess) return r;
+    r = hipEventRecord(e0, st);
+    if (r != hipSuccess) return r;
+  }
+  hipError_t r = launch_enum(isint, bt, ch, ninst, st);
+  if (r != hipSuccess) return r;
+  if (g_timing) r = hipEventRecord(e1, st);
+  return r;
+}
+
 sg_status run_search(bool isint, int N, const void* J, const void* h, int S, uint64_t lo,
                      uint64_t hi, uint64_t* states_out, void* energies_out, void* stream) {
   g_last_error.clear();
   sg_status v = validate(N, J, h, S, lo, hi, states_out, energies_out);
   if (v != SG_OK) return v;
   hipStream_t st = (hipStream_t)stream;
+  uint32_t cap = kCandCapMin;
+  while (cap < 8u * (uint32_t)S) cap <<= 1;
+  const int ncap = std::min(kMaxFree, std::max(N, kU));
+  const size_t recs = table_records(kMaxFree);
   Workspace* w = nullptr;
-  v = ws_get(st, S, &w);
+  v = ws_get(st, 1, recs, cap, S, &w);
   if (v != SG_OK) return v;
+  const Batch bt = make_batch(w, J, h, nullptr, N, N, 1, S, (int64_t)recs, cap);
 
-  HIP_TRY(launch_prep(isint, J, h, N, S, w->P, w->qtab, st));
+  HIP_TRY(launch_prep(isint, bt, st));
   const int score_grid = std::max(1, w->cus) * 4;
   int64_t nchunks = 0;
   int kmax = 0, nmaxu = 0;
+  w->ev_used = 0;
   if (N < kU) {
-    HIP_TRY(launch_direct(N, lo, hi, w->P, w->cand, w->cap, st));
-    HIP_TRY(launch_score(isint, J, h, N, w->P, w->cand, w->cap, w->skey, w->smask, score_grid, st));
-    HIP_TRY(launch_merge(w->P, S, w->cap, w->skey, w->smask, w->rkey, w->rmask, w->tkey, w->tmask,
-                         st));
+    HIP_TRY(launch_direct(bt, lo, hi, st));
+    HIP_TRY(launch_score(isint, bt, 0, score_grid, N, st));
+    HIP_TRY(launch_merge(bt, 0, st));
     nchunks = 1;
+    w->last_states = (double)(hi - lo);
   } else {
-    const int nmax = std::min(kMaxFree, N);
-    HIP_TRY(launch_tables(isint, J, h, N, nmax, w->table, st));
+    HIP_TRY(launch_tables(isint, bt, ncap, st));
     const std::vector<PlanChunk> plan = plan_chunks(N, S, lo, hi, w->fill[isint ? 1 : 0]);
+    double states = 0.0;
     for (const PlanChunk& pc : plan) {
       Chunk ch{};
       ch.first_mask = pc.first_mask;
@@ -263,22 +345,145 @@ sg_status run_search(bool isint, int N, const void* J, const void* h, int S, uin
       ch.lanes = pc.lanes;
       ch.n = pc.n;
       ch.table_offset = (1 << (pc.n - kU)) - 1;
-      HIP_TRY(launch_enum(isint, J, h, N, ch, w->table, w->qtab, w->P, w->cand, w->cap, st));
-      HIP_TRY(launch_score(isint, J, h, N, w->P, w->cand, w->cap, w->skey, w->smask, score_grid,
-                           st));
-      HIP_TRY(launch_merge(w->P, S, w->cap, w->skey, w->smask, w->rkey, w->rmask, w->tkey,
-                           w->tmask, st));
+      HIP_TRY(enum_timed(w, isint, bt, ch, 1, st));
+      states += (double)pc.lanes * (double)((uint64_t)1 << pc.n);
+      HIP_TRY(launch_score(isint, bt, 0, score_grid, N, st));
+      HIP_TRY(launch_merge(bt, 0, st));
       kmax = std::max(kmax, N - pc.n);
       nmaxu = std::max(nmaxu, pc.n);
     }
     nchunks = (int64_t)plan.size();
+    w->last_states = states;
   }
-  HIP_TRY(launch_finalize(isint, w->P, S, w->rkey, w->rmask, states_out, energies_out, w->sticky,
-                          st));
+  HIP_TRY(launch_finalize(isint, bt, states_out, energies_out, st));
   w->last_chunks = nchunks;
   w->last_kmax = kmax;
   w->last_nmax = nmaxu;
   return SG_OK;
+}
+
+// Chunk levels of a batched search.  Level 0 is [0, first) with
+// first = max(S, 4096) rounded up to a power of two; level j >= 1 is
+// [first 2^(j-1), first 2^j), so every level is as large as everything before
+// it.  All instances with states in a level run it in the same launch, with
+// the same geometry: n = clamp(log2(size) - 12, U, 17) free spins per lane.
+struct Level {
+  uint64_t first;
+  int n;
+  int64_t lanes;
+};
+
+std::vector<Level> batch_levels(int Nmax, int S) {
+  std::vector<Level> out;
+  uint64_t size0 = 4096;
+  while (size0 < (uint64_t)S) size0 <<= 1;
+  const uint64_t full = (uint64_t)1 << Nmax;
+  uint64_t first = 0, size = size0;
+  while (first < full) {
+    const int a = ilog2_floor(size);
+    int n = std::max(kU, std::min(kBatchFreeCap, a - 12));
+    n = std::min(n, a);
+    out.push_back(Level{first, n, (int64_t)(size >> n)});
+    first += size;
+    size = first;
+  }
+  return out;
+}
+
+// Enqueue the batched search over bt (levels of batch_levels) and its
+// finalize into states_out / energies_out.
+sg_status batch_search(Workspace* w, bool isint, const Batch& bt, int Nmax, int ncap,
+                       uint64_t* states_out, void* energies_out, hipStream_t st) {
+  HIP_TRY(launch_prep(isint, bt, st));
+  HIP_TRY(launch_tables(isint, bt, ncap, st));
+  const std::vector<Level> levels = batch_levels(Nmax, bt.S);
+  w->ev_used = 0;
+  double states = 0.0;
+  int nmaxu = 0;
+  for (const Level& L : levels) {
+    Chunk ch{};
+    ch.first_mask = L.first;
+    ch.prefix_base = L.first >> L.n;
+    ch.lanes = L.lanes;
+    ch.n = L.n;
+    ch.table_offset = (1 << (L.n - kU)) - 1;
+    HIP_TRY(enum_timed(w, isint, bt, ch, bt.B, st));
+    states += (double)L.lanes * (double)((uint64_t)1 << L.n);
+    HIP_TRY(launch_merge_batched(isint, bt, L.first, st));
+    nmaxu = std::max(nmaxu, L.n);
+  }
+  HIP_TRY(launch_finalize(isint, bt, states_out, energies_out, st));
+  w->last_chunks = (int64_t)levels.size();
+  w->last_kmax = Nmax - nmaxu;
+  w->last_nmax = nmaxu;
+  w->last_states = states;
+  return SG_OK;
+}
+
+uint32_t batch_cap(int S) {
+  uint32_t cap = kBatchCandCapMin;
+  while (cap < 2u * 4096u || cap < 4u * (uint32_t)S) cap <<= 1;
+  return cap;
+}
+
+sg_status run_batched(bool isint, int B, const int32_t* Ns, int Nmax, const void* J,
+                      const void* h, int S, uint64_t* states_out, void* energies_out,
+                      void* stream) {
+  g_last_error.clear();
+  if (B < 1) return fail(SG_EINVAL, "B must be >= 1");
+  if (Nmax < kU || Nmax > 40) return fail(SG_EINVAL, "N_max must be in [6, 40]");
+  if (S < 1 || S > SG_MAX_S_BATCHED) return fail(SG_EINVAL, "S must be in [1, SG_MAX_S_BATCHED]");
+  if (!Ns || !J || !h || !states_out || !energies_out)
+    return fail(SG_EINVAL, "null pointer argument");
+  hipStream_t st = (hipStream_t)stream;
+  const uint32_t cap = batch_cap(S);
+  const int ncap = std::min(kBatchFreeCap, Nmax);
+  const size_t recs = table_records(ncap);
+  Workspace* w = nullptr;
+  sg_status v = ws_get(st, B, recs, cap, S, &w);
+  if (v != SG_OK) return v;
+  const Batch bt = make_batch(w, J, h, Ns, 0, Nmax, B, S, (int64_t)recs, cap);
+  return batch_search(w, isint, bt, Nmax, ncap, states_out, energies_out, st);
+}
+
+// ------------------------------------------------------------------ log Z
+
+sg_status lz_validate(int B, int N, const void* J, const void* h, int nb, const void* beta) {
+  if (B < 1) return fail(SG_EINVAL, "B must be >= 1");
+  if (N < kU || N > 40) return fail(SG_EINVAL, "N must be in [6, 40]");
+  if (nb < 1 || nb > kMaxBeta) return fail(SG_EINVAL, "n_beta must be in [1, 4]");
+  if (!J || !h || !beta) return fail(SG_EINVAL, "null pointer argument");
+  return SG_OK;
+}
+
+sg_status lz_buffers(Workspace* w, int B, int N) {
+  const size_t Bz = (size_t)B;
+  const size_t stride = std::max<size_t>(kMaxBeta, (size_t)N * N + N);
+  HIP_TRY(grow(&w->table64, &w->ntable64, Bz * table_records(std::min(kLzFree, N)) * 8));
+  HIP_TRY(grow(&w->q64, &w->nq64, Bz * 2 * kBlockSteps));
+  HIP_TRY(grow(&w->lz_acc, &w->nlz_acc, Bz * stride));
+  HIP_TRY(grow(&w->lz_coef, &w->nlz_coef, Bz * kMaxBeta));
+  return SG_OK;
+}
+
+LzArgs lz_args(Workspace* w, int B, int N, int nb, int S, const float* beta, const float* e0,
+               int mode) {
+  LzArgs a{};
+  a.B = B;
+  a.N = N;
+  a.n = std::min(kLzFree, N);
+  a.nb = nb;
+  a.S = S;
+  a.lanes = (int64_t)1 << (N - a.n);
+  a.table_recs = (int64_t)table_records(std::min(kLzFree, N));
+  a.table_offset = (1 << (a.n - kU)) - 1;
+  a.beta = beta;
+  a.e0 = e0;
+  a.coef = w->lz_coef;
+  a.acc = w->lz_acc;
+  a.acc_stride = mode == 0 ? kMaxBeta : N * N + N;
+  a.sticky = w->sticky;
+  return a;
 }
 
 Workspace* ws_find(hipStream_t st) {
@@ -290,6 +495,9 @@ Workspace* ws_find(hipStream_t st) {
 }
 
 sg_status status_of_bits(uint32_t bits) {
+  if (bits & kErrInval)
+    return fail(SG_EINVAL,
+                "device-side argument check: N_b outside [6, N_max], S > 2^N_b, or a beta not > 0");
   if (bits & kErrNonFinite) return fail(SG_ENONFINITE, "NaN or Inf in J or h");
   if (bits & kErrOverflow)
     return fail(SG_EOVERFLOW, "integer instance too large: sum|J| + sum|h| must be < 2^28");
@@ -326,6 +534,76 @@ sg_status sg_low_spectrum_range_i32(int N, const int32_t* J, const int32_t* h, i
   return run_search(true, N, J, h, S, lo, hi, states_out, energies_out, stream);
 }
 
+sg_status sg_low_spectrum_batched_f32(int B, const int32_t* N_dev, int N_max, const float* J,
+                                      const float* h, int S, uint64_t* states_out,
+                                      float* energies_out, void* stream) {
+  return run_batched(false, B, N_dev, N_max, J, h, S, states_out, energies_out, stream);
+}
+
+sg_status sg_low_spectrum_batched_i32(int B, const int32_t* N_dev, int N_max, const int32_t* J,
+                                      const int32_t* h, int S, uint64_t* states_out,
+                                      int32_t* energies_out, void* stream) {
+  return run_batched(true, B, N_dev, N_max, J, h, S, states_out, energies_out, stream);
+}
+
+sg_status sg_logz_forward_f32(int B, int N, const float* J, const float* h, int n_beta,
+                              const float* beta, int S, double* logz_out, float* e0_out,
+                              uint64_t* states_out, float* energies_out, void* stream) {
+  g_last_error.clear();
+  sg_status v = lz_validate(B, N, J, h, n_beta, beta);
+  if (v != SG_OK) return v;
+  if (!logz_out || !e0_out || !states_out || !energies_out)
+    return fail(SG_EINVAL, "null pointer argument");
+  if (S < 1 || S > SG_MAX_S_BATCHED || (uint64_t)S > ((uint64_t)1 << N))
+    return fail(SG_EINVAL, "S must be in [1, min(SG_MAX_S_BATCHED, 2^N)]");
+  hipStream_t st = (hipStream_t)stream;
+  const uint32_t cap = batch_cap(S);
+  const int ncap = std::min(kBatchFreeCap, N);
+  const size_t recs = table_records(ncap);
+  Workspace* w = nullptr;
+  v = ws_get(st, B, recs, cap, S, &w);
+  if (v != SG_OK) return v;
+  v = lz_buffers(w, B, N);
+  if (v != SG_OK) return v;
+  // 1. low spectrum of every instance (E0 and the S lowest states)
+  const Batch bt = make_batch(w, J, h, nullptr, N, N, B, S, (int64_t)recs, cap);
+  v = batch_search(w, false, bt, N, ncap, states_out, energies_out, st);
+  if (v != SG_OK) return v;
+  // 2. partition sums shifted by E0
+  const LzArgs a = lz_args(w, B, N, n_beta, S, beta, e0_out, 0);
+  Batch b64 = bt;
+  b64.table_recs = a.table_recs;
+  HIP_TRY(launch_tables64(b64, std::min(kLzFree, N), w->table64, st));
+  HIP_TRY(launch_lz_prep(0, a, J, w->q64, energies_out, e0_out, nullptr, nullptr, st));
+  HIP_TRY(launch_logz(0, a, J, h, w->table64, w->q64, st));
+  HIP_TRY(launch_lz_final(0, a, logz_out, nullptr, nullptr, st));
+  return SG_OK;
+}
+
+sg_status sg_logz_backward_f32(int B, int N, const float* J, const float* h, int n_beta,
+                               const float* beta, const float* e0, const double* logz,
+                               const double* grad_logz, float* grad_J, float* grad_h,
+                               void* stream) {
+  g_last_error.clear();
+  sg_status v = lz_validate(B, N, J, h, n_beta, beta);
+  if (v != SG_OK) return v;
+  if (!e0 || !logz || !grad_logz || !grad_J || !grad_h)
+    return fail(SG_EINVAL, "null pointer argument");
+  hipStream_t st = (hipStream_t)stream;
+  Workspace* w = nullptr;
+  v = ws_get(st, B, 1, 1, 1, &w);
+  if (v != SG_OK) return v;
+  v = lz_buffers(w, B, N);
+  if (v != SG_OK) return v;
+  const LzArgs a = lz_args(w, B, N, n_beta, 1, beta, e0, 1);
+  Batch b64 = make_batch(w, J, h, nullptr, N, N, B, 1, a.table_recs, 1);
+  HIP_TRY(launch_tables64(b64, std::min(kLzFree, N), w->table64, st));
+  HIP_TRY(launch_lz_prep(1, a, J, w->q64, nullptr, nullptr, logz, grad_logz, st));
+  HIP_TRY(launch_logz(1, a, J, h, w->table64, w->q64, st));
+  HIP_TRY(launch_lz_final(1, a, nullptr, grad_J, grad_h, st));
+  return SG_OK;
+}
+
 sg_status sg_get_error(void* stream) {
   hipStream_t st = (hipStream_t)stream;
   HIP_TRY(hipStreamSynchronize(st));
@@ -357,7 +635,24 @@ sg_status sg_get_run_info(void* stream, sg_run_info* out) {
   out->max_drift = d;
   out->prefix_bits_max = w->last_kmax;
   out->free_bits_max = w->last_nmax;
+  out->enum_launches = w->last_chunks;
+  out->enum_states = w->last_states;
+  double ms = 0.0;
+  for (int i = 0; i < w->ev_used; ++i) {
+    float t = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&t, w->ev[2 * i], w->ev[2 * i + 1]));
+    ms += t;
+  }
+  out->enum_ms = ms;
+  out->max_chunk_candidates = p.max_chunk_cand;
   return SG_OK;
+}
+
+void sg_set_kernel_timing(int enable) { g_timing = enable != 0; }
+
+double sg_probe_valu(int op, int waves_per_simd) {
+  if (op < 0 || op > 13 || waves_per_simd < 1 || waves_per_simd > 8) return -1.0;
+  return probe_valu(op, waves_per_simd);
 }
 
 int sg_debug_plan(int N, int S, uint64_t lo, uint64_t hi, int64_t lanes_fill,

@@ -23,11 +23,13 @@ constexpr int kBlockSteps = 1 << kU;
 constexpr int kMaxFree = 22;          // largest n (free spins per lane)
 constexpr int kMaxHigh = kMaxFree - kU;
 constexpr int kRecWords = 8;          // per-block table record (32 B)
-constexpr int kReanchorLog2 = 16;     // fp32: fresh G every 2^16 flips
+constexpr int kReanchorLog2 = 10;     // fp32: fresh G every 2^10 flips
 constexpr int kReanchorBlocks = 1 << (kReanchorLog2 - kU);
 constexpr int kWaveLanes = 64;
 constexpr int kEnumBlock = 256;       // threads per enumeration workgroup
 constexpr int kMergeThreads = 1024;   // threads of the single-workgroup merge
+constexpr int kMergeBatchThreads = 256;  // threads per instance in the batched merge
+constexpr int kBatchFreeCap = 17;     // largest n of a batched search
 constexpr int kLdsSortCap = 4096;     // survivors sorted in LDS up to this
 constexpr int kMaxN = 56;
 
@@ -37,6 +39,7 @@ enum : uint32_t {
   kErrOverflow = 1u << 1,
   kErrCapacity = 1u << 2,
   kErrDrift = 1u << 3,
+  kErrInval = 1u << 4,   // device-side argument check (batched N_b, S)
 };
 
 // Per-search device state, written by the prep / merge kernels and read by
@@ -58,7 +61,51 @@ struct Params {
   unsigned long long stat_candidates;
   unsigned long long stat_slow;
   uint32_t max_drift_bits;  // float bits, non-negative
-  uint32_t pad0;
+  uint32_t max_chunk_cand;  // most candidates any one chunk produced
+};
+
+// Device views of one search over B instances (B = 1 for a single search).
+// Instance b has N_b spins (Ns[b], or N0 for every instance when Ns is
+// null); its couplings are J[b][i][j] with row stride ld (i < j read), its
+// fields h[b][i].  Every per-instance buffer is a slice of a [B][...] array.
+struct Batch {
+  const void* J;
+  const void* h;
+  const int32_t* Ns;
+  int N0;
+  int ld;
+  int B;
+  int S;
+  Params* P;           // [B]
+  uint32_t* qtab;      // [B][2 * kBlockSteps]
+  uint32_t* table;     // [B][table_recs][kRecWords]
+  int64_t table_recs;
+  uint64_t* cand;      // [B][cap]
+  uint32_t* skey;      // [B][cap]
+  uint64_t* smask;     // [B][cap]
+  uint32_t cap;
+  uint32_t* rkey;      // [B][S] record: keys ascending
+  uint64_t* rmask;     // [B][S]
+  uint32_t* tkey;      // [B][S] merge scratch
+  uint64_t* tmask;     // [B][S]
+  uint32_t* sticky;    // error bits accumulated over searches
+};
+
+// Exact log Z walk (forward: partition sums; backward: gradient moments).
+constexpr int kMaxBeta = 4;
+constexpr int kLzFree = 14;  // free spins per lane: n = min(N, 14)
+
+struct LzArgs {
+  int B, N, n, nb, S;
+  int64_t lanes;        // lanes per instance: 2^(N - n)
+  int64_t table_recs;   // fp64 records per instance
+  int table_offset;     // first record of the table of n
+  const float* beta;    // [nb]
+  const float* e0;      // [B] shift (ground energy)
+  double* coef;         // [B][kMaxBeta]: backward weights g_b beta_b / Z_b
+  double* acc;          // forward: [B][kMaxBeta]; backward: [B][N*N + N]
+  int acc_stride;
+  uint32_t* sticky;
 };
 
 // One enumeration launch: lanes L, prefixes base..base+L-1, n free spins.

@@ -1,15 +1,16 @@
 // sg_kernels.hip -- gfx950 kernels of the exhaustive low-spectrum search.
 //
-// Pipeline per search (all on one stream, no host round trip):
-//   k_prep      instance checks, |J|+|h| bound, pruning margin, Q tables
-//   k_tables    per-block records of every free-spin count n in use
-//   per chunk (Sec. 3, Algorithm 1, one chunk of the state space):
-//     k_enum    Gray-code enumeration, one lane per prefix; candidates out
-//     k_score   exact energy of every candidate, keep those beating the
-//               current S-th key
-//     k_merge   sort the survivors, merge them into the running top-S record,
-//               update the threshold
-//   k_finalize  record -> caller's output arrays
+// Pipeline of one search over B instances (B = 1 for a single instance), all
+// on one stream with no host round trip:
+//   k_prep       per-instance checks, |J|+|h| bound, pruning margin, Q tables
+//   k_tables     per-block records of every free-spin count n in use
+//   per chunk of the state space (Sec. 3, Algorithm 1):
+//     k_enum     Gray-code enumeration, one lane per prefix; candidates out
+//     k_score +  exact energy of every candidate, keep those beating the
+//     k_merge    current S-th key, sort them and merge them into the running
+//                top-S record (single instance: a grid + one workgroup;
+//                batch: k_merge_batched, one workgroup per instance)
+//   k_finalize   record -> caller's output arrays
 //
 // Energy of Eq. (1), mask bit i <-> spin i, bit set <-> s_i = +1.
 #include <hip/hip_runtime.h>
@@ -21,38 +22,44 @@ namespace sg {
 
 // ------------------------------------------------------------------ helpers
 
-__device__ inline float jf(const float* J, int N, int a, int b) {
-  return a < b ? J[a * N + b] : J[b * N + a];
+__device__ inline int inst_N(const Batch& bt, int b) { return bt.Ns ? bt.Ns[b] : bt.N0; }
+
+template <typename T>
+__device__ inline const T* inst_J(const Batch& bt, int b) {
+  return (const T*)bt.J + (size_t)b * bt.ld * bt.ld;
 }
-__device__ inline int32_t ji(const int32_t* J, int N, int a, int b) {
-  return a < b ? J[a * N + b] : J[b * N + a];
+template <typename T>
+__device__ inline const T* inst_h(const Batch& bt, int b) {
+  return (const T*)bt.h + (size_t)b * bt.ld;
 }
 
 __device__ inline uint32_t gray32(uint32_t t) { return t ^ (t >> 1); }
 
-// Energy of one state from scratch, Eq. (1), fixed i<j order.
-__device__ inline double energy_f64(const float* J, const float* h, int N, uint64_t m) {
+// Energy of one state from scratch, Eq. (1), fixed i<j order; J has row
+// stride ld.
+__device__ inline double energy_f64(const float* J, const float* h, int N, int ld, uint64_t m) {
   double e = 0.0;
   for (int i = 0; i < N; ++i) {
     const double si = ((m >> i) & 1ull) ? 1.0 : -1.0;
     double f = (double)h[i];
     for (int j = i + 1; j < N; ++j) {
       const double sj = ((m >> j) & 1ull) ? 1.0 : -1.0;
-      f += (double)J[i * N + j] * sj;
+      f += (double)J[i * ld + j] * sj;
     }
     e -= si * f;
   }
   return e;
 }
 
-__device__ inline int32_t energy_i32(const int32_t* J, const int32_t* h, int N, uint64_t m) {
+__device__ inline int32_t energy_i32(const int32_t* J, const int32_t* h, int N, int ld,
+                                     uint64_t m) {
   int32_t e = 0;
   for (int i = 0; i < N; ++i) {
     const int32_t si = ((m >> i) & 1ull) ? 1 : -1;
     int32_t f = h[i];
     for (int j = i + 1; j < N; ++j) {
       const int32_t sj = ((m >> j) & 1ull) ? 1 : -1;
-      f += J[i * N + j] * sj;
+      f += J[i * ld + j] * sj;
     }
     e -= si * f;
   }
@@ -101,46 +108,70 @@ __device__ inline void append_mask(uint64_t mask, Params* P, uint64_t* cand, uin
 }
 
 // ------------------------------------------------------------------ k_prep
-// One workgroup.  Writes the Q tables (low-spin coupling energy for both
-// block parities), their minimum, the pruning margin, the error flags and the
-// initial (empty) record state.
+// One workgroup per instance.  Writes the Q tables (low-spin coupling energy
+// for both block parities), their minimum, the pruning margin, the error
+// flags and the initial (empty) record state.
 
 template <bool kInt>
-__global__ void k_prep(const void* Jv, const void* hv, int N, int S, Params* P,
-                       uint32_t* qtab) {
+__global__ void k_prep(Batch bt) {
+  const int b = blockIdx.x;
+  const int N = inst_N(bt, b);
+  const int ld = bt.ld;
+  Params* P = bt.P + b;
+  uint32_t* qtab = bt.qtab + (size_t)b * 2 * kBlockSteps;
+  // a batch (per-instance sizes) needs N_b >= U; a single search takes any N >= 1
+  const bool badN = N < (bt.Ns ? kU : 1) || N > ld || (N < 63 && (uint64_t)bt.S > (1ull << N));
+  const int Nc = badN ? 0 : N;
+  using T = typename std::conditional<kInt, int32_t, float>::type;
+  const T* Jb = inst_J<T>(bt, b);
+  const T* hb = inst_h<T>(bt, b);
+
   __shared__ double s_sum[256];
   __shared__ int s_bad[256];
+  __shared__ int s_lsb[256];
   const int tid = threadIdx.x;
   double acc = 0.0;
   int bad = 0;
-  for (int idx = tid; idx < N * N + N; idx += blockDim.x) {
+  int lsb = 1 << 20;  // smallest exponent of a set bit over all values (fp32)
+  for (int idx = tid; idx < Nc * Nc + Nc; idx += blockDim.x) {
     double v;
     bool use;
-    if (idx < N * N) {
-      const int i = idx / N, j = idx % N;
+    if (idx < Nc * Nc) {
+      const int i = idx / Nc, j = idx % Nc;
       use = i < j;
-      v = kInt ? (double)((const int32_t*)Jv)[idx] : (double)((const float*)Jv)[idx];
+      v = (double)Jb[i * ld + j];
     } else {
       use = true;
-      v = kInt ? (double)((const int32_t*)hv)[idx - N * N] : (double)((const float*)hv)[idx - N * N];
+      v = (double)hb[idx - Nc * Nc];
     }
     if (use) {
       if (!kInt && !isfinite(v)) bad = 1;
       else acc += fabs(v);
+      if (!kInt && v != 0.0) {
+        const uint32_t bits = __float_as_uint((float)v);
+        const int ex = (int)((bits >> 23) & 0xffu);
+        const uint32_t man = bits & 0x7fffffu;
+        const int e = ex == 0 ? -149 + __builtin_ctz(man)
+                              : ex - 150 + __builtin_ctz(man | 0x800000u);
+        lsb = min(lsb, e);
+      }
     }
   }
   s_sum[tid] = acc;
   s_bad[tid] = bad;
+  s_lsb[tid] = lsb;
   __syncthreads();
   for (int st = 128; st > 0; st >>= 1) {
     if (tid < st) {
       s_sum[tid] += s_sum[tid + st];
       s_bad[tid] |= s_bad[tid + st];
+      s_lsb[tid] = min(s_lsb[tid], s_lsb[tid + st]);
     }
     __syncthreads();
   }
   const double Bv = s_sum[0];
   const int anybad = s_bad[0];
+  const int lsb_min = s_lsb[0];
 
   // Q tables: Q(x) = -sum_{f<f'<U} J_ff' s_f s_f' over the low configuration
   // x = gray(i) ^ (par << (U-1)) of step i in a block of parity par.
@@ -150,12 +181,10 @@ __global__ void k_prep(const void* Jv, const void* hv, int N, int S, Params* P,
     const int par = tid / kBlockSteps, i = tid % kBlockSteps;
     const uint32_t x = gray32((uint32_t)i) ^ ((uint32_t)par << (U - 1));
     double q = 0.0;
-    for (int a = 0; a < U && a < N; ++a)
-      for (int b = a + 1; b < U && b < N; ++b) {
-        const double sa = ((x >> a) & 1u) ? 1.0 : -1.0, sb = ((x >> b) & 1u) ? 1.0 : -1.0;
-        const double jv = kInt ? (double)((const int32_t*)Jv)[a * N + b]
-                               : (double)((const float*)Jv)[a * N + b];
-        q -= jv * sa * sb;
+    for (int a = 0; a < U && a < Nc; ++a)
+      for (int c = a + 1; c < U && c < Nc; ++c) {
+        const double sa = ((x >> a) & 1u) ? 1.0 : -1.0, sc = ((x >> c) & 1u) ? 1.0 : -1.0;
+        q -= (double)Jb[a * ld + c] * sa * sc;
       }
     s_q[tid] = q;
     if (kInt) qtab[tid] = (uint32_t)(int32_t)q;
@@ -169,28 +198,35 @@ __global__ void k_prep(const void* Jv, const void* hv, int N, int S, Params* P,
   if (tid == 0) {
     const double qmin = s_q[0];
     uint32_t err = 0;
+    if (badN) err |= kErrInval;
     if (anybad) err |= kErrNonFinite;
     if (kInt && Bv >= 268435456.0) err |= kErrOverflow;  // 2^28
-    // Margin (fp32): a bound on |computed G - exact G| + the rounding of the
-    // rescored key.  Exact G, W, Y, boundary constants and energies are all
-    // bounded by 2 Bv; the computed ones stay below 2 Bv + margin < 2.1 Bv
-    // (margin < 0.03 Bv below), so each fp32 rounding is at most
-    // uH = H 2^-24 with H the power of two above 2.1 Bv.  Between two
-    // re-anchors a lane crosses at most R = 2^16 / 2^U block boundaries, and
-    // per block G takes 63 rounded inner adds, 2 rounded boundary adds and a
-    // rounded boundary constant; the block's W values carry three roundings
-    // each and enter the block's sum with net weight at most 1 (a spin's
-    // flips alternate in sign).  Add the anchor (2 + n/2 roundings), the
-    // high fields (net weight <= 1 each over any stretch, n of them), the
-    // final E = G + Q (2) and the key rounding (2).
+    // Margin (fp32): a bound on |computed E - exact E| of any state, plus
+    // the rounding of the rescored key.  Exact G, W, Y, the table constants
+    // and energies are all bounded by 2 Bv; the computed ones stay below
+    // 2 Bv + margin < 2.1 Bv (margin < 0.01 Bv below), so each fp32
+    // rounding is at most uH = H 2^-24, H the power of two above 2.1 Bv.
+    // Between two re-anchors (R = 2^10 / 2^U blocks) G takes per block 63
+    // rounded inner adds, 2 rounded boundary adds and a rounded boundary
+    // constant, and the block's W values carry three roundings each with net
+    // weight at most 1 per block (a spin's flips alternate in sign).  The
+    // re-anchor itself rounds n + 3 times and starts from per-lane fields
+    // rounded once each (n/2, fixed per lane: the high fields enter with net
+    // weight <= 1 over any stretch); add the final E = G + Q (2) and the key
+    // rounding (2).  When every value is a multiple of 2^lsb and 2.1 Bv
+    // < 2^(24 + lsb), every fp32 operation on the path is exact: margin 0.
     double margin = 0.0;
     if (!kInt) {
       double H = 1.0;
       while (H <= 2.1 * Bv) H *= 2.0;
-      const double uH = H * 5.9604644775390625e-08;  // 2^-24
-      const double R = (double)kReanchorBlocks;
-      const double rounds = R * (63.0 + 3.0 * U + 3.0) + (2.0 + kMaxFree * 0.5) + kMaxFree + 4.0;
-      margin = rounds * uH;
+      const bool exact = Bv == 0.0 || (lsb_min < (1 << 19) && 2.1 * Bv < ldexp(1.0, 24 + lsb_min));
+      if (!exact) {
+        const double uH = H * 5.9604644775390625e-08;  // 2^-24
+        const double R = (double)kReanchorBlocks;
+        const double rounds =
+            R * (63.0 + 3.0 * U + 3.0) + (kMaxFree + 3.0) + kMaxFree * 0.5 + 4.0 + 4.0;
+        margin = rounds * uH;
+      }
     }
     P->thr_key = 0xFFFFFFFFu;
     P->rec_count = 0;
@@ -204,7 +240,7 @@ __global__ void k_prep(const void* Jv, const void* hv, int N, int S, Params* P,
     P->stat_candidates = 0;
     P->stat_slow = 0;
     P->max_drift_bits = 0;
-    (void)S;
+    P->max_chunk_cand = 0;
   }
 }
 
@@ -221,10 +257,14 @@ __global__ void k_prep(const void* Jv, const void* hv, int N, int S, Params* P,
 //                 odd T, -1 for even T (old value of spin U-1 when the inner
 //                 step 2^(U-1) flips it).
 // Tables for n = U .. nmax are concatenated; the table of n starts at record
-// 2^(n-U) - 1.
+// 2^(n-U) - 1.  grid.y indexes the instance.
 
-template <bool kInt>
-__global__ void k_tables(const void* Jv, const void* hv, int N, int nmax, uint32_t* table) {
+template <bool kInt, bool kF64>
+__global__ void k_tables(Batch bt, int ncap, void* out) {
+  const int b = blockIdx.y;
+  const int N = inst_N(bt, b);
+  if (N < kU || N > bt.ld) return;
+  const int nmax = min(ncap, N);
   const int64_t total = ((int64_t)1 << (nmax - kU + 1)) - 1;
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= total) return;
@@ -233,13 +273,13 @@ __global__ void k_tables(const void* Jv, const void* hv, int N, int nmax, uint32
   while (((int64_t)1 << (n - kU + 1)) - 1 <= r) ++n;
   const uint32_t T = (uint32_t)(r - (((int64_t)1 << (n - kU)) - 1));
   const int U = kU;
+  const int ld = bt.ld;
   const uint32_t x = gray32(T << U);
-  auto J = [&](int a, int b) -> double {
-    return kInt ? (double)ji((const int32_t*)Jv, N, a, b) : (double)jf((const float*)Jv, N, a, b);
-  };
-  auto H = [&](int a) -> double {
-    return kInt ? (double)((const int32_t*)hv)[a] : (double)((const float*)hv)[a];
-  };
+  using Tv = typename std::conditional<kInt, int32_t, float>::type;
+  const Tv* Jb = inst_J<Tv>(bt, b);
+  const Tv* hb = inst_h<Tv>(bt, b);
+  auto J = [&](int a, int c) -> double { return (double)(a < c ? Jb[a * ld + c] : Jb[c * ld + a]); };
+  auto H = [&](int a) -> double { return (double)hb[a]; };
   auto S = [&](int j) -> double { return ((x >> j) & 1u) ? 1.0 : -1.0; };
 
   double cB = 0.0;
@@ -255,12 +295,12 @@ __global__ void k_tables(const void* Jv, const void* hv, int N, int nmax, uint32
   double eff = 0.0;
   for (int a = 0; a < n; ++a) {
     double f = H(a);
-    for (int b = a + 1; b < n; ++b) f += J(a, b) * S(b);
+    for (int c = a + 1; c < n; ++c) f += J(a, c) * S(c);
     eff -= S(a) * f;
   }
   double q = 0.0;
   for (int a = 0; a < U; ++a)
-    for (int b = a + 1; b < U; ++b) q -= J(a, b) * S(a) * S(b);
+    for (int c = a + 1; c < U; ++c) q -= J(a, c) * S(a) * S(c);
   const double R = eff - q;
   double wu[kU];
   for (int f = 0; f < U; ++f) {
@@ -270,7 +310,14 @@ __global__ void k_tables(const void* Jv, const void* hv, int N, int nmax, uint32
   }
   wu[U - 1] *= (T & 1u) ? 1.0 : -1.0;
 
-  uint32_t* rec = table + (size_t)r * kRecWords;
+  if (kF64) {  // records of 8 doubles (the log Z walk keeps its energies in fp64)
+    double* rec = (double*)out + ((size_t)b * bt.table_recs + (size_t)r) * 8;
+    rec[0] = cB;
+    rec[1] = R;
+    for (int f = 0; f < U; ++f) rec[2 + f] = wu[f];
+    return;
+  }
+  uint32_t* rec = bt.table + ((size_t)b * bt.table_recs + (size_t)r) * kRecWords;
   if (kInt) {
     rec[0] = (uint32_t)(int32_t)cB;
     rec[1] = (uint32_t)(int32_t)R;
@@ -285,12 +332,13 @@ __global__ void k_tables(const void* Jv, const void* hv, int N, int nmax, uint32
 // ------------------------------------------------------------------ k_enum
 // One lane per prefix p (spins n..N-1 fixed to the bits of p); the lane walks
 // all 2^n configurations of the free spins in reflected Gray-code order,
-// blocks of 2^U steps at a time.  G (the energy minus the low-low part) is
-// updated by one add per state; the block's minimum of G plus the smallest
-// low-low energy is a lower bound on every energy in the block, so a block
-// whose bound exceeds the threshold is skipped without looking at its states
-// one by one.  Otherwise the block is walked again (same arithmetic) and every
-// state at or below the threshold is appended as a candidate mask.
+// blocks of 2^U steps at a time.  Every state costs one add (its G, the
+// energy minus the low-low part) and enters the block minimum (one 3-input
+// min per two states).  The block minimum plus the smallest low-low energy
+// bounds every energy of the block from below; a block whose bound passes the
+// threshold is walked again with the same arithmetic, each state tested
+// exactly, and every state at or below the threshold is appended as a
+// candidate mask.  blockIdx.x / blocks_per_inst selects the instance.
 
 template <typename V>
 struct Num;
@@ -306,36 +354,44 @@ struct Num<int32_t> {
 };
 
 template <bool kInt>
-__global__ __launch_bounds__(kEnumBlock, 8) void k_enum(
-    const void* __restrict__ Jv, const void* __restrict__ hv, int N, Chunk ch,
-    const uint32_t* __restrict__ table, const uint32_t* __restrict__ qtab,
-    Params* __restrict__ P, uint64_t* __restrict__ cand, uint32_t cand_cap) {
+__global__ __launch_bounds__(kEnumBlock, 8) void k_enum(Batch bt, const void* __restrict__ Jv,
+                                                        const void* __restrict__ hv,
+                                                        const uint32_t* __restrict__ table,
+                                                        const uint32_t* __restrict__ qtab_all,
+                                                        Chunk ch, int blocks_per_inst) {
   using V = typename std::conditional<kInt, int32_t, float>::type;
   using A = typename std::conditional<kInt, int64_t, double>::type;  // exact init
   constexpr int U = kU;
 
-  // Q tables of both parities, and the lane's high-spin fields Y_g (index
-  // [g - U][thread]): read once per block boundary, so they live in LDS
-  // rather than in registers.
-  __shared__ V s_q[2 * kBlockSteps];
-  __shared__ V s_y[kMaxHigh * kEnumBlock];
-  for (int k = threadIdx.x; k < 2 * kBlockSteps; k += blockDim.x) {
-    const uint32_t b = qtab[k];
-    s_q[k] = kInt ? (V)(int32_t)b : (V)__uint_as_float(b);
-  }
-
+  const int b = blockIdx.x / blocks_per_inst;
+  const int blk = blockIdx.x - b * blocks_per_inst;
+  const int N = inst_N(bt, b);
+  const int n = ch.n;
+  // this chunk's masks must lie inside the instance's state space
+  if (N < n || N > bt.ld || (N < 63 && ch.first_mask >= (1ull << N))) return;
+  const int64_t lanes = N < 63 ? min(ch.lanes, (int64_t)(((1ull << N) - ch.first_mask) >> n))
+                               : ch.lanes;
+  Params* P = bt.P + b;
   const uint32_t err0 = P->err;
-  if (err0 & (kErrNonFinite | kErrOverflow)) return;
+  if (err0 & (kErrNonFinite | kErrOverflow | kErrInval)) return;
+
+  // The lane's high-spin fields Y_g (index [g - U][thread]) are read once per
+  // block boundary, so they live in LDS rather than in registers.
+  __shared__ V s_y[kMaxHigh * kEnumBlock];
+  const uint32_t* qtab = qtab_all + (size_t)b * 2 * kBlockSteps;  // uniform: SGPRs
 
   const int tid = threadIdx.x;
-  const int n = ch.n;
-  const int64_t lane = (int64_t)blockIdx.x * kEnumBlock + tid;
-  const bool valid = lane < ch.lanes;
+  const int ld = bt.ld;
+  const int64_t lane = (int64_t)blk * kEnumBlock + tid;
+  const bool valid = lane < lanes;
   const uint64_t p = ch.prefix_base + (uint64_t)(valid ? lane : 0);
-  const uint32_t* tab = table + (size_t)ch.table_offset * kRecWords;
+  const uint32_t* tab =
+      table + ((size_t)b * bt.table_recs + (size_t)ch.table_offset) * kRecWords;
+  uint64_t* cand = bt.cand + (size_t)b * bt.cap;
+  const uint32_t cand_cap = bt.cap;
 
-  const V* Jt = (const V*)Jv;
-  const V* ht = (const V*)hv;
+  const V* Jt = (const V*)Jv + (size_t)b * ld * ld;
+  const V* ht = (const V*)hv + (size_t)b * ld;
 
   // ---- per-lane init (exact in int64 / fp64) --------------------------------
   // y_f = sum_{q >= n} J_fq s_q (field on free spin f from the prefix);
@@ -347,7 +403,7 @@ __global__ __launch_bounds__(kEnumBlock, 8) void k_enum(
   for (int f = 0; f < U; ++f) {
     A acc = 0;
     for (int q = n; q < N; ++q) {
-      const A jq = (A)Jt[f * N + q];
+      const A jq = (A)Jt[f * ld + q];
       acc += ((p >> (q - n)) & 1ull) ? jq : -jq;
     }
     ysum += acc;
@@ -356,7 +412,7 @@ __global__ __launch_bounds__(kEnumBlock, 8) void k_enum(
   for (int f = U; f < n; ++f) {
     A acc = 0;
     for (int q = n; q < N; ++q) {
-      const A jq = (A)Jt[f * N + q];
+      const A jq = (A)Jt[f * ld + q];
       acc += ((p >> (q - n)) & 1ull) ? jq : -jq;
     }
     ysum += acc;
@@ -367,7 +423,7 @@ __global__ __launch_bounds__(kEnumBlock, 8) void k_enum(
     const A sq = ((p >> (q - n)) & 1ull) ? (A)1 : (A)-1;
     A f = (A)ht[q];
     for (int r = q + 1; r < N; ++r) {
-      const A jr = (A)Jt[q * N + r];
+      const A jr = (A)Jt[q * ld + r];
       f += ((p >> (r - n)) & 1ull) ? jr : -jr;
     }
     EP -= sq * f;
@@ -378,7 +434,18 @@ __global__ __launch_bounds__(kEnumBlock, 8) void k_enum(
     const A R0 = kInt ? (A)(int32_t)r0 : (A)__uint_as_float(r0);
     G = valid ? (V)(EP + ysum + R0) : Num<V>::big();
   }
-  __syncthreads();  // s_q, s_y visible
+  // fp32 re-anchor constants: E_P minus the low spins' prefix fields at a
+  // block start of either parity (low spins all -1, except spin U-1 = +1 in
+  // odd blocks), from the rounded fields the walk itself uses.
+  float epa0 = 0.0f, epa1 = 0.0f;
+  if (!kInt) {
+    double lo = 0.0;
+    for (int f = 0; f < U - 1; ++f) lo += 0.5 * (double)WL[f];
+    const double yl = 0.5 * (double)WL[U - 1];
+    epa0 = (float)((double)EP + lo + yl);
+    epa1 = (float)((double)EP + lo - yl);
+  }
+  __syncthreads();  // s_y visible
 
   // ---- thresholds ------------------------------------------------------------
   const uint32_t thr_key = P->thr_key;
@@ -394,9 +461,16 @@ __global__ __launch_bounds__(kEnumBlock, 8) void k_enum(
     fastThr = (V)(t - (int64_t)P->qmin_i);
   } else {
     if (full) {
-      const double t = (double)__uint_as_float(bits_of_f32_key(thr_key)) + (double)P->margin;
-      thrE = (V)f32_up(t);
-      fastThr = (V)f32_up(t - (double)P->qmin_f);
+      const float tk = __uint_as_float(bits_of_f32_key(thr_key));
+      float te;
+      if (P->margin > 0.0f) {
+        te = f32_up((double)tk + (double)P->margin);
+      } else {
+        // exact fp32 instance: the integer tie rule applies unchanged
+        te = (ch.first_mask > thr_mask) ? nextafterf(tk, -__int_as_float(0x7f800000)) : tk;
+      }
+      thrE = (V)te;
+      fastThr = (V)f32_up((double)te - (double)P->qmin_f);
     } else {
       thrE = Num<V>::big();
       fastThr = Num<V>::big();
@@ -405,7 +479,7 @@ __global__ __launch_bounds__(kEnumBlock, 8) void k_enum(
 
   const uint32_t nblocks = 1u << (n - U);
   float drift = 0.0f;
-  uint32_t slow = 0;
+  uint32_t slow = 0;  // wave-blocks that took the re-walk (wave-uniform)
   V ynext = nblocks > 1 ? s_y[tid] : (V)0;  // block 1 flips high spin U
 
   for (uint32_t T = 0; T < nblocks; ++T) {
@@ -425,21 +499,16 @@ __global__ __launch_bounds__(kEnumBlock, 8) void k_enum(
       G = up ? G + ycur : G - ycur;
       G = G + rw[0];
       if (!kInt && (T & (kReanchorBlocks - 1)) == 0) {
-        // fresh G = E_P - sum_f s_f y_f + R(T), with y = WL/2 and Y/2
-        const uint32_t x = gray32(T << U);
-        double a = (double)EP + (double)rw[1];
-#pragma unroll
-        for (int f = 0; f < U; ++f) {
-          float wl = (float)WL[f];
-          asm volatile("" : "+v"(wl));  // keep the conversion inside this rare path
-          const double yf = 0.5 * (double)wl;
-          a += ((x >> f) & 1u) ? -yf : yf;
-        }
+        // fresh G = E_P - sum_f s_f y_f + R(T) in fp32 from the lane's
+        // fields: the low part is the parity constant, the high part one LDS
+        // read and one fma per high spin (signs from the Gray code of T)
+        const uint32_t xh = gray32(T);  // high spins' bits
+        float a = (float)(T & 1u ? epa1 : epa0) + (float)rw[1];
         for (int k = 0; k < n - U; ++k) {
-          const double yg = 0.5 * (double)s_y[k * kEnumBlock + tid];
-          a += ((x >> (U + k)) & 1u) ? -yg : yg;
+          const float yg = (float)s_y[k * kEnumBlock + tid];
+          a = fmaf(((xh >> k) & 1u) ? -0.5f : 0.5f, yg, a);
         }
-        const float fresh = valid ? (float)a : (float)G;
+        const float fresh = valid ? a : (float)G;
         drift = fmaxf(drift, fabsf((float)G - fresh));
         G = (V)fresh;
       }
@@ -468,29 +537,32 @@ __global__ __launch_bounds__(kEnumBlock, 8) void k_enum(
       }
     }
 
-    if (m <= fastThr) {
-      // re-walk of this block for the lanes whose bound passed, testing every
-      // state; the opaque copy keeps the compiler from holding the 64 values
-      // of the fast walk live across the branch
+    const bool pass = m <= fastThr;
+    if (__ballot(pass) != 0ull) {
+      // re-walk of this block, testing every state, for the lanes whose
+      // bound passed; the opaque copy keeps the compiler from holding the 64
+      // values of the fast walk live across the branch
       ++slow;
-      const V* q = s_q + (T & 1u) * kBlockSteps;
+      const uint32_t* q = qtab + (T & 1u) * kBlockSteps;
       V g2 = Gs;
       asm volatile("" : "+v"(g2));
       uint64_t hits = 0;
-      if (g2 + q[0] <= thrE) hits |= 1ull;
+      auto qv = [&](int i) -> V { return kInt ? (V)(int32_t)q[i] : (V)__uint_as_float(q[i]); };
+      if (g2 + qv(0) <= thrE) hits |= 1ull;
 #pragma unroll
       for (int i = 1; i < kBlockSteps; ++i) {
         const int f = __builtin_ctz(i);
         if (f == U - 1) g2 = g2 + W[f];
         else g2 = ((i >> (f + 1)) & 1) ? g2 + W[f] : g2 - W[f];
-        if (g2 + q[i] <= thrE) hits |= (1ull << i);
+        if (g2 + qv(i) <= thrE) hits |= (1ull << i);
       }
-      if (!valid) hits = 0;
+      if (!valid || !pass) hits = 0;
+      const uint64_t pl = ch.prefix_base + (uint64_t)lane;
       while (hits) {
         const int i = __builtin_ctzll(hits);
         hits &= hits - 1ull;
         const uint64_t t = ((uint64_t)T << U) | (uint64_t)i;
-        const uint64_t mask = (p << n) | (t ^ (t >> 1));
+        const uint64_t mask = (pl << n) | (t ^ (t >> 1));
         append_mask(mask, P, cand, cand_cap);
       }
     }
@@ -498,43 +570,59 @@ __global__ __launch_bounds__(kEnumBlock, 8) void k_enum(
 
   // statistics: one atomic per wave
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    slow += __shfl_xor(slow, o);
-    drift = fmaxf(drift, __shfl_xor(drift, o));
-  }
+  for (int o = 32; o > 0; o >>= 1) drift = fmaxf(drift, __shfl_xor(drift, o));
   if (__lane_id() == 0) {
     if (slow) atomicAdd(&P->stat_slow, (unsigned long long)slow);
-    if (!kInt && drift > 0.0f) atomicMax(&P->max_drift_bits, __float_as_uint(drift));
+    if (!kInt && drift > 0.0f) {
+      atomicMax(&P->max_drift_bits, __float_as_uint(drift));
+      // drift guard: the accumulated error must stay inside the margin
+      if (drift > P->margin) atomicOr(&P->err, kErrDrift);
+    }
   }
 }
 
 // Tiny instances (N < U): one thread per state, every state a candidate.
-__global__ void k_direct(int N, uint64_t lo, uint64_t hi, Params* P, uint64_t* cand,
-                         uint32_t cap) {
+__global__ void k_direct(Batch bt, uint64_t lo, uint64_t hi) {
   const uint64_t m = lo + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= hi) return;
+  Params* P = bt.P;
   const uint32_t slot = atomicAdd(&P->cand_count, 1u);
-  if (slot < cap) cand[slot] = m;
+  if (slot < bt.cap) bt.cand[slot] = m;
   else atomicOr(&P->err, kErrCapacity);
 }
 
-// ----------------------------------------------------------------- k_score
+// ------------------------------------------------- scoring and merging
 // Exact energy of each candidate (fp64 for float instances, rounded to fp32;
-// int32 for integer ones), kept if its key (E, mask) is below the S-th key of
-// the record.  Survivors are compacted into (skey, smask).
+// int32 for integer ones); it survives if its key (E, mask) is below the S-th
+// key of the record.
 
 template <bool kInt>
-__global__ void k_score(const void* Jv, const void* hv, int N, Params* P, const uint64_t* cand,
-                        uint32_t cap, uint32_t* skey, uint64_t* smask) {
-  extern __shared__ unsigned char s_raw[];
-  float* sJf = (float*)s_raw;
-  int32_t* sJi = (int32_t*)s_raw;
-  for (int k = threadIdx.x; k < N * N + N; k += blockDim.x) {
-    if (kInt) sJi[k] = k < N * N ? ((const int32_t*)Jv)[k] : ((const int32_t*)hv)[k - N * N];
-    else sJf[k] = k < N * N ? ((const float*)Jv)[k] : ((const float*)hv)[k - N * N];
-  }
+__device__ inline uint32_t exact_key(const void* Js, const void* hs, int N, int ld, uint64_t m) {
+  if (kInt) return key_of_i32(energy_i32((const int32_t*)Js, (const int32_t*)hs, N, ld, m));
+  return key_f32((float)energy_f64((const float*)Js, (const float*)hs, N, ld, m));
+}
+
+// Stage instance b's J (N x N, stride N) and h into LDS.
+template <bool kInt>
+__device__ inline void stage_instance(const Batch& bt, int b, int N, uint32_t* s) {
+  const uint32_t* Jb = (const uint32_t*)bt.J + (size_t)b * bt.ld * bt.ld;
+  const uint32_t* hb = (const uint32_t*)bt.h + (size_t)b * bt.ld;
+  for (int k = threadIdx.x; k < N * N + N; k += blockDim.x)
+    s[k] = k < N * N ? Jb[(k / N) * bt.ld + (k % N)] : hb[k - N * N];
+}
+
+// Single instance: grid-stride over the candidates of instance b.
+template <bool kInt>
+__global__ void k_score(Batch bt, int b) {
+  extern __shared__ uint32_t s_inst[];
+  const int N = inst_N(bt, b);
+  stage_instance<kInt>(bt, b, N, s_inst);
   __syncthreads();
-  const uint32_t cnt = min(P->cand_count, cap);
+  Params* P = bt.P + b;
+  const uint64_t* cand = bt.cand + (size_t)b * bt.cap;
+  uint32_t* skey = bt.skey + (size_t)b * bt.cap;
+  uint64_t* smask = bt.smask + (size_t)b * bt.cap;
+  const uint32_t cnt = min(P->cand_count, bt.cap);
   const uint32_t thr_key = P->thr_key;
   const uint64_t thr_mask = P->thr_mask;
   const bool full = P->rec_count != 0 && thr_key != 0xFFFFFFFFu;
@@ -547,8 +635,7 @@ __global__ void k_score(const void* Jv, const void* hv, int N, Params* P, const 
     uint32_t key = 0;
     if (j < cnt) {
       m = cand[j];
-      if (kInt) key = key_of_i32(energy_i32(sJi, sJi + N * N, N, m));
-      else key = key_f32((float)energy_f64(sJf, sJf + N * N, N, m));
+      key = exact_key<kInt>(s_inst, s_inst + N * N, N, N, m);
       keep = !full || key_less(key, m, thr_key, thr_mask);
     }
     if (keep) {
@@ -564,13 +651,6 @@ __global__ void k_score(const void* Jv, const void* hv, int N, Params* P, const 
     }
   }
 }
-
-// ----------------------------------------------------------------- k_merge
-// One workgroup of kMergeThreads.  Sorts the survivors by (key, mask) --
-// bitonic sort in LDS when they fit, in global memory otherwise -- then
-// merges them with the sorted record (rank of each element = its index plus
-// the number of smaller elements in the other list; keys are distinct because
-// masks are), keeps the first S, and publishes the S-th key as the threshold.
 
 __device__ inline void cmp_swap(uint32_t* k, uint64_t* m, uint32_t a, uint32_t b, bool asc) {
   const uint32_t ka = k[a], kb = k[b];
@@ -608,15 +688,15 @@ __device__ inline uint32_t rank_in(const uint32_t* k, const uint64_t* m, uint32_
   return lo;
 }
 
-__global__ __launch_bounds__(kMergeThreads) void k_merge(Params* P, int S, uint32_t cap,
-                                                         uint32_t* skey, uint64_t* smask,
-                                                         uint32_t* rkey, uint64_t* rmask,
-                                                         uint32_t* tkey, uint64_t* tmask) {
-  __shared__ uint32_t l_key[kLdsSortCap];
-  __shared__ uint64_t l_mask[kLdsSortCap];
-  const uint32_t ns = P->surv_count;
+// The whole workgroup: sort the ns survivors (skey, smask) -- bitonic sort
+// in LDS when they fit, in global memory otherwise -- and merge them with
+// the sorted record (rank of an element = its index plus the number of
+// smaller elements in the other list; keys are distinct because masks are),
+// keeping the first S; publish the S-th key as the threshold.
+__device__ void merge_body(Params* P, int S, uint32_t cap, uint32_t ns, uint32_t* skey,
+                           uint64_t* smask, uint32_t* rkey, uint64_t* rmask, uint32_t* tkey,
+                           uint64_t* tmask, uint32_t* l_key, uint64_t* l_mask) {
   const uint32_t rn = P->rec_count;
-  const uint32_t cc = P->cand_count;
   __syncthreads();
   if (ns > 0) {
     uint32_t P2 = 1;
@@ -631,7 +711,7 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge(Params* P, int S, uint3
       ks = l_key;
       ms = l_mask;
     } else {
-      for (uint32_t t = ns + threadIdx.x; t < P2; t += blockDim.x) {
+      for (uint32_t t = ns + threadIdx.x; t < P2 && t < cap; t += blockDim.x) {
         skey[t] = 0xFFFFFFFFu;
         smask[t] = ~0ull;
       }
@@ -645,9 +725,9 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge(Params* P, int S, uint3
       const uint32_t r = a + rank_in(ks, ms, ns, rkey[a], rmask[a]);
       if (r < nn) { tkey[r] = rkey[a]; tmask[r] = rmask[a]; }
     }
-    for (uint32_t b = threadIdx.x; b < ns; b += blockDim.x) {
-      const uint32_t r = b + rank_in(rkey, rmask, rn, ks[b], ms[b]);
-      if (r < nn) { tkey[r] = ks[b]; tmask[r] = ms[b]; }
+    for (uint32_t c = threadIdx.x; c < ns; c += blockDim.x) {
+      const uint32_t r = c + rank_in(rkey, rmask, rn, ks[c], ms[c]);
+      if (r < nn) { tkey[r] = ks[c]; tmask[r] = ms[c]; }
     }
     __syncthreads();
     for (uint32_t a = threadIdx.x; a < nn; a += blockDim.x) {
@@ -664,97 +744,155 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge(Params* P, int S, uint3
     }
   }
   if (threadIdx.x == 0) {
+    const uint32_t cc = P->cand_count;
     if (cc > cap) P->err |= kErrCapacity;
     P->stat_candidates += cc;
+    P->max_chunk_cand = max(P->max_chunk_cand, cc);
     P->cand_count = 0;
     P->surv_count = 0;
   }
 }
 
+// Single instance: one workgroup merges the survivors k_score left.
+__global__ __launch_bounds__(kMergeThreads) void k_merge(Batch bt, int b) {
+  __shared__ uint32_t l_key[kLdsSortCap];
+  __shared__ uint64_t l_mask[kLdsSortCap];
+  Params* P = bt.P + b;
+  const uint32_t ns = P->surv_count;
+  merge_body(P, bt.S, bt.cap, ns, bt.skey + (size_t)b * bt.cap, bt.smask + (size_t)b * bt.cap,
+             bt.rkey + (size_t)b * bt.S, bt.rmask + (size_t)b * bt.S,
+             bt.tkey + (size_t)b * bt.S, bt.tmask + (size_t)b * bt.S, l_key, l_mask);
+}
+
+// Batch: one workgroup per instance scores its own candidates of the chunk
+// starting at first_mask, then merges the survivors into its record.
+template <bool kInt>
+__global__ __launch_bounds__(kMergeBatchThreads) void k_merge_batched(Batch bt,
+                                                                      uint64_t first_mask) {
+  __shared__ uint32_t l_key[kLdsSortCap];
+  __shared__ uint64_t l_mask[kLdsSortCap];
+  __shared__ uint32_t s_inst[kMaxN * kMaxN + kMaxN];
+  __shared__ uint32_t s_ns;
+  const int b = blockIdx.x;
+  const int N = inst_N(bt, b);
+  if (N < kU || N > bt.ld || (N < 63 && first_mask >= (1ull << N))) return;
+  Params* P = bt.P + b;
+  stage_instance<kInt>(bt, b, N, s_inst);
+  if (threadIdx.x == 0) s_ns = 0;
+  __syncthreads();
+  const uint64_t* cand = bt.cand + (size_t)b * bt.cap;
+  uint32_t* skey = bt.skey + (size_t)b * bt.cap;
+  uint64_t* smask = bt.smask + (size_t)b * bt.cap;
+  const uint32_t cnt = min(P->cand_count, bt.cap);
+  const uint32_t thr_key = P->thr_key;
+  const uint64_t thr_mask = P->thr_mask;
+  const bool full = P->rec_count != 0 && thr_key != 0xFFFFFFFFu;
+  for (uint32_t j = threadIdx.x; j < cnt; j += blockDim.x) {
+    const uint64_t m = cand[j];
+    const uint32_t key = exact_key<kInt>(s_inst, s_inst + N * N, N, N, m);
+    if (!full || key_less(key, m, thr_key, thr_mask)) {
+      const uint32_t slot = atomicAdd(&s_ns, 1u);
+      skey[slot] = key;
+      smask[slot] = m;
+    }
+  }
+  __syncthreads();
+  const uint32_t ns = s_ns;
+  merge_body(P, bt.S, bt.cap, ns, skey, smask, bt.rkey + (size_t)b * bt.S,
+             bt.rmask + (size_t)b * bt.S, bt.tkey + (size_t)b * bt.S,
+             bt.tmask + (size_t)b * bt.S, l_key, l_mask);
+}
+
 // -------------------------------------------------------------- k_finalize
+// grid.y indexes the instance; outputs are [B][S].
 
 template <bool kInt>
-__global__ void k_finalize(const Params* P, int S, const uint32_t* rkey, const uint64_t* rmask,
-                           uint64_t* states_out, void* energies_out, uint32_t* sticky) {
+__global__ void k_finalize(Batch bt, uint64_t* states_out, void* energies_out) {
+  const int b = blockIdx.y;
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k == 0) atomicOr(sticky, P->err);
-  if (k >= S) return;
+  const Params* P = bt.P + b;
+  if (k == 0) atomicOr(bt.sticky, P->err);
+  if (k >= bt.S) return;
+  const size_t o = (size_t)b * bt.S + k;
   const bool have = (uint32_t)k < P->rec_count;
-  states_out[k] = have ? rmask[k] : ~0ull;
-  if (kInt) ((int32_t*)energies_out)[k] = have ? i32_of_key(rkey[k]) : 0;
-  else ((float*)energies_out)[k] = have ? __uint_as_float(bits_of_f32_key(rkey[k])) : 0.0f;
+  const uint32_t key = have ? bt.rkey[(size_t)b * bt.S + k] : 0u;
+  states_out[o] = have ? bt.rmask[(size_t)b * bt.S + k] : ~0ull;
+  if (kInt) ((int32_t*)energies_out)[o] = have ? i32_of_key(key) : 0;
+  else ((float*)energies_out)[o] = have ? __uint_as_float(bits_of_f32_key(key)) : 0.0f;
 }
 
 // ---------------------------------------------------------------- launchers
 
-hipError_t launch_prep(bool isint, const void* J, const void* h, int N, int S, Params* P,
-                       uint32_t* qtab, hipStream_t st) {
-  if (isint) hipLaunchKernelGGL(k_prep<true>, dim3(1), dim3(256), 0, st, J, h, N, S, P, qtab);
-  else hipLaunchKernelGGL(k_prep<false>, dim3(1), dim3(256), 0, st, J, h, N, S, P, qtab);
+hipError_t launch_prep(bool isint, const Batch& bt, hipStream_t st) {
+  if (isint) hipLaunchKernelGGL(k_prep<true>, dim3(bt.B), dim3(256), 0, st, bt);
+  else hipLaunchKernelGGL(k_prep<false>, dim3(bt.B), dim3(256), 0, st, bt);
   return hipGetLastError();
 }
 
-hipError_t launch_tables(bool isint, const void* J, const void* h, int N, int nmax,
-                         uint32_t* table, hipStream_t st) {
-  const int64_t total = ((int64_t)1 << (nmax - kU + 1)) - 1;
-  const dim3 grid((unsigned)((total + 255) / 256));
-  if (isint) hipLaunchKernelGGL(k_tables<true>, grid, dim3(256), 0, st, J, h, N, nmax, table);
-  else hipLaunchKernelGGL(k_tables<false>, grid, dim3(256), 0, st, J, h, N, nmax, table);
+hipError_t launch_tables(bool isint, const Batch& bt, int ncap, hipStream_t st) {
+  const int64_t total = ((int64_t)1 << (ncap - kU + 1)) - 1;
+  const dim3 grid((unsigned)((total + 255) / 256), (unsigned)bt.B);
+  if (isint) hipLaunchKernelGGL((k_tables<true, false>), grid, dim3(256), 0, st, bt, ncap, nullptr);
+  else hipLaunchKernelGGL((k_tables<false, false>), grid, dim3(256), 0, st, bt, ncap, nullptr);
   return hipGetLastError();
 }
 
-hipError_t launch_enum(bool isint, const void* J, const void* h, int N, const Chunk& ch,
-                       const uint32_t* table, const uint32_t* qtab, Params* P, uint64_t* cand,
-                       uint32_t cap, hipStream_t st) {
-  const dim3 grid((unsigned)((ch.lanes + kEnumBlock - 1) / kEnumBlock));
+// fp64 records (8 doubles each) of an fp32 batch, for the log Z walk.
+hipError_t launch_tables64(const Batch& bt, int ncap, double* out, hipStream_t st) {
+  const int64_t total = ((int64_t)1 << (ncap - kU + 1)) - 1;
+  const dim3 grid((unsigned)((total + 255) / 256), (unsigned)bt.B);
+  hipLaunchKernelGGL((k_tables<false, true>), grid, dim3(256), 0, st, bt, ncap, (void*)out);
+  return hipGetLastError();
+}
+
+hipError_t launch_enum(bool isint, const Batch& bt, const Chunk& ch, int ninst, hipStream_t st) {
+  const int bpi = (int)((ch.lanes + kEnumBlock - 1) / kEnumBlock);
+  const dim3 grid((unsigned)((int64_t)bpi * ninst));
   if (isint)
-    hipLaunchKernelGGL(k_enum<true>, grid, dim3(kEnumBlock), 0, st, J, h, N, ch, table, qtab, P,
-                       cand, cap);
+    hipLaunchKernelGGL(k_enum<true>, grid, dim3(kEnumBlock), 0, st, bt, bt.J, bt.h,
+                       (const uint32_t*)bt.table, (const uint32_t*)bt.qtab, ch, bpi);
   else
-    hipLaunchKernelGGL(k_enum<false>, grid, dim3(kEnumBlock), 0, st, J, h, N, ch, table, qtab,
-                       P, cand, cap);
+    hipLaunchKernelGGL(k_enum<false>, grid, dim3(kEnumBlock), 0, st, bt, bt.J, bt.h,
+                       (const uint32_t*)bt.table, (const uint32_t*)bt.qtab, ch, bpi);
   return hipGetLastError();
 }
 
-hipError_t launch_direct(int N, uint64_t lo, uint64_t hi, Params* P, uint64_t* cand, uint32_t cap,
-                         hipStream_t st) {
+hipError_t launch_direct(const Batch& bt, uint64_t lo, uint64_t hi, hipStream_t st) {
   const uint64_t cnt = hi - lo;
-  hipLaunchKernelGGL(k_direct, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, N, lo, hi,
-                     P, cand, cap);
+  hipLaunchKernelGGL(k_direct, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, bt, lo, hi);
   return hipGetLastError();
 }
 
-hipError_t launch_score(bool isint, const void* J, const void* h, int N, Params* P,
-                        const uint64_t* cand, uint32_t cap, uint32_t* skey, uint64_t* smask,
-                        int grid, hipStream_t st) {
+hipError_t launch_score(bool isint, const Batch& bt, int b, int grid, int N, hipStream_t st) {
   const size_t shm = (size_t)(N * N + N) * 4;
-  if (isint)
-    hipLaunchKernelGGL(k_score<true>, dim3(grid), dim3(256), shm, st, J, h, N, P, cand, cap, skey,
-                       smask);
-  else
-    hipLaunchKernelGGL(k_score<false>, dim3(grid), dim3(256), shm, st, J, h, N, P, cand, cap,
-                       skey, smask);
+  if (isint) hipLaunchKernelGGL(k_score<true>, dim3(grid), dim3(256), shm, st, bt, b);
+  else hipLaunchKernelGGL(k_score<false>, dim3(grid), dim3(256), shm, st, bt, b);
   return hipGetLastError();
 }
 
-hipError_t launch_merge(Params* P, int S, uint32_t cap, uint32_t* skey, uint64_t* smask,
-                        uint32_t* rkey, uint64_t* rmask, uint32_t* tkey, uint64_t* tmask,
-                        hipStream_t st) {
-  hipLaunchKernelGGL(k_merge, dim3(1), dim3(kMergeThreads), 0, st, P, S, cap, skey, smask, rkey,
-                     rmask, tkey, tmask);
+hipError_t launch_merge(const Batch& bt, int b, hipStream_t st) {
+  hipLaunchKernelGGL(k_merge, dim3(1), dim3(kMergeThreads), 0, st, bt, b);
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(bool isint, const Params* P, int S, const uint32_t* rkey,
-                           const uint64_t* rmask, uint64_t* states_out, void* energies_out,
-                           uint32_t* sticky, hipStream_t st) {
-  const dim3 grid((unsigned)((S + 255) / 256));
+hipError_t launch_merge_batched(bool isint, const Batch& bt, uint64_t first_mask,
+                                hipStream_t st) {
   if (isint)
-    hipLaunchKernelGGL(k_finalize<true>, grid, dim3(256), 0, st, P, S, rkey, rmask, states_out,
-                       energies_out, sticky);
+    hipLaunchKernelGGL(k_merge_batched<true>, dim3(bt.B), dim3(kMergeBatchThreads), 0, st, bt,
+                       first_mask);
   else
-    hipLaunchKernelGGL(k_finalize<false>, grid, dim3(256), 0, st, P, S, rkey, rmask, states_out,
-                       energies_out, sticky);
+    hipLaunchKernelGGL(k_merge_batched<false>, dim3(bt.B), dim3(kMergeBatchThreads), 0, st, bt,
+                       first_mask);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(bool isint, const Batch& bt, uint64_t* states_out, void* energies_out,
+                           hipStream_t st) {
+  const dim3 grid((unsigned)((bt.S + 255) / 256), (unsigned)bt.B);
+  if (isint)
+    hipLaunchKernelGGL(k_finalize<true>, grid, dim3(256), 0, st, bt, states_out, energies_out);
+  else
+    hipLaunchKernelGGL(k_finalize<false>, grid, dim3(256), 0, st, bt, states_out, energies_out);
   return hipGetLastError();
 }
 

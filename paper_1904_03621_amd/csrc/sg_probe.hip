@@ -1,0 +1,105 @@
+// sg_probe.hip -- VALU issue-rate probe: the measured denominator of the
+// enumeration kernel's roofline.  Each lane runs long chains of one VALU
+// instruction kind over 8 independent accumulators (inline asm, so the
+// compiler cannot fold or reorder them); the rate is lane-instructions per
+// second over a grid that fills every SIMD.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sg {
+
+constexpr int kProbeIters = 4096;
+constexpr int kProbeThreads = 256;
+
+// Instruction kinds measured (one asm template each; %0 accumulates, %1 and
+// %2 are loop-invariant operands).
+#define SG_PROBE_OPS(X)                                 \
+  X(0, "v_add_f32 %0, %0, %1")                          \
+  X(1, "v_min3_f32 %0, %0, %1, %2")                     \
+  X(2, "v_add_u32 %0, %0, %1")                          \
+  X(3, "v_min3_i32 %0, %0, %1, %2")                     \
+  X(4, "v_fma_f32 %0, %0, %1, %2")                      \
+  X(5, "v_min_f32 %0, %0, %1")                          \
+  X(6, "v_or_b32 %0, %0, %1")                           \
+  X(7, "v_or3_b32 %0, %0, %1, %2")                      \
+  X(8, "v_add3_u32 %0, %0, %1, %2")                     \
+  X(9, "v_max3_f32 %0, %0, %1, %2")                     \
+  X(10, "v_min_i32 %0, %0, %1")                         \
+  X(11, "v_sub_f32 %0, %1, %0")                         \
+  X(12, "v_and_or_b32 %0, %0, %1, %2")                  \
+  X(13, "v_med3_f32 %0, %0, %1, %2")
+
+template <int kOp>
+__global__ __launch_bounds__(kProbeThreads) void k_probe(uint32_t seed, uint32_t* out) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t a0 = t ^ seed, a1 = a0 + 1, a2 = a0 + 2, a3 = a0 + 3, a4 = a0 + 4, a5 = a0 + 5,
+           a6 = a0 + 6, a7 = a0 + 7;
+  // small positive float bit patterns keep the float chains finite
+  a0 = 0x3f800000u | (a0 & 0xffu); a1 = 0x3f800000u | (a1 & 0xffu);
+  a2 = 0x3f800000u | (a2 & 0xffu); a3 = 0x3f800000u | (a3 & 0xffu);
+  a4 = 0x3f800000u | (a4 & 0xffu); a5 = 0x3f800000u | (a5 & 0xffu);
+  a6 = 0x3f800000u | (a6 & 0xffu); a7 = 0x3f800000u | (a7 & 0xffu);
+  const uint32_t b = 0x33800000u + (seed & 7u), c = 0x34400000u + (seed & 3u);
+  for (int it = 0; it < kProbeIters; ++it) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (false) {}
+#define ONE(code, str) \
+      else if (kOp == code) { \
+        asm volatile(str : "+v"(a0) : "v"(b), "v"(c)); asm volatile(str : "+v"(a1) : "v"(b), "v"(c)); \
+        asm volatile(str : "+v"(a2) : "v"(b), "v"(c)); asm volatile(str : "+v"(a3) : "v"(b), "v"(c)); \
+        asm volatile(str : "+v"(a4) : "v"(b), "v"(c)); asm volatile(str : "+v"(a5) : "v"(b), "v"(c)); \
+        asm volatile(str : "+v"(a6) : "v"(b), "v"(c)); asm volatile(str : "+v"(a7) : "v"(b), "v"(c)); }
+      SG_PROBE_OPS(ONE)
+#undef ONE
+    }
+  }
+  const uint32_t x = a0 ^ a1 ^ a2 ^ a3 ^ a4 ^ a5 ^ a6 ^ a7;
+  if (x == 0x12345678u) out[0] = t;  // keeps the chains live
+}
+
+// Lane-instructions per second of instruction kind `op` (SG_PROBE_OPS), over
+// `waves_per_simd` resident waves per SIMD on every CU.  Returns < 0 on error.
+double probe_valu(int op, int waves_per_simd) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return -1.0;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return -1.0;
+  const int blocks = prop.multiProcessorCount * 4 * waves_per_simd * 64 / kProbeThreads;
+  uint32_t* out = nullptr;
+  if (hipMalloc(&out, sizeof(uint32_t)) != hipSuccess) return -1.0;
+  hipStream_t st;
+  if (hipStreamCreate(&st) != hipSuccess) return -1.0;
+  hipEvent_t a, b;
+  (void)hipEventCreate(&a);
+  (void)hipEventCreate(&b);
+  auto launch = [&](uint32_t seed) {
+    switch (op) {
+#define L(code, str)                                                                       \
+  case code:                                                                              \
+    hipLaunchKernelGGL(k_probe<code>, dim3(blocks), dim3(kProbeThreads), 0, st, seed, out); \
+    break;
+      SG_PROBE_OPS(L)
+#undef L
+      default: break;
+    }
+  };
+  launch(1u);  // warm-up
+  (void)hipEventRecord(a, st);
+  for (int r = 0; r < 4; ++r) launch(2u + r);
+  (void)hipEventRecord(b, st);
+  double rate = -1.0;
+  if (hipEventSynchronize(b) == hipSuccess) {
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, a, b);
+    const double lane_ops = 4.0 * (double)blocks * kProbeThreads * kProbeIters * 4 * 8;
+    rate = ms > 0.0f ? lane_ops / (ms * 1e-3) : -1.0;
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  (void)hipStreamDestroy(st);
+  (void)hipFree(out);
+  return rate;
+}
+
+}  // namespace sg

@@ -1,0 +1,125 @@
+"""Batched search: every instance of a batch against the CPU oracle and bit for
+bit against the single-instance search, at small sizes, at the 4096-instance
+workload shape, and replayed from a captured HIP graph."""
+
+import numpy as np
+import pytest
+
+import instances as I
+from parity import check_f32, check_int
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU test run without a GPU"
+    return torch
+
+
+def make_batch(B, lo, hi, seed, isint, Nmax=None):
+    rng = np.random.default_rng(seed)
+    Ns = rng.integers(lo, hi + 1, size=B).astype(np.int32)
+    Nmax = Nmax or hi
+    dt = np.int32 if isint else np.float32
+    J = np.zeros((B, Nmax, Nmax), dtype=dt)
+    h = np.zeros((B, Nmax), dtype=dt)
+    for b in range(B):
+        n = int(Ns[b])
+        if isint:
+            Jb, hb = I.random_int_dense(n, 1000 + seed * 7919 + b)
+        else:
+            Jb, hb = I.random_f32_dense(n, 1000 + seed * 7919 + b, j_scale=1.0, h_scale=0.1)
+        J[b, :n, :n] = Jb
+        h[b, :n] = hb
+    return Ns, J, h
+
+
+def run_batched(torch, Ns, J, h, S):
+    import paper_1904_03621_amd as sg
+    m, e = sg.low_spectrum_batched(torch.from_numpy(Ns).cuda(), torch.from_numpy(J).cuda(),
+                                   torch.from_numpy(h).cuda(), S)
+    return m.cpu().numpy().astype(np.uint64), e.cpu().numpy()
+
+
+def run_single(torch, J, h, S):
+    import paper_1904_03621_amd as sg
+    m, e = sg.low_spectrum(torch.from_numpy(np.ascontiguousarray(J)).cuda(),
+                           torch.from_numpy(np.ascontiguousarray(h)).cuda(), S)
+    return m.cpu().numpy().astype(np.uint64), e.cpu().numpy()
+
+
+@pytest.mark.parametrize("isint", [True, False])
+def test_small_batch_vs_oracle_and_single(orc, torch_dev, isint):
+    B, S = 40, 32
+    Ns, J, h = make_batch(B, 6, 20, 3, isint)
+    bm, be = run_batched(torch_dev, Ns, J, h, S)
+    for b in range(B):
+        n = int(Ns[b])
+        Jb, hb = J[b, :n, :n], h[b, :n]
+        S_b = min(S, 1 << n)
+        om, oe = orc.low_spectrum(Jb, hb, S_b)
+        if isint:
+            check_int(bm[b, :S_b], be[b, :S_b], om, oe, "batch %d (N=%d)" % (b, n))
+        else:
+            check_f32(n, Jb, bm[b, :S_b], be[b, :S_b], om, oe,
+                      lambda x: orc.energy(Jb, hb, x), "batch %d (N=%d)" % (b, n))
+        sm, se = run_single(torch_dev, Jb, hb, S_b)
+        assert np.array_equal(sm, bm[b, :S_b]) and np.array_equal(se, be[b, :S_b])
+
+
+def test_workload_shape_matches_single(orc, torch_dev):
+    """N uniform in [16, 26] (the 4096-instance workload's distribution, cut at
+    26 to keep the per-instance loop short), fp32, unscaled couplings, S = 64."""
+    B, S = 256, 64
+    Ns, J, h = make_batch(B, 16, 26, 4, False, Nmax=32)
+    bm, be = run_batched(torch_dev, Ns, J, h, S)
+    for b in range(B):
+        n = int(Ns[b])
+        sm, se = run_single(torch_dev, J[b, :n, :n], h[b, :n], S)
+        assert np.array_equal(sm, bm[b]) and np.array_equal(se, be[b]), "instance %d" % b
+    for b in range(0, B, 37):
+        n = int(Ns[b])
+        om, oe = orc.low_spectrum(J[b, :n, :n], h[b, :n], S)
+        check_f32(n, J[b, :n, :n], bm[b], be[b], om, oe,
+                  lambda x: orc.energy(J[b, :n, :n], h[b, :n], x), "oracle %d" % b)
+
+
+def test_graph_replay(torch_dev):
+    import paper_1904_03621_amd as sg
+    torch = torch_dev
+    B, S = 64, 16
+    Ns, J, h = make_batch(B, 10, 22, 5, False)
+    Nt, Jt, ht = (torch.from_numpy(x).cuda() for x in (Ns, J, h))
+    m0, e0 = sg.low_spectrum_batched(Nt, Jt, ht, S)  # eager: sizes the workspace
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(stream):
+        m_out = torch.empty((B, S), dtype=torch.int64, device="cuda")
+        e_out = torch.empty((B, S), dtype=torch.float32, device="cuda")
+        sg.low_spectrum_batched(Nt, Jt, ht, S)  # same stream, eager, before capture
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=stream):
+            st = sg.sg_low_spectrum_batched_f32(B, Nt, J.shape[1], Jt, ht, S, m_out, e_out,
+                                                stream)
+        assert st == 0
+    for rep in range(3):
+        m_out.fill_(0)
+        e_out.fill_(0)
+        _ = torch.randn(1000, device="cuda").sum()  # unrelated eager work between replays
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(m_out, m0) and torch.equal(e_out, e0), "replay %d differs" % rep
+    assert sg.sg_get_error(stream) == 0
+
+
+def test_bad_instance_size_reported(torch_dev):
+    import paper_1904_03621_amd as sg
+    from paper_1904_03621_amd import _lib
+    Ns, J, h = make_batch(4, 8, 12, 6, True)
+    Ns[2] = 3  # below 6
+    with pytest.raises(sg.SgError) as ei:
+        run_batched(torch_dev, Ns, J, h, 8)
+    assert ei.value.status == _lib.SG_EINVAL

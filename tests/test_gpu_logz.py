@@ -1,0 +1,247 @@
+"""log Z(beta) forward and backward on the GPU against the CPU oracle, closed
+forms and central finite differences; the 256 x N = 28 workload shape checked
+on a sampled instance and through the identity that ties the gradients to the
+beta-derivative of log Z.
+
+Tolerances: log Z within 1e-6 relative; gradients within 1e-5 of the largest
+gradient entry of the instance (element-wise relative error is meaningless for
+entries that vanish)."""
+
+import numpy as np
+import pytest
+
+import instances as I
+
+pytestmark = pytest.mark.gpu
+
+BETAS = [0.5, 1.0, 2.0]
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU test run without a GPU"
+    return torch
+
+
+def to_dev(torch, *arrs):
+    return [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in arrs]
+
+
+def gpu_forward(torch, J, h, betas, S):
+    import paper_1904_03621_amd as sg
+    Jt, ht, bt = to_dev(torch, J, h, np.asarray(betas, dtype=np.float32))
+    lz, e0, m, e = sg.logz_forward(Jt, ht, bt, S)
+    return lz.cpu().numpy(), e0.cpu().numpy(), m.cpu().numpy().astype(np.uint64), e.cpu().numpy()
+
+
+def gpu_backward(torch, J, h, betas, g, S=1):
+    import paper_1904_03621_amd as sg
+    Jt, ht, bt = to_dev(torch, J, h, np.asarray(betas, dtype=np.float32))
+    lz, e0, _, _ = sg.logz_forward(Jt, ht, bt, S)
+    gt = torch.from_numpy(np.asarray(g, dtype=np.float64)).cuda()
+    gJ, gh = sg.logz_backward(Jt, ht, bt, e0, lz, gt)
+    return gJ.cpu().numpy().astype(np.float64), gh.cpu().numpy().astype(np.float64)
+
+
+def check_logz(lz, lz_ref, what):
+    err = np.abs(lz - lz_ref) / np.maximum(np.abs(lz_ref), 1e-300)
+    assert np.all(err <= 1e-6), "%s: log Z rel err %.3g\n%s\n%s" % (what, err.max(), lz, lz_ref)
+
+
+def check_grad(gJ, gh, gJ_ref, gh_ref, what):
+    N = len(gh)
+    iu = np.triu_indices(N, 1)
+    scale = max(np.abs(gJ_ref[iu]).max() if N > 1 else 0.0, np.abs(gh_ref).max(), 1e-30)
+    eJ = np.abs(gJ[iu] - gJ_ref[iu]).max() / scale if N > 1 else 0.0
+    eh = np.abs(gh - gh_ref).max() / scale
+    assert eJ <= 1e-5 and eh <= 1e-5, "%s: grad err J %.3g h %.3g" % (what, eJ, eh)
+    low = np.tril_indices(N)
+    assert np.all(gJ[low] == 0.0), "%s: grad_J nonzero on or below the diagonal" % what
+
+
+@pytest.mark.parametrize("N", [6, 7, 9, 13, 14, 15, 17, 20])
+def test_forward_backward_vs_oracle(orc, torch_dev, N):
+    B = 3
+    J, h = I.logz_batch(B, N, 40 + N)
+    S = min(32, 1 << N)
+    lz, e0, m, e = gpu_forward(torch_dev, J, h, BETAS, S)
+    rng = np.random.default_rng(N)
+    g = rng.standard_normal((B, len(BETAS)))
+    gJ, gh = gpu_backward(torch_dev, J, h, BETAS, g, S)
+    for b in range(B):
+        lz_ref, e0_ref = orc.logz(J[b], h[b], BETAS)
+        check_logz(lz[b], lz_ref, "N=%d b=%d" % (N, b))
+        tau = 1e-5 * np.abs(np.triu(J[b].astype(np.float64), 1)).sum()
+        assert abs(e0[b] - e0_ref) <= tau and e0[b] == e[b, 0]
+        om, oe = orc.low_spectrum(J[b], h[b], S)
+        assert np.all(np.abs(e[b].astype(np.float64) - oe) <= tau)
+        gJ_ref, gh_ref = orc.logz_grad(J[b], h[b], BETAS, g[b])
+        check_grad(gJ[b], gh[b], gJ_ref, gh_ref, "N=%d b=%d" % (N, b))
+
+
+def test_states_match_batched_search(torch_dev):
+    import paper_1904_03621_amd as sg
+    torch = torch_dev
+    B, N, S = 16, 18, 32
+    J, h = I.logz_batch(B, N, 7)
+    _, _, m, e = gpu_forward(torch, J, h, BETAS, S)
+    Ns = np.full(B, N, dtype=np.int32)
+    bm, be = sg.low_spectrum_batched(*to_dev(torch, Ns, J, h), S)
+    assert np.array_equal(m, bm.cpu().numpy().astype(np.uint64))
+    assert np.array_equal(e, be.cpu().numpy())
+
+
+def test_n22_batch(orc, torch_dev):
+    B, N = 2, 22
+    J, h = I.logz_batch(B, N, 22)
+    g = np.array([[1.0, -0.5, 0.25], [0.0, 1.0, 0.0]])
+    lz, _, _, _ = gpu_forward(torch_dev, J, h, BETAS, 32)
+    gJ, gh = gpu_backward(torch_dev, J, h, BETAS, g)
+    for b in range(B):
+        check_logz(lz[b], orc.logz(J[b], h[b], BETAS)[0], "N=22 b=%d" % b)
+        gJ_ref, gh_ref = orc.logz_grad(J[b], h[b], BETAS, g[b])
+        check_grad(gJ[b], gh[b], gJ_ref, gh_ref, "N=22 b=%d" % b)
+
+
+def test_free_spins_closed_form(torch_dev):
+    """J = 0: log Z = sum_i log(2 cosh(beta h_i)), <s_i> = tanh(beta h_i),
+    <s_i s_j> = tanh(beta h_i) tanh(beta h_j)."""
+    B, N = 2, 16
+    rng = np.random.default_rng(3)
+    J = np.zeros((B, N, N), dtype=np.float32)
+    h = (rng.standard_normal((B, N)) * 0.5).astype(np.float32)
+    lz, e0, _, _ = gpu_forward(torch_dev, J, h, BETAS, 8)
+    g = np.zeros((B, 3))
+    g[:, 1] = 1.0  # beta = 1
+    gJ, gh = gpu_backward(torch_dev, J, h, BETAS, g)
+    hd = h.astype(np.float64)
+    for b in range(B):
+        want = [np.sum(np.log(2.0 * np.cosh(bt * hd[b]))) for bt in BETAS]
+        check_logz(lz[b], np.array(want), "free b=%d" % b)
+        assert abs(e0[b] + np.abs(hd[b]).sum()) <= 1e-5
+        t = np.tanh(hd[b])
+        check_grad(gJ[b], gh[b], np.triu(np.outer(t, t), 1), t, "free b=%d" % b)
+
+
+def test_open_chain_transfer_matrix(torch_dev):
+    """Open chain (J_{i,i+1} only): log Z from 2 x 2 transfer matrices."""
+    N = 20
+    rng = np.random.default_rng(9)
+    J = np.zeros((1, N, N), dtype=np.float32)
+    for i in range(N - 1):
+        J[0, i, i + 1] = rng.standard_normal()
+    h = (rng.standard_normal((1, N)) * 0.3).astype(np.float32)
+    lz, _, _, _ = gpu_forward(torch_dev, J, h, BETAS, 4)
+    Jd, hd = J[0].astype(np.float64), h[0].astype(np.float64)
+    sv = np.array([-1.0, 1.0])
+    for k, bt in enumerate(BETAS):
+        v = np.exp(bt * hd[0] * sv)
+        logscale = 0.0
+        for i in range(1, N):
+            M = np.exp(bt * Jd[i - 1, i] * np.outer(sv, sv) + bt * hd[i] * sv[None, :])
+            v = v @ M
+            c = v.max()
+            v /= c
+            logscale += np.log(c)
+        want = logscale + np.log(v.sum())
+        check_logz(lz[0, k:k + 1], np.array([want]), "chain beta=%g" % bt)
+
+
+def test_gradient_vs_central_differences(orc, torch_dev):
+    """GPU gradient against central differences of the oracle's log Z."""
+    B, N = 1, 10
+    J, h = I.logz_batch(B, N, 17)
+    g = np.array([[0.3, 1.0, -0.7]])
+    gJ, gh = gpu_backward(torch_dev, J, h, BETAS, g)
+    Jd, hd = J[0].astype(np.float64), h[0].astype(np.float64)
+
+    def f(Jx, hx):
+        return float(np.dot(g[0], orc.logz(Jx, hx, BETAS)[0]))
+
+    d = 1e-4
+    for (i, j) in [(0, 1), (2, 7), (8, 9), (0, 9)]:
+        Jp, Jm = Jd.copy(), Jd.copy()
+        Jp[i, j] += d
+        Jm[i, j] -= d
+        fd = (f(Jp, hd) - f(Jm, hd)) / (2 * d)
+        assert abs(gJ[0, i, j] - fd) <= 1e-5 * max(1.0, abs(fd)), (i, j, gJ[0, i, j], fd)
+    for i in [0, 4, 9]:
+        hp, hm = hd.copy(), hd.copy()
+        hp[i] += d
+        hm[i] -= d
+        fd = (f(Jd, hp) - f(Jd, hm)) / (2 * d)
+        assert abs(gh[0, i] - fd) <= 1e-5 * max(1.0, abs(fd)), (i, gh[0, i], fd)
+
+
+def test_autograd_function(orc, torch_dev):
+    import paper_1904_03621_amd as sg
+    torch = torch_dev
+    B, N = 2, 12
+    J, h = I.logz_batch(B, N, 5)
+    Jt, ht, bt = to_dev(torch, J, h, np.asarray(BETAS, dtype=np.float32))
+    Jt.requires_grad_(True)
+    ht.requires_grad_(True)
+    w = torch.tensor([[1.0, 2.0, -1.0], [0.5, 0.0, 1.5]], dtype=torch.float64, device="cuda")
+    lz, states, energies = sg.logz(Jt, ht, bt, 16)
+    assert lz.requires_grad and not states.requires_grad and not energies.requires_grad
+    (lz * w).sum().backward()
+    wn = w.cpu().numpy()
+    for b in range(B):
+        gJ_ref, gh_ref = orc.logz_grad(J[b], h[b], BETAS, wn[b])
+        check_grad(Jt.grad[b].cpu().numpy().astype(np.float64),
+                   ht.grad[b].cpu().numpy().astype(np.float64), gJ_ref, gh_ref, "autograd %d" % b)
+
+
+def test_workload_shape(orc, torch_dev):
+    """256 instances, N = 28, beta in {0.5, 1, 2}, S = 32.  Instance 0's log Z
+    against the oracle; for every instance, sum_{i<j} J_ij dlogZ/dJ_ij +
+    sum_i h_i dlogZ/dh_i = -beta <E> = beta dlogZ/dbeta, the beta-derivative
+    taken by central differences of the GPU forward."""
+    import paper_1904_03621_amd as sg
+    torch = torch_dev
+    B, N, S = 256, 28, 32
+    J, h = I.logz_batch(B, N, 2028)
+    Jt, ht = to_dev(torch, J, h)
+    bt = torch.tensor(BETAS, dtype=torch.float32, device="cuda")
+    lz, e0, m, e = sg.logz_forward(Jt, ht, bt, S)
+    lz = lz.cpu().numpy()
+    check_logz(lz[0], orc.logz(J[0], h[0], BETAS)[0], "N=28 b=0")
+    om, oe = orc.low_spectrum(J[0], h[0], S)
+    tau = 1e-5 * np.abs(J[0].astype(np.float64)).sum()
+    assert np.all(np.abs(e[0].cpu().numpy().astype(np.float64) - oe) <= tau)
+    k = 1  # beta = 1
+    g = torch.zeros((B, 3), dtype=torch.float64, device="cuda")
+    g[:, k] = 1.0
+    gJ, gh = sg.logz_backward(Jt, ht, bt, e0, torch.from_numpy(lz).cuda(), g)
+    lhs = ((gJ.double() * Jt.double()).sum(dim=(1, 2)) + (gh.double() * ht.double()).sum(dim=1))
+    lhs = lhs.cpu().numpy() / BETAS[k]
+    d = 1e-3
+    bpm = torch.tensor([BETAS[k] + d, BETAS[k] - d], dtype=torch.float32, device="cuda")
+    lzpm, _, _, _ = sg.logz_forward(Jt, ht, bpm, S)
+    lzpm = lzpm.cpu().numpy()
+    db = float(bpm[0].item()) - float(bpm[1].item())
+    fd = (lzpm[:, 0] - lzpm[:, 1]) / db
+    err = np.abs(lhs - fd) / np.maximum(np.abs(fd), 1.0)
+    assert err.max() <= 1e-4, err.max()
+
+
+def test_errors(torch_dev):
+    import paper_1904_03621_amd as sg
+    from paper_1904_03621_amd import _lib
+    torch = torch_dev
+    J, h = I.logz_batch(2, 10, 1)
+    Jt, ht = to_dev(torch, J, h)
+    with pytest.raises(sg.SgError) as ei:
+        sg.logz_forward(Jt, ht, torch.tensor([1.0, -1.0], device="cuda"), 4)
+    assert ei.value.status == _lib.SG_EINVAL
+    with pytest.raises(sg.SgError) as ei:
+        sg.logz_forward(Jt, ht, torch.ones(5, device="cuda"), 4)
+    assert ei.value.status == _lib.SG_EINVAL
+    J5, h5 = I.logz_batch(1, 5, 1)
+    with pytest.raises(sg.SgError) as ei:
+        sg.logz_forward(*to_dev(torch, J5, h5), torch.ones(1, device="cuda"), 4)
+    assert ei.value.status == _lib.SG_EINVAL
+    # the stream is clean again
+    lz, _, _, _ = sg.logz_forward(Jt, ht, torch.ones(1, device="cuda"), 4)
+    assert np.all(np.isfinite(lz.cpu().numpy()))

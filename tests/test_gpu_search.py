@@ -105,6 +105,25 @@ def test_ferromagnet_f32_exact_ties(orc, torch_dev):
     assert np.array_equal(m, om) and np.array_equal(e.astype(np.float64), oe)
 
 
+def test_exact_f32_degenerate(orc, torch_dev):
+    """fp32 instances whose arithmetic is exact (all values on one dyadic
+    grid) run with a zero margin and the integer tie rule: an all-zero
+    instance returns the S smallest masks, a dyadic one matches the oracle
+    bit for bit."""
+    N = 30
+    J = np.zeros((N, N), dtype=np.float32)
+    h = np.zeros(N, dtype=np.float32)
+    m, e = gpu_search(torch_dev, J, h, 100)
+    assert np.array_equal(m, np.arange(100, dtype=np.uint64)) and np.all(e == 0)
+    N = 22
+    rng = np.random.default_rng(33)
+    J = np.triu(rng.integers(-4, 5, size=(N, N)) * 0.25, 1).astype(np.float32)
+    h = (rng.integers(-4, 5, size=N) * 0.125).astype(np.float32)
+    m, e = gpu_search(torch_dev, J, h, 2000)
+    om, oe = orc.low_spectrum(J, h, 2000)
+    assert np.array_equal(m, om) and np.array_equal(e.astype(np.float64), oe)
+
+
 @pytest.mark.parametrize("isint", [True, False])
 def test_range_slices(orc, torch_dev, isint):
     N = 32
