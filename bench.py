@@ -28,6 +28,8 @@ SEED = 2
 PEAK_LANE_OPS = 256 * 128 * 2.4e9
 # algorithmic work per state: one accumulate and one order test
 OPS_PER_STATE = 2.0
+# size of the plain device copy that calibrates the HBM byte counters
+COPY_BYTES = 512 << 20
 
 
 def cpu_baseline(J, h, seconds_hint: float = 20.0) -> dict:
@@ -50,12 +52,142 @@ def cpu_baseline(J, h, seconds_hint: float = 20.0) -> dict:
             "S=%d, %.1f s" % (int(np.log2(M)), S_STATES, dt)}
 
 
+def _sync_time(torch, fn):
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    fn()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t
+
+
+def bench_batched(torch, sg, reps: int) -> dict:
+    """4096 instances, N_b uniform in [16, 32], J ~ N(0,1) fp32 (unscaled),
+    h ~ N(0, 0.1^2), S = 64: one batched call against one single-instance
+    call per instance (same stream, buffers allocated beforehand, no
+    per-instance synchronisation)."""
+    import instances as I
+    B, S = 4096, 64
+    Ns, J, h = I.batched_f32_dense(B, 4)
+    dev = torch.device("cuda:0")
+    Nt, Jt, ht = (torch.from_numpy(x).to(dev) for x in (Ns, J, h))
+    Nmax = J.shape[1]
+    stream = torch.cuda.current_stream()
+    bm = torch.empty((B, S), dtype=torch.int64, device=dev)
+    be = torch.empty((B, S), dtype=torch.float32, device=dev)
+
+    def batched():
+        st = sg.sg_low_spectrum_batched_f32(B, Nt, Nmax, Jt, ht, S, bm, be, stream)
+        if st != 0:
+            raise sg.SgError(st, "sg_low_spectrum_batched_f32", sg._lib.last_error())
+
+    Jb = [torch.from_numpy(np.ascontiguousarray(J[b, :Ns[b], :Ns[b]])).to(dev) for b in range(B)]
+    hb = [torch.from_numpy(np.ascontiguousarray(h[b, :Ns[b]])).to(dev) for b in range(B)]
+    sm = torch.empty((B, S), dtype=torch.int64, device=dev)
+    se = torch.empty((B, S), dtype=torch.float32, device=dev)
+
+    def per_instance():
+        for b in range(B):
+            st = sg.sg_low_spectrum_f32(int(Ns[b]), Jb[b], hb[b], S, sm[b], se[b], stream)
+            if st != 0:
+                raise sg.SgError(st, "sg_low_spectrum_f32", sg._lib.last_error())
+
+    batched()
+    per_instance()  # warm-up: workspaces sized
+    t_b = min(_sync_time(torch, batched) for _ in range(reps))
+    t_p = _sync_time(torch, per_instance)
+    err = sg.sg_get_error(stream)
+    if err != 0:
+        raise sg.SgError(err, "device", sg._lib.last_error())
+    identical = bool(torch.equal(bm, sm) and torch.equal(be, se))
+    states = float(np.sum(2.0 ** Ns.astype(np.float64)))
+    print("batched done", file=sys.stderr, flush=True)
+    return {"workload": "4096 dense fp32 instances, N_b uniform in [16,32], J ~ N(0,1), "
+                        "h ~ N(0,0.1^2), seed 4, S=64 each",
+            "value": states / t_b, "unit": "spin configs/s", "ms": t_b * 1e3,
+            "per_instance_ms": t_p * 1e3, "speedup": t_p / t_b, "identical": identical,
+            "states": states}
+
+
+def bench_logz(torch, sg, reps: int) -> dict:
+    """256 instances, N = 28, J ~ N(0,1)/sqrt(28), h ~ N(0, 0.2^2), beta in
+    {0.5, 1, 2}, S = 32: log Z forward + backward of the batch against one
+    forward + backward per instance."""
+    import instances as I
+    B, N, S = 256, 28, 32
+    J, h = I.logz_batch(B, N, 5)
+    dev = torch.device("cuda:0")
+    Jt, ht = (torch.from_numpy(x).to(dev) for x in (J, h))
+    beta = torch.tensor([0.5, 1.0, 2.0], dtype=torch.float32, device=dev)
+    K = 3
+    stream = torch.cuda.current_stream()
+    g = torch.ones((B, K), dtype=torch.float64, device=dev)
+    out = {}
+
+    def alloc(nb):
+        return (torch.empty((nb, K), dtype=torch.float64, device=dev),
+                torch.empty(nb, dtype=torch.float32, device=dev),
+                torch.empty((nb, S), dtype=torch.int64, device=dev),
+                torch.empty((nb, S), dtype=torch.float32, device=dev),
+                torch.empty((nb, N, N), dtype=torch.float32, device=dev),
+                torch.empty((nb, N), dtype=torch.float32, device=dev))
+
+    lz, e0, m, e, gJ, gh = alloc(B)
+
+    def fwd():
+        st = sg.sg_logz_forward_f32(B, N, Jt, ht, K, beta, S, lz, e0, m, e, stream)
+        if st != 0:
+            raise sg.SgError(st, "sg_logz_forward_f32", sg._lib.last_error())
+
+    def bwd():
+        st = sg.sg_logz_backward_f32(B, N, Jt, ht, K, beta, e0, lz, g, gJ, gh, stream)
+        if st != 0:
+            raise sg.SgError(st, "sg_logz_backward_f32", sg._lib.last_error())
+
+    lz1, e01, m1, e1, gJ1, gh1 = alloc(B)
+
+    def per_instance():
+        for b in range(B):
+            st = sg.sg_logz_forward_f32(1, N, Jt[b], ht[b], K, beta, S, lz1[b], e01[b], m1[b],
+                                        e1[b], stream)
+            if st == 0:
+                st = sg.sg_logz_backward_f32(1, N, Jt[b], ht[b], K, beta, e01[b], lz1[b], g[b],
+                                             gJ1[b], gh1[b], stream)
+            if st != 0:
+                raise sg.SgError(st, "sg_logz per instance", sg._lib.last_error())
+
+    fwd(); bwd(); per_instance()  # warm-up
+    t_f = min(_sync_time(torch, fwd) for _ in range(reps))
+    t_bw = min(_sync_time(torch, bwd) for _ in range(reps))
+    t_p = _sync_time(torch, per_instance)
+    err = sg.sg_get_error(stream)
+    if err != 0:
+        raise sg.SgError(err, "device", sg._lib.last_error())
+    rel_lz = float(((lz - lz1).abs() / lz1.abs()).max())
+    scale = torch.maximum(gJ1.abs().amax(dim=(1, 2)), gh1.abs().amax(dim=1))
+    rel_g = float(torch.maximum((gJ - gJ1).abs().amax(dim=(1, 2)),
+                                (gh - gh1).abs().amax(dim=1)).div(scale).max())
+    print("logz done", file=sys.stderr, flush=True)
+    out.update({"workload": "256 dense fp32 instances, N=28, J ~ N(0,1)/sqrt(28), "
+                            "h ~ N(0,0.2^2), seed 5, beta in {0.5,1,2}, S=32",
+                "value": B * 2.0 ** N / t_f, "unit": "spin configs/s (forward)",
+                "forward_ms": t_f * 1e3, "backward_ms": t_bw * 1e3,
+                "per_instance_ms": t_p * 1e3, "speedup": t_p / (t_f + t_bw),
+                "same_states": bool(torch.equal(m, m1) and torch.equal(e, e1)),
+                "max_rel_diff_logz": rel_lz, "max_rel_diff_grad": rel_g})
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extensions", action="store_true",
+                    help="skip the batched and log Z measurements")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="one search, then a plain 512 MiB device copy (the reference for "
+                         "scaling the FETCH_SIZE / WRITE_SIZE counters); prints nothing else")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -80,6 +212,17 @@ def main() -> int:
         st = sg.sg_low_spectrum_f32(N_SPINS, Jt, ht, S_STATES, states, energies, stream)
         if st != 0:
             raise sg.SgError(st, "sg_low_spectrum_f32", sg._lib.last_error())
+
+    if args.traffic_probe:
+        step()
+        torch.cuda.synchronize()
+        src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"traffic_probe": "done", "copy_bytes": COPY_BYTES}), flush=True)
+        return 0
 
     sg.sg_set_kernel_timing(True)
     for _ in range(args.warmup):
@@ -130,7 +273,7 @@ def main() -> int:
               and np.max(np.abs(eo - e)) <= tau)
 
     out = {
-        "metric": "spin configs evaluated/sec (N=48 dense, S=1000)",
+        "metric": "spin configs evaluated/sec (N=48 dense, S=1000); % VALU peak; batched speedup",
         "value": value,
         "unit": "spin configs/s",
         "n_gpus": 1,
@@ -151,6 +294,9 @@ def main() -> int:
         "run_info": {k: v for k, v in sg.sg_get_run_info(stream).items()
                      if k in ("chunks", "candidates", "slow_blocks", "margin", "max_drift")},
     }
+    if not args.no_extensions:
+        out["batched"] = bench_batched(torch, sg, 3)
+        out["logz"] = bench_logz(torch, sg, 3)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(J, h)
     print(json.dumps(out), flush=True)

@@ -190,6 +190,16 @@ sg_status sg_logz_backward_f32(int B, int N, const float *J, const float *h, int
                                const double *grad_logz, float *grad_J, float *grad_h,
                                void *stream);
 
+/*
+ * Sizes the library's workspace of (current device, stream) for every later
+ * call on that stream with B <= B_max, N <= N_max and S <= S_max (single,
+ * batched and log Z calls).  Calls within those limits then allocate nothing,
+ * so they can be captured into a HIP graph.  Synchronous; returns SG_EINVAL
+ * for out-of-range limits and SG_ENOMEM / SG_EHIP if allocation fails.  The
+ * workspace is owned by the library and lives until the process ends.
+ */
+sg_status sg_reserve(int B_max, int N_max, int S_max, void *stream);
+
 /* Waits for `stream`, then returns and clears the sticky device error of the
  * calls enqueued on it (SG_OK if none). */
 sg_status sg_get_error(void *stream);
@@ -211,6 +221,8 @@ typedef struct {
     double  enum_ms;         /* their summed duration (HIP events; 0 unless
                                 kernel timing is on)                          */
     int64_t max_chunk_candidates; /* most candidates one chunk produced       */
+    int64_t repeated_passes; /* chunks walked again because their candidates
+                                overflowed the buffer (instance 0)            */
 } sg_run_info;
 sg_status sg_get_run_info(void *stream, sg_run_info *out);
 

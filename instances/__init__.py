@@ -24,5 +24,5 @@ from .generators import (  # noqa: F401
     open_chain,
     listing1_dict,
     dict_to_dense,
-    config,
+    workload,
 )

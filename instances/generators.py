@@ -28,7 +28,7 @@ __all__ = [
     "random_int_dense", "random_f32_dense", "chimera_edges", "chimera_pm1",
     "batched_f32_dense", "logz_batch", "ferromagnet", "mattis",
     "free_spins_pow2_fields", "open_chain", "listing1_dict", "dict_to_dense",
-    "config",
+    "workload",
 ]
 
 
@@ -189,21 +189,26 @@ def dict_to_dense(graph: dict, N: int | None = None, dtype=np.float64):
     return J, h
 
 
-def config(name: str, seed: int | None = None):
-    """The five measured workloads, by name ("c1".."c5")."""
-    if name == "c1":
+def workload(name: str, seed: int | None = None):
+    """The measured workloads, by name:
+    "int24"       N=24 integer dense, S=100
+    "dense48"     N=48 fp32 dense, S=1000
+    "chimera48"   2x3-cell Chimera, J = +-1, h = 0, S=10000
+    "batch4096"   4096 fp32 dense instances, N_b in [16, 32], S=64
+    "logz256"     256 fp32 dense instances, N=28, beta in {0.5, 1, 2}, S=32"""
+    if name == "int24":
         J, h = random_int_dense(24, 1 if seed is None else seed)
         return dict(N=24, J=J, h=h, S=100)
-    if name == "c2":
+    if name == "dense48":
         J, h = random_f32_dense(48, 2 if seed is None else seed)
         return dict(N=48, J=J, h=h, S=1000)
-    if name == "c3":
+    if name == "chimera48":
         J, h = chimera_pm1(2, 3, 3 if seed is None else seed)
         return dict(N=48, J=J, h=h, S=10000)
-    if name == "c4":
+    if name == "batch4096":
         Ns, J, h = batched_f32_dense(4096, 4 if seed is None else seed)
         return dict(B=4096, Ns=Ns, J=J, h=h, S=64)
-    if name == "c5":
+    if name == "logz256":
         J, h = logz_batch(256, 28, 5 if seed is None else seed)
         return dict(B=256, N=28, J=J, h=h, S=32,
                     beta=np.array([0.5, 1.0, 2.0], dtype=np.float32))

@@ -29,7 +29,7 @@ EXPORTS = [
     "sg_low_spectrum_f32", "sg_low_spectrum_i32",
     "sg_low_spectrum_range_f32", "sg_low_spectrum_range_i32",
     "sg_low_spectrum_batched_f32", "sg_low_spectrum_batched_i32",
-    "sg_logz_forward_f32", "sg_logz_backward_f32",
+    "sg_logz_forward_f32", "sg_logz_backward_f32", "sg_reserve",
     "sg_get_error", "sg_last_error", "sg_get_run_info", "sg_debug_plan",
     "sg_set_kernel_timing", "sg_probe_valu",
 ]
@@ -57,6 +57,7 @@ class RunInfo(ctypes.Structure):
         ("enum_states", ctypes.c_double),
         ("enum_ms", ctypes.c_double),
         ("max_chunk_candidates", ctypes.c_int64),
+        ("repeated_passes", ctypes.c_int64),
     ]
 
     def as_dict(self):
@@ -92,6 +93,8 @@ def lib() -> ctypes.CDLL:
         L.sg_logz_forward_f32.argtypes = [i32, i32, vp, vp, i32, vp, i32, vp, vp, vp, vp, vp]
         L.sg_logz_backward_f32.restype = i32
         L.sg_logz_backward_f32.argtypes = [i32, i32, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]
+        L.sg_reserve.restype = i32
+        L.sg_reserve.argtypes = [i32, i32, i32, vp]
         L.sg_get_error.restype = i32
         L.sg_get_error.argtypes = [vp]
         L.sg_last_error.restype = ctypes.c_char_p
@@ -176,6 +179,10 @@ def sg_logz_backward_f32(B, N, J, h, n_beta, beta, e0, logz, grad_logz, grad_J, 
     return lib().sg_logz_backward_f32(B, N, _ptr(J), _ptr(h), n_beta, _ptr(beta), _ptr(e0),
                                       _ptr(logz), _ptr(grad_logz), _ptr(grad_J), _ptr(grad_h),
                                       _stream(stream))
+
+
+def sg_reserve(B_max, N_max, S_max, stream=None) -> int:
+    return lib().sg_reserve(B_max, N_max, S_max, _stream(stream))
 
 
 def sg_get_error(stream=None) -> int:

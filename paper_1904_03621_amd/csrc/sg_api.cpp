@@ -19,10 +19,11 @@ hipError_t launch_prep(bool isint, const Batch& bt, hipStream_t st);
 hipError_t launch_tables(bool isint, const Batch& bt, int ncap, hipStream_t st);
 hipError_t launch_enum(bool isint, const Batch& bt, const Chunk& ch, int ninst, hipStream_t st);
 hipError_t launch_direct(const Batch& bt, uint64_t lo, uint64_t hi, hipStream_t st);
-hipError_t launch_score(bool isint, const Batch& bt, int b, int grid, int N, hipStream_t st);
-hipError_t launch_merge(const Batch& bt, int b, hipStream_t st);
-hipError_t launch_merge_batched(bool isint, const Batch& bt, uint64_t first_mask,
-                                hipStream_t st);
+hipError_t launch_score(bool isint, const Batch& bt, int b, int grid, int N, int retry,
+                        hipStream_t st);
+hipError_t launch_merge(const Batch& bt, int b, int retry, bool last_pass, hipStream_t st);
+hipError_t launch_merge_batched(bool isint, const Batch& bt, uint64_t first_mask, int retry,
+                                bool last_pass, hipStream_t st);
 hipError_t launch_finalize(bool isint, const Batch& bt, uint64_t* states_out, void* energies_out,
                            hipStream_t st);
 int enum_occupancy(bool isint);
@@ -148,6 +149,7 @@ struct Workspace {
   int cus = 0;
   // last run
   int64_t last_chunks = 0;
+  int64_t last_launches = 0;  // enumeration launches of the last call
   int last_kmax = 0, last_nmax = 0;
   double last_states = 0.0;
   // kernel timing: one event pair per enumeration launch of the last call
@@ -175,6 +177,7 @@ std::map<std::pair<int, hipStream_t>, Workspace*> g_ws;
 
 constexpr uint32_t kCandCapMin = 1u << 22;     // single search
 constexpr uint32_t kBatchCandCapMin = 1u << 13;  // per instance of a batch
+constexpr uint64_t kBatchCandBudget = 1ull << 24;  // slots over the whole batch
 
 template <typename T>
 hipError_t grow(T** p, size_t* have, size_t need) {
@@ -304,6 +307,7 @@ hipError_t enum_timed(Workspace* w, bool isint, const Batch& bt, const Chunk& ch
   }
   hipError_t r = launch_enum(isint, bt, ch, ninst, st);
   if (r != hipSuccess) return r;
+  ++w->last_launches;
   if (g_timing) r = hipEventRecord(e1, st);
   return r;
 }
@@ -328,10 +332,11 @@ sg_status run_search(bool isint, int N, const void* J, const void* h, int S, uin
   int64_t nchunks = 0;
   int kmax = 0, nmaxu = 0;
   w->ev_used = 0;
+  w->last_launches = 0;
   if (N < kU) {
     HIP_TRY(launch_direct(bt, lo, hi, st));
-    HIP_TRY(launch_score(isint, bt, 0, score_grid, N, st));
-    HIP_TRY(launch_merge(bt, 0, st));
+    HIP_TRY(launch_score(isint, bt, 0, score_grid, N, 0, st));
+    HIP_TRY(launch_merge(bt, 0, 0, true, st));
     nchunks = 1;
     w->last_states = (double)(hi - lo);
   } else {
@@ -345,10 +350,17 @@ sg_status run_search(bool isint, int N, const void* J, const void* h, int S, uin
       ch.lanes = pc.lanes;
       ch.n = pc.n;
       ch.table_offset = (1 << (pc.n - kU)) - 1;
-      HIP_TRY(enum_timed(w, isint, bt, ch, 1, st));
-      states += (double)pc.lanes * (double)((uint64_t)1 << pc.n);
-      HIP_TRY(launch_score(isint, bt, 0, score_grid, N, st));
-      HIP_TRY(launch_merge(bt, 0, st));
+      // a chunk with more states than candidate slots may overflow: it gets
+      // up to kRetries repeated passes, each run only if the last overflowed
+      const uint64_t cstates = (uint64_t)pc.lanes << pc.n;
+      const int passes = cstates > (uint64_t)cap ? 1 + kRetries : 1;
+      for (int r = 0; r < passes; ++r) {
+        ch.retry = r;
+        HIP_TRY(enum_timed(w, isint, bt, ch, 1, st));
+        HIP_TRY(launch_score(isint, bt, 0, score_grid, N, r, st));
+        HIP_TRY(launch_merge(bt, 0, r, r == passes - 1, st));
+      }
+      states += (double)cstates;
       kmax = std::max(kmax, N - pc.n);
       nmaxu = std::max(nmaxu, pc.n);
     }
@@ -398,6 +410,7 @@ sg_status batch_search(Workspace* w, bool isint, const Batch& bt, int Nmax, int 
   HIP_TRY(launch_tables(isint, bt, ncap, st));
   const std::vector<Level> levels = batch_levels(Nmax, bt.S);
   w->ev_used = 0;
+  w->last_launches = 0;
   double states = 0.0;
   int nmaxu = 0;
   for (const Level& L : levels) {
@@ -407,9 +420,14 @@ sg_status batch_search(Workspace* w, bool isint, const Batch& bt, int Nmax, int 
     ch.lanes = L.lanes;
     ch.n = L.n;
     ch.table_offset = (1 << (L.n - kU)) - 1;
-    HIP_TRY(enum_timed(w, isint, bt, ch, bt.B, st));
-    states += (double)L.lanes * (double)((uint64_t)1 << L.n);
-    HIP_TRY(launch_merge_batched(isint, bt, L.first, st));
+    const uint64_t lstates = (uint64_t)L.lanes << L.n;
+    const int passes = lstates > (uint64_t)bt.cap ? 1 + kRetries : 1;
+    for (int r = 0; r < passes; ++r) {
+      ch.retry = r;
+      HIP_TRY(enum_timed(w, isint, bt, ch, bt.B, st));
+      HIP_TRY(launch_merge_batched(isint, bt, L.first, r, r == passes - 1, st));
+    }
+    states += (double)lstates;
     nmaxu = std::max(nmaxu, L.n);
   }
   HIP_TRY(launch_finalize(isint, bt, states_out, energies_out, st));
@@ -420,9 +438,12 @@ sg_status batch_search(Workspace* w, bool isint, const Batch& bt, int Nmax, int 
   return SG_OK;
 }
 
-uint32_t batch_cap(int S) {
+// Candidate slots per instance of a batch: at least 8192 and 4 S, more for
+// small batches (up to kBatchCandBudget slots in all, 20 bytes each).
+uint32_t batch_cap(int B, int S) {
   uint32_t cap = kBatchCandCapMin;
   while (cap < 2u * 4096u || cap < 4u * (uint32_t)S) cap <<= 1;
+  while (cap < (1u << 20) && (uint64_t)(2u * cap) * (uint64_t)B <= kBatchCandBudget) cap <<= 1;
   return cap;
 }
 
@@ -436,7 +457,7 @@ sg_status run_batched(bool isint, int B, const int32_t* Ns, int Nmax, const void
   if (!Ns || !J || !h || !states_out || !energies_out)
     return fail(SG_EINVAL, "null pointer argument");
   hipStream_t st = (hipStream_t)stream;
-  const uint32_t cap = batch_cap(S);
+  const uint32_t cap = batch_cap(B, S);
   const int ncap = std::min(kBatchFreeCap, Nmax);
   const size_t recs = table_records(ncap);
   Workspace* w = nullptr;
@@ -471,11 +492,14 @@ LzArgs lz_args(Workspace* w, int B, int N, int nb, int S, const float* beta, con
   LzArgs a{};
   a.B = B;
   a.N = N;
+  // free spins per lane: at most kLzFree, fewer when the batch alone would
+  // not give every resident lane of the device a prefix
   a.n = std::min(kLzFree, N);
+  while (a.n > kU && (int64_t)B * ((int64_t)1 << (N - a.n)) < w->fill[0]) --a.n;
   a.nb = nb;
   a.S = S;
   a.lanes = (int64_t)1 << (N - a.n);
-  a.table_recs = (int64_t)table_records(std::min(kLzFree, N));
+  a.table_recs = (int64_t)table_records(a.n);
   a.table_offset = (1 << (a.n - kU)) - 1;
   a.beta = beta;
   a.e0 = e0;
@@ -557,7 +581,7 @@ sg_status sg_logz_forward_f32(int B, int N, const float* J, const float* h, int 
   if (S < 1 || S > SG_MAX_S_BATCHED || (uint64_t)S > ((uint64_t)1 << N))
     return fail(SG_EINVAL, "S must be in [1, min(SG_MAX_S_BATCHED, 2^N)]");
   hipStream_t st = (hipStream_t)stream;
-  const uint32_t cap = batch_cap(S);
+  const uint32_t cap = batch_cap(B, S);
   const int ncap = std::min(kBatchFreeCap, N);
   const size_t recs = table_records(ncap);
   Workspace* w = nullptr;
@@ -573,7 +597,7 @@ sg_status sg_logz_forward_f32(int B, int N, const float* J, const float* h, int 
   const LzArgs a = lz_args(w, B, N, n_beta, S, beta, e0_out, 0);
   Batch b64 = bt;
   b64.table_recs = a.table_recs;
-  HIP_TRY(launch_tables64(b64, std::min(kLzFree, N), w->table64, st));
+  HIP_TRY(launch_tables64(b64, a.n, w->table64, st));
   HIP_TRY(launch_lz_prep(0, a, J, w->q64, energies_out, e0_out, nullptr, nullptr, st));
   HIP_TRY(launch_logz(0, a, J, h, w->table64, w->q64, st));
   HIP_TRY(launch_lz_final(0, a, logz_out, nullptr, nullptr, st));
@@ -597,10 +621,36 @@ sg_status sg_logz_backward_f32(int B, int N, const float* J, const float* h, int
   if (v != SG_OK) return v;
   const LzArgs a = lz_args(w, B, N, n_beta, 1, beta, e0, 1);
   Batch b64 = make_batch(w, J, h, nullptr, N, N, B, 1, a.table_recs, 1);
-  HIP_TRY(launch_tables64(b64, std::min(kLzFree, N), w->table64, st));
+  HIP_TRY(launch_tables64(b64, a.n, w->table64, st));
   HIP_TRY(launch_lz_prep(1, a, J, w->q64, nullptr, nullptr, logz, grad_logz, st));
   HIP_TRY(launch_logz(1, a, J, h, w->table64, w->q64, st));
   HIP_TRY(launch_lz_final(1, a, nullptr, grad_J, grad_h, st));
+  return SG_OK;
+}
+
+sg_status sg_reserve(int B_max, int N_max, int S_max, void* stream) {
+  g_last_error.clear();
+  if (B_max < 1) return fail(SG_EINVAL, "B_max must be >= 1");
+  if (N_max < 1 || N_max > SG_MAX_N) return fail(SG_EINVAL, "N_max must be in [1, SG_MAX_N]");
+  if (S_max < 1 || S_max > SG_MAX_S) return fail(SG_EINVAL, "S_max must be in [1, SG_MAX_S]");
+  hipStream_t st = (hipStream_t)stream;
+  Workspace* w = nullptr;
+  // single-instance search
+  uint32_t cap = kCandCapMin;
+  while (cap < 8u * (uint32_t)S_max) cap <<= 1;
+  sg_status v = ws_get(st, 1, table_records(kMaxFree), cap, S_max, &w);
+  if (v != SG_OK) return v;
+  // batched search and log Z
+  if (N_max >= kU && N_max <= 40 && S_max <= SG_MAX_S_BATCHED) {
+    // the per-instance slots grow as B shrinks: size for the largest B * cap
+    uint64_t slots = 0;
+    for (int b = 1; b <= B_max; ++b) slots = std::max(slots, (uint64_t)b * batch_cap(b, S_max));
+    const size_t cap_b = (size_t)((slots + B_max - 1) / B_max);
+    v = ws_get(st, B_max, table_records(std::min(kBatchFreeCap, N_max)), cap_b, S_max, &w);
+    if (v != SG_OK) return v;
+    v = lz_buffers(w, B_max, N_max);
+    if (v != SG_OK) return v;
+  }
   return SG_OK;
 }
 
@@ -635,7 +685,7 @@ sg_status sg_get_run_info(void* stream, sg_run_info* out) {
   out->max_drift = d;
   out->prefix_bits_max = w->last_kmax;
   out->free_bits_max = w->last_nmax;
-  out->enum_launches = w->last_chunks;
+  out->enum_launches = w->last_launches;
   out->enum_states = w->last_states;
   double ms = 0.0;
   for (int i = 0; i < w->ev_used; ++i) {
@@ -645,6 +695,7 @@ sg_status sg_get_run_info(void* stream, sg_run_info* out) {
   }
   out->enum_ms = ms;
   out->max_chunk_candidates = p.max_chunk_cand;
+  out->repeated_passes = p.stat_redo;
   return SG_OK;
 }
 

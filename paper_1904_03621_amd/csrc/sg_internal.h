@@ -62,7 +62,15 @@ struct Params {
   unsigned long long stat_slow;
   uint32_t max_drift_bits;  // float bits, non-negative
   uint32_t max_chunk_cand;  // most candidates any one chunk produced
+  // 1 when the last pass over the current chunk produced more candidates
+  // than the buffer holds: the chunk is walked again with the tightened
+  // threshold (at most kRetries times)
+  uint32_t redo;
+  uint32_t stat_redo;       // repeated passes taken
 };
+
+// Extra passes over a chunk whose candidates overflowed the buffer.
+constexpr int kRetries = 2;
 
 // Device views of one search over B instances (B = 1 for a single search).
 // Instance b has N_b spins (Ns[b], or N0 for every instance when Ns is
@@ -115,6 +123,7 @@ struct Chunk {
   int64_t lanes;
   int n;
   int table_offset;       // record index of block 0 in the table for this n
+  int retry;              // 0: first pass; r >= 1: r-th repeat (only if redo)
 };
 
 // Orderable 32-bit keys of energies.

@@ -100,11 +100,9 @@ __device__ inline void append_mask(uint64_t mask, Params* P, uint64_t* cand, uin
   base = __shfl(base, leader);
   const uint64_t below = act & ((1ull << lid) - 1ull);
   const uint32_t slot = base + (uint32_t)__popcll(below);
-  if (slot < cap) {
-    cand[slot] = mask;
-  } else {
-    atomicOr(&P->err, kErrCapacity);
-  }
+  // beyond cap the mask is dropped; the merge sees cand_count > cap and asks
+  // for another pass over the chunk
+  if (slot < cap) cand[slot] = mask;
 }
 
 // ------------------------------------------------------------------ k_prep
@@ -237,6 +235,8 @@ __global__ void k_prep(Batch bt) {
     P->err = err;
     P->cand_count = 0;
     P->surv_count = 0;
+    P->redo = 0;
+    P->stat_redo = 0;
     P->stat_candidates = 0;
     P->stat_slow = 0;
     P->max_drift_bits = 0;
@@ -374,6 +374,7 @@ __global__ __launch_bounds__(kEnumBlock, 8) void k_enum(Batch bt, const void* __
   Params* P = bt.P + b;
   const uint32_t err0 = P->err;
   if (err0 & (kErrNonFinite | kErrOverflow | kErrInval)) return;
+  if (ch.retry && !P->redo) return;
 
   // The lane's high-spin fields Y_g (index [g - U][thread]) are read once per
   // block boundary, so they live in LDS rather than in registers.
@@ -588,7 +589,6 @@ __global__ void k_direct(Batch bt, uint64_t lo, uint64_t hi) {
   Params* P = bt.P;
   const uint32_t slot = atomicAdd(&P->cand_count, 1u);
   if (slot < bt.cap) bt.cand[slot] = m;
-  else atomicOr(&P->err, kErrCapacity);
 }
 
 // ------------------------------------------------- scoring and merging
@@ -612,9 +612,15 @@ __device__ inline void stage_instance(const Batch& bt, int b, int N, uint32_t* s
 }
 
 // Single instance: grid-stride over the candidates of instance b.
+// In a repeated pass the record already holds some of the chunk's states:
+// a candidate equal to a record entry is dropped.
+__device__ inline bool in_record(const uint32_t* rkey, const uint64_t* rmask, uint32_t rn,
+                                 uint32_t key, uint64_t m);
+
 template <bool kInt>
-__global__ void k_score(Batch bt, int b) {
+__global__ void k_score(Batch bt, int b, int retry) {
   extern __shared__ uint32_t s_inst[];
+  if (retry && !bt.P[b].redo) return;
   const int N = inst_N(bt, b);
   stage_instance<kInt>(bt, b, N, s_inst);
   __syncthreads();
@@ -637,6 +643,9 @@ __global__ void k_score(Batch bt, int b) {
       m = cand[j];
       key = exact_key<kInt>(s_inst, s_inst + N * N, N, N, m);
       keep = !full || key_less(key, m, thr_key, thr_mask);
+      if (keep && retry)
+        keep = !in_record(bt.rkey + (size_t)b * bt.S, bt.rmask + (size_t)b * bt.S,
+                          P->rec_count, key, m);
     }
     if (keep) {
       const uint64_t act = __ballot(1);
@@ -688,14 +697,20 @@ __device__ inline uint32_t rank_in(const uint32_t* k, const uint64_t* m, uint32_
   return lo;
 }
 
+__device__ inline bool in_record(const uint32_t* rkey, const uint64_t* rmask, uint32_t rn,
+                                 uint32_t key, uint64_t m) {
+  const uint32_t r = rank_in(rkey, rmask, rn, key, m);
+  return r < rn && rkey[r] == key && rmask[r] == m;
+}
+
 // The whole workgroup: sort the ns survivors (skey, smask) -- bitonic sort
 // in LDS when they fit, in global memory otherwise -- and merge them with
 // the sorted record (rank of an element = its index plus the number of
 // smaller elements in the other list; keys are distinct because masks are),
 // keeping the first S; publish the S-th key as the threshold.
-__device__ void merge_body(Params* P, int S, uint32_t cap, uint32_t ns, uint32_t* skey,
-                           uint64_t* smask, uint32_t* rkey, uint64_t* rmask, uint32_t* tkey,
-                           uint64_t* tmask, uint32_t* l_key, uint64_t* l_mask) {
+__device__ void merge_body(Params* P, int S, uint32_t cap, bool last_pass, uint32_t ns,
+                           uint32_t* skey, uint64_t* smask, uint32_t* rkey, uint64_t* rmask,
+                           uint32_t* tkey, uint64_t* tmask, uint32_t* l_key, uint64_t* l_mask) {
   const uint32_t rn = P->rec_count;
   __syncthreads();
   if (ns > 0) {
@@ -745,7 +760,11 @@ __device__ void merge_body(Params* P, int S, uint32_t cap, uint32_t ns, uint32_t
   }
   if (threadIdx.x == 0) {
     const uint32_t cc = P->cand_count;
-    if (cc > cap) P->err |= kErrCapacity;
+    // overflow: the first cap candidates were merged, which can only lower
+    // the threshold; the chunk is walked again unless this was the last pass
+    P->redo = cc > cap ? 1u : 0u;
+    if (cc > cap && !last_pass) P->stat_redo += 1;
+    if (cc > cap && last_pass) P->err |= kErrCapacity;
     P->stat_candidates += cc;
     P->max_chunk_cand = max(P->max_chunk_cand, cc);
     P->cand_count = 0;
@@ -754,12 +773,14 @@ __device__ void merge_body(Params* P, int S, uint32_t cap, uint32_t ns, uint32_t
 }
 
 // Single instance: one workgroup merges the survivors k_score left.
-__global__ __launch_bounds__(kMergeThreads) void k_merge(Batch bt, int b) {
+__global__ __launch_bounds__(kMergeThreads) void k_merge(Batch bt, int b, int retry,
+                                                        int last_pass) {
   __shared__ uint32_t l_key[kLdsSortCap];
   __shared__ uint64_t l_mask[kLdsSortCap];
   Params* P = bt.P + b;
+  if (retry && !P->redo) return;
   const uint32_t ns = P->surv_count;
-  merge_body(P, bt.S, bt.cap, ns, bt.skey + (size_t)b * bt.cap, bt.smask + (size_t)b * bt.cap,
+  merge_body(P, bt.S, bt.cap, last_pass != 0, ns, bt.skey + (size_t)b * bt.cap, bt.smask + (size_t)b * bt.cap,
              bt.rkey + (size_t)b * bt.S, bt.rmask + (size_t)b * bt.S,
              bt.tkey + (size_t)b * bt.S, bt.tmask + (size_t)b * bt.S, l_key, l_mask);
 }
@@ -768,7 +789,8 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge(Batch bt, int b) {
 // starting at first_mask, then merges the survivors into its record.
 template <bool kInt>
 __global__ __launch_bounds__(kMergeBatchThreads) void k_merge_batched(Batch bt,
-                                                                      uint64_t first_mask) {
+                                                                      uint64_t first_mask,
+                                                                      int retry, int last_pass) {
   __shared__ uint32_t l_key[kLdsSortCap];
   __shared__ uint64_t l_mask[kLdsSortCap];
   __shared__ uint32_t s_inst[kMaxN * kMaxN + kMaxN];
@@ -777,6 +799,7 @@ __global__ __launch_bounds__(kMergeBatchThreads) void k_merge_batched(Batch bt,
   const int N = inst_N(bt, b);
   if (N < kU || N > bt.ld || (N < 63 && first_mask >= (1ull << N))) return;
   Params* P = bt.P + b;
+  if (retry && !P->redo) return;
   stage_instance<kInt>(bt, b, N, s_inst);
   if (threadIdx.x == 0) s_ns = 0;
   __syncthreads();
@@ -790,7 +813,11 @@ __global__ __launch_bounds__(kMergeBatchThreads) void k_merge_batched(Batch bt,
   for (uint32_t j = threadIdx.x; j < cnt; j += blockDim.x) {
     const uint64_t m = cand[j];
     const uint32_t key = exact_key<kInt>(s_inst, s_inst + N * N, N, N, m);
-    if (!full || key_less(key, m, thr_key, thr_mask)) {
+    bool keep = !full || key_less(key, m, thr_key, thr_mask);
+    if (keep && retry)
+      keep = !in_record(bt.rkey + (size_t)b * bt.S, bt.rmask + (size_t)b * bt.S, P->rec_count,
+                        key, m);
+    if (keep) {
       const uint32_t slot = atomicAdd(&s_ns, 1u);
       skey[slot] = key;
       smask[slot] = m;
@@ -798,7 +825,7 @@ __global__ __launch_bounds__(kMergeBatchThreads) void k_merge_batched(Batch bt,
   }
   __syncthreads();
   const uint32_t ns = s_ns;
-  merge_body(P, bt.S, bt.cap, ns, skey, smask, bt.rkey + (size_t)b * bt.S,
+  merge_body(P, bt.S, bt.cap, last_pass != 0, ns, skey, smask, bt.rkey + (size_t)b * bt.S,
              bt.rmask + (size_t)b * bt.S, bt.tkey + (size_t)b * bt.S,
              bt.tmask + (size_t)b * bt.S, l_key, l_mask);
 }
@@ -863,26 +890,28 @@ hipError_t launch_direct(const Batch& bt, uint64_t lo, uint64_t hi, hipStream_t 
   return hipGetLastError();
 }
 
-hipError_t launch_score(bool isint, const Batch& bt, int b, int grid, int N, hipStream_t st) {
+hipError_t launch_score(bool isint, const Batch& bt, int b, int grid, int N, int retry,
+                        hipStream_t st) {
   const size_t shm = (size_t)(N * N + N) * 4;
-  if (isint) hipLaunchKernelGGL(k_score<true>, dim3(grid), dim3(256), shm, st, bt, b);
-  else hipLaunchKernelGGL(k_score<false>, dim3(grid), dim3(256), shm, st, bt, b);
+  if (isint) hipLaunchKernelGGL(k_score<true>, dim3(grid), dim3(256), shm, st, bt, b, retry);
+  else hipLaunchKernelGGL(k_score<false>, dim3(grid), dim3(256), shm, st, bt, b, retry);
   return hipGetLastError();
 }
 
-hipError_t launch_merge(const Batch& bt, int b, hipStream_t st) {
-  hipLaunchKernelGGL(k_merge, dim3(1), dim3(kMergeThreads), 0, st, bt, b);
+hipError_t launch_merge(const Batch& bt, int b, int retry, bool last_pass, hipStream_t st) {
+  hipLaunchKernelGGL(k_merge, dim3(1), dim3(kMergeThreads), 0, st, bt, b, retry,
+                     last_pass ? 1 : 0);
   return hipGetLastError();
 }
 
-hipError_t launch_merge_batched(bool isint, const Batch& bt, uint64_t first_mask,
-                                hipStream_t st) {
+hipError_t launch_merge_batched(bool isint, const Batch& bt, uint64_t first_mask, int retry,
+                                bool last_pass, hipStream_t st) {
   if (isint)
     hipLaunchKernelGGL(k_merge_batched<true>, dim3(bt.B), dim3(kMergeBatchThreads), 0, st, bt,
-                       first_mask);
+                       first_mask, retry, last_pass ? 1 : 0);
   else
     hipLaunchKernelGGL(k_merge_batched<false>, dim3(bt.B), dim3(kMergeBatchThreads), 0, st, bt,
-                       first_mask);
+                       first_mask, retry, last_pass ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -65,6 +65,30 @@ def test_validation_is_synchronous(L, case):
     assert L.last_error() != ""
 
 
+@pytest.mark.parametrize("case", [
+    dict(B=0), dict(N=5), dict(N=41), dict(nb=0), dict(nb=5), dict(S=0), dict(S=4097),
+    dict(S=65, N=6), dict(null=True),
+])
+def test_batched_and_logz_validation_is_synchronous(L, case):
+    lib = L.lib()
+    B, N, S, nb = case.get("B", 4), case.get("N", 20), case.get("S", 8), case.get("nb", 3)
+    p = 0 if case.get("null") else 4096  # never dereferenced: validation fails first
+    st = lib.sg_logz_forward_f32(B, N, p, p, nb, p, S, p, p, p, p, 0)
+    assert st == L.SG_EINVAL and L.last_error() != ""
+    if "S" not in case:
+        st = lib.sg_logz_backward_f32(B, N, p, p, nb, p, p, p, p, p, p, 0)
+        assert st == L.SG_EINVAL and L.last_error() != ""
+    if "nb" not in case and not (N == 6 and S == 65):
+        st = lib.sg_low_spectrum_batched_f32(B, p, N, p, p, S, p, p, 0)
+        assert st == L.SG_EINVAL and L.last_error() != ""
+
+
+@pytest.mark.parametrize("args", [(0, 20, 8), (4, 0, 8), (4, 57, 8), (4, 20, 0),
+                                  (4, 20, (1 << 20) + 1)])
+def test_reserve_validation(L, args):
+    assert L.lib().sg_reserve(*args, 0) == L.SG_EINVAL
+
+
 def _check_plan(L, N, S, lo, hi, fill):
     plan = L.sg_debug_plan(N, S, lo, hi, fill)
     assert plan, "empty plan"
@@ -117,3 +141,12 @@ def test_plan_uses_full_fill_at_scale(L):
     # every chunk of the second half of the space runs a full device
     assert all(l == fill for (m, _, l) in plan if m >= (1 << 47))
     assert len(plan) < 200
+
+
+def test_run_info_struct_matches_header(L):
+    """The ctypes mirror of sg_run_info lists the header's fields in order."""
+    import re
+    text = open(os.path.join(ROOT, "include", "sg.h")).read()
+    body = text[text.index("typedef struct"):text.index("} sg_run_info;")]
+    names = re.findall(r"^\s*(?:int64_t|int32_t|double|float)\s+(\w+);", body, re.M)
+    assert names == [n for n, _ in L.RunInfo._fields_]

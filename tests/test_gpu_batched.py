@@ -123,3 +123,58 @@ def test_bad_instance_size_reported(torch_dev):
     with pytest.raises(sg.SgError) as ei:
         run_batched(torch_dev, Ns, J, h, 8)
     assert ei.value.status == _lib.SG_EINVAL
+
+
+def test_reserve_then_capture(torch_dev):
+    """sg_reserve sizes a fresh stream's workspace, so the first call on that
+    stream can be captured into a graph directly."""
+    import paper_1904_03621_amd as sg
+    torch = torch_dev
+    B, S = 48, 32
+    Ns, J, h = make_batch(B, 8, 24, 11, False)
+    Nt, Jt, ht = (torch.from_numpy(x).cuda() for x in (Ns, J, h))
+    m0, e0 = sg.low_spectrum_batched(Nt, Jt, ht, S)  # reference on the default stream
+    stream = torch.cuda.Stream()
+    assert sg.sg_reserve(B, J.shape[1], S, stream) == 0
+    m_out = torch.zeros((B, S), dtype=torch.int64, device="cuda")
+    e_out = torch.zeros((B, S), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        st = sg.sg_low_spectrum_batched_f32(B, Nt, J.shape[1], Jt, ht, S, m_out, e_out, stream)
+    assert st == 0
+    for rep in range(2):
+        m_out.fill_(-1)
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(m_out, m0) and torch.equal(e_out, e0), "replay %d differs" % rep
+    assert sg.sg_get_error(stream) == 0
+
+
+def test_overflowing_level_is_walked_again(orc, torch_dev):
+    """A strong field on the top spin puts ~55000 states of the last level
+    below the threshold that the first half of the state space leaves; with
+    2048 instances each has 8192 candidate slots, so that level overflows,
+    is merged in part and walked again with the tighter threshold."""
+    import paper_1904_03621_amd as sg
+    torch = torch_dev
+    B, N, S = 2048, 20, 64
+    J0, h0 = I.random_f32_dense(N, 71, j_scale=1.0 / np.sqrt(N), h_scale=0.1)
+    h0 = h0.copy()
+    h0[N - 1] = 3.0
+    Ns, J, h = make_batch(B, 6, 10, 12, False, Nmax=N)
+    Ns[0] = N
+    J[0], h[0] = J0, h0
+    bm, be = run_batched(torch, Ns, J, h, S)
+    info = sg.run_info()
+    assert info["repeated_passes"] >= 1 and info["max_chunk_candidates"] > 8192, info
+    om, oe = orc.low_spectrum(J0, h0, S)
+    check_f32(N, J0, bm[0], be[0], om, oe, lambda x: orc.energy(J0, h0, x), "overflow instance")
+    sm, se = run_single(torch, J0, h0, S)
+    assert np.array_equal(sm, bm[0]) and np.array_equal(se, be[0])
+    for b in range(1, B, 97):
+        n = int(Ns[b])
+        om, oe = orc.low_spectrum(J[b, :n, :n], h[b, :n], min(S, 1 << n))
+        k = len(om)
+        check_f32(n, J[b, :n, :n], bm[b, :k], be[b, :k], om, oe,
+                  lambda x: orc.energy(J[b, :n, :n], h[b, :n], x), "instance %d" % b)
