@@ -185,6 +185,10 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extensions", action="store_true",
                     help="skip the batched and log Z measurements")
+    ap.add_argument("--valu-probe", action="store_true",
+                    help="print the measured issue rate of each probed VALU instruction")
+    ap.add_argument("--leg", choices=["batched", "logz"],
+                    help="run only this extension leg (for profiling) and print its result")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="one search, then a plain 512 MiB device copy (the reference for "
                          "scaling the FETCH_SIZE / WRITE_SIZE counters); prints nothing else")
@@ -199,6 +203,15 @@ def main() -> int:
     import torch
     import instances as I
     import paper_1904_03621_amd as sg
+
+    if args.valu_probe:
+        rates = {op: sg.sg_probe_valu(code, 8) for op, code in sg._lib.PROBE_OPS.items()}
+        print(json.dumps({"valu_lane_ops_per_s": rates, "waves_per_simd": 8}), flush=True)
+        return 0
+    if args.leg:
+        fn = bench_batched if args.leg == "batched" else bench_logz
+        print(json.dumps({args.leg: fn(torch, sg, 1)}), flush=True)
+        return 0
 
     J, h = I.random_f32_dense(N_SPINS, SEED)
     dev = torch.device("cuda:0")
