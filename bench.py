@@ -30,6 +30,30 @@ PEAK_LANE_OPS = 256 * 128 * 2.4e9
 OPS_PER_STATE = 2.0
 # size of the plain device copy that calibrates the HBM byte counters
 COPY_BYTES = 512 << 20
+# HBM bytes per k_enum launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes
+# (KiB per dispatch, averaged over the 447 dispatches of one search), scaled by
+# what the same counters read for the 512 MiB copy (fetch x2.0, write x1.0);
+# valid for the k_enum source with this SHA-256 prefix only
+TRAFFIC = {"kenum_sha256_16": "367145bb966a9bb0", "fetch_kib": 4807.47, "write_kib": 95.37,
+           "fetch_factor": 524288.0 / 262162.0, "write_factor": 1.0,
+           "profile": "profiles/k_enum_f32_dense48_counters.md"}
+
+
+def kenum_source_hash() -> str:
+    import hashlib
+    src = open(os.path.join(ROOT, "paper_1904_03621_amd", "csrc", "sg_kernels.hip")).read()
+    i = src.index("void k_enum(Batch bt")
+    j = src.index("\n}\n", i)
+    return hashlib.sha256(src[i:j].encode()).hexdigest()[:16]
+
+
+def traffic_per_launch():
+    """HBM bytes per k_enum launch from the committed counter profile, or None
+    once the kernel's source differs from the one the counters were taken on."""
+    if kenum_source_hash() != TRAFFIC["kenum_sha256_16"]:
+        return None
+    return 1024.0 * (TRAFFIC["fetch_kib"] * TRAFFIC["fetch_factor"]
+                     + TRAFFIC["write_kib"] * TRAFFIC["write_factor"])
 
 
 def cpu_baseline(J, h, seconds_hint: float = 20.0) -> dict:
@@ -60,7 +84,7 @@ def _sync_time(torch, fn):
     return time.perf_counter() - t
 
 
-def bench_batched(torch, sg, reps: int) -> dict:
+def bench_batched(torch, sg, reps: int, baseline: bool = True) -> dict:
     """4096 instances, N_b uniform in [16, 32], J ~ N(0,1) fp32 (unscaled),
     h ~ N(0, 0.1^2), S = 64: one batched call against one single-instance
     call per instance (same stream, buffers allocated beforehand, no
@@ -92,6 +116,9 @@ def bench_batched(torch, sg, reps: int) -> dict:
                 raise sg.SgError(st, "sg_low_spectrum_f32", sg._lib.last_error())
 
     batched()
+    if not baseline:
+        t_b = min(_sync_time(torch, batched) for _ in range(reps))
+        return {"ms": t_b * 1e3}
     per_instance()  # warm-up: workspaces sized
     t_b = min(_sync_time(torch, batched) for _ in range(reps))
     t_p = _sync_time(torch, per_instance)
@@ -108,7 +135,7 @@ def bench_batched(torch, sg, reps: int) -> dict:
             "states": states}
 
 
-def bench_logz(torch, sg, reps: int) -> dict:
+def bench_logz(torch, sg, reps: int, baseline: bool = True) -> dict:
     """256 instances, N = 28, J ~ N(0,1)/sqrt(28), h ~ N(0, 0.2^2), beta in
     {0.5, 1, 2}, S = 32: log Z forward + backward of the batch against one
     forward + backward per instance."""
@@ -155,7 +182,12 @@ def bench_logz(torch, sg, reps: int) -> dict:
             if st != 0:
                 raise sg.SgError(st, "sg_logz per instance", sg._lib.last_error())
 
-    fwd(); bwd(); per_instance()  # warm-up
+    fwd(); bwd()
+    if not baseline:
+        t_f = min(_sync_time(torch, fwd) for _ in range(reps))
+        t_bw = min(_sync_time(torch, bwd) for _ in range(reps))
+        return {"forward_ms": t_f * 1e3, "backward_ms": t_bw * 1e3}
+    per_instance()  # warm-up
     t_f = min(_sync_time(torch, fwd) for _ in range(reps))
     t_bw = min(_sync_time(torch, bwd) for _ in range(reps))
     t_p = _sync_time(torch, per_instance)
@@ -188,7 +220,8 @@ def main() -> int:
     ap.add_argument("--valu-probe", action="store_true",
                     help="print the measured issue rate of each probed VALU instruction")
     ap.add_argument("--leg", choices=["batched", "logz"],
-                    help="run only this extension leg (for profiling) and print its result")
+                    help="run only this extension's batched calls (warm-up + 1 timed; for "
+                         "profiling) and print their times")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="one search, then a plain 512 MiB device copy (the reference for "
                          "scaling the FETCH_SIZE / WRITE_SIZE counters); prints nothing else")
@@ -210,7 +243,7 @@ def main() -> int:
         return 0
     if args.leg:
         fn = bench_batched if args.leg == "batched" else bench_logz
-        print(json.dumps({args.leg: fn(torch, sg, 1)}), flush=True)
+        print(json.dumps({args.leg: fn(torch, sg, 1, baseline=False)}), flush=True)
         return 0
 
     J, h = I.random_f32_dense(N_SPINS, SEED)
@@ -271,7 +304,8 @@ def main() -> int:
     ops_per_launch = OPS_PER_STATE * enum_states / max(enum_launches, 1)
     achieved = ops_per_launch / (avg_ms * 1e-3) if avg_ms > 0 else 0.0
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
-                "unit": "Tlane-op/s", "frac": achieved / PEAK_LANE_OPS, "traffic": None,
+                "unit": "Tlane-op/s", "frac": achieved / PEAK_LANE_OPS,
+                "traffic": traffic_per_launch(), "traffic_unit": "HBM bytes per launch",
                 "kernel": "k_enum<float>", "avg_launch_ms": avg_ms,
                 "launches_per_step": enum_launches / max(args.steps, 1),
                 "ops_per_state": OPS_PER_STATE}

@@ -29,11 +29,12 @@ hipError_t launch_finalize(bool isint, const Batch& bt, uint64_t* states_out, vo
 int enum_occupancy(bool isint);
 double probe_valu(int op, int waves_per_simd);
 hipError_t launch_tables64(const Batch& bt, int ncap, double* out, hipStream_t st);
-hipError_t launch_lz_prep(int mode, const LzArgs& a, const float* J, double* q64,
+hipError_t launch_lz_prep(int mode, const LzArgs& a, const float* J, float* lzq, double* lzqmin,
                           const float* energies, float* e0_out, const double* logz,
                           const double* grad, hipStream_t st);
 hipError_t launch_logz(int mode, const LzArgs& a, const float* J, const float* h,
-                       const double* table64, const double* q64, hipStream_t st);
+                       const double* table64, const float* lzq, const double* lzqmin,
+                       hipStream_t st);
 hipError_t launch_lz_final(int mode, const LzArgs& a, double* logz, float* grad_J, float* grad_h,
                            hipStream_t st);
 }  // namespace sg
@@ -139,8 +140,10 @@ struct Workspace {
   // log Z walk
   double* table64 = nullptr;
   size_t ntable64 = 0;
-  double* q64 = nullptr;
-  size_t nq64 = 0;
+  float* lzq = nullptr;        // [B][4][3 * 64] exp(-beta (Q - min Q)) tables
+  size_t nlzq = 0;
+  double* lzqmin = nullptr;    // [B] min Q
+  size_t nlzqmin = 0;
   double* lz_acc = nullptr;
   size_t nlz_acc = 0;
   double* lz_coef = nullptr;
@@ -375,10 +378,12 @@ sg_status run_search(bool isint, int N, const void* J, const void* h, int S, uin
 }
 
 // Chunk levels of a batched search.  Level 0 is [0, first) with
-// first = max(S, 4096) rounded up to a power of two; level j >= 1 is
-// [first 2^(j-1), first 2^j), so every level is as large as everything before
-// it.  All instances with states in a level run it in the same launch, with
-// the same geometry: n = clamp(log2(size) - 12, U, 17) free spins per lane.
+// first = max(S, 64) rounded up to a power of two (every state of it is a
+// candidate, so it is kept small); level j >= 1 is [first 2^(j-1), first 2^j),
+// so every level is as large as everything before it and brings about S
+// candidates.  All instances with states in a level run it in the same launch,
+// with the same geometry: n = clamp(log2(size) - 12, U, 17) free spins per
+// lane.
 struct Level {
   uint64_t first;
   int n;
@@ -387,7 +392,7 @@ struct Level {
 
 std::vector<Level> batch_levels(int Nmax, int S) {
   std::vector<Level> out;
-  uint64_t size0 = 4096;
+  uint64_t size0 = kBlockSteps;
   while (size0 < (uint64_t)S) size0 <<= 1;
   const uint64_t full = (uint64_t)1 << Nmax;
   uint64_t first = 0, size = size0;
@@ -481,7 +486,8 @@ sg_status lz_buffers(Workspace* w, int B, int N) {
   const size_t Bz = (size_t)B;
   const size_t stride = std::max<size_t>(kMaxBeta, (size_t)N * N + N);
   HIP_TRY(grow(&w->table64, &w->ntable64, Bz * table_records(std::min(kLzFree, N)) * 8));
-  HIP_TRY(grow(&w->q64, &w->nq64, Bz * 2 * kBlockSteps));
+  HIP_TRY(grow(&w->lzq, &w->nlzq, Bz * kMaxBeta * 3 * kBlockSteps));
+  HIP_TRY(grow(&w->lzqmin, &w->nlzqmin, Bz));
   HIP_TRY(grow(&w->lz_acc, &w->nlz_acc, Bz * stride));
   HIP_TRY(grow(&w->lz_coef, &w->nlz_coef, Bz * kMaxBeta));
   return SG_OK;
@@ -598,8 +604,8 @@ sg_status sg_logz_forward_f32(int B, int N, const float* J, const float* h, int 
   Batch b64 = bt;
   b64.table_recs = a.table_recs;
   HIP_TRY(launch_tables64(b64, a.n, w->table64, st));
-  HIP_TRY(launch_lz_prep(0, a, J, w->q64, energies_out, e0_out, nullptr, nullptr, st));
-  HIP_TRY(launch_logz(0, a, J, h, w->table64, w->q64, st));
+  HIP_TRY(launch_lz_prep(0, a, J, w->lzq, w->lzqmin, energies_out, e0_out, nullptr, nullptr, st));
+  HIP_TRY(launch_logz(0, a, J, h, w->table64, w->lzq, w->lzqmin, st));
   HIP_TRY(launch_lz_final(0, a, logz_out, nullptr, nullptr, st));
   return SG_OK;
 }
@@ -622,8 +628,8 @@ sg_status sg_logz_backward_f32(int B, int N, const float* J, const float* h, int
   const LzArgs a = lz_args(w, B, N, n_beta, 1, beta, e0, 1);
   Batch b64 = make_batch(w, J, h, nullptr, N, N, B, 1, a.table_recs, 1);
   HIP_TRY(launch_tables64(b64, a.n, w->table64, st));
-  HIP_TRY(launch_lz_prep(1, a, J, w->q64, nullptr, nullptr, logz, grad_logz, st));
-  HIP_TRY(launch_logz(1, a, J, h, w->table64, w->q64, st));
+  HIP_TRY(launch_lz_prep(1, a, J, w->lzq, w->lzqmin, nullptr, nullptr, logz, grad_logz, st));
+  HIP_TRY(launch_logz(1, a, J, h, w->table64, w->lzq, w->lzqmin, st));
   HIP_TRY(launch_lz_final(1, a, nullptr, grad_J, grad_h, st));
   return SG_OK;
 }
@@ -702,7 +708,7 @@ sg_status sg_get_run_info(void* stream, sg_run_info* out) {
 void sg_set_kernel_timing(int enable) { g_timing = enable != 0; }
 
 double sg_probe_valu(int op, int waves_per_simd) {
-  if (op < 0 || op > 13 || waves_per_simd < 1 || waves_per_simd > 8) return -1.0;
+  if (op < 0 || op > 16 || waves_per_simd < 1 || waves_per_simd > 8) return -1.0;
   return probe_valu(op, waves_per_simd);
 }
 

@@ -31,6 +31,7 @@ constexpr int kMergeThreads = 1024;   // threads of the single-workgroup merge
 constexpr int kMergeBatchThreads = 256;  // threads per instance in the batched merge
 constexpr int kBatchFreeCap = 17;     // largest n of a batched search
 constexpr int kLdsSortCap = 4096;     // survivors sorted in LDS up to this
+constexpr int kLdsSortCapBatch = 1024;  // the same for the per-instance batched merge
 constexpr int kMaxN = 56;
 
 // Sticky device error bits (mapped to sg_status on the host).

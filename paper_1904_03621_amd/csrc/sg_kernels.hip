@@ -710,7 +710,8 @@ __device__ inline bool in_record(const uint32_t* rkey, const uint64_t* rmask, ui
 // keeping the first S; publish the S-th key as the threshold.
 __device__ void merge_body(Params* P, int S, uint32_t cap, bool last_pass, uint32_t ns,
                            uint32_t* skey, uint64_t* smask, uint32_t* rkey, uint64_t* rmask,
-                           uint32_t* tkey, uint64_t* tmask, uint32_t* l_key, uint64_t* l_mask) {
+                           uint32_t* tkey, uint64_t* tmask, uint32_t* l_key, uint64_t* l_mask,
+                           uint32_t lds_cap) {
   const uint32_t rn = P->rec_count;
   __syncthreads();
   if (ns > 0) {
@@ -718,7 +719,7 @@ __device__ void merge_body(Params* P, int S, uint32_t cap, bool last_pass, uint3
     while (P2 < ns) P2 <<= 1;
     uint32_t* ks;
     uint64_t* ms;
-    if (P2 <= (uint32_t)kLdsSortCap) {
+    if (P2 <= lds_cap) {
       for (uint32_t t = threadIdx.x; t < P2; t += blockDim.x) {
         l_key[t] = t < ns ? skey[t] : 0xFFFFFFFFu;
         l_mask[t] = t < ns ? smask[t] : ~0ull;
@@ -782,7 +783,8 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge(Batch bt, int b, int re
   const uint32_t ns = P->surv_count;
   merge_body(P, bt.S, bt.cap, last_pass != 0, ns, bt.skey + (size_t)b * bt.cap, bt.smask + (size_t)b * bt.cap,
              bt.rkey + (size_t)b * bt.S, bt.rmask + (size_t)b * bt.S,
-             bt.tkey + (size_t)b * bt.S, bt.tmask + (size_t)b * bt.S, l_key, l_mask);
+             bt.tkey + (size_t)b * bt.S, bt.tmask + (size_t)b * bt.S, l_key, l_mask,
+             (uint32_t)kLdsSortCap);
 }
 
 // Batch: one workgroup per instance scores its own candidates of the chunk
@@ -791,8 +793,8 @@ template <bool kInt>
 __global__ __launch_bounds__(kMergeBatchThreads) void k_merge_batched(Batch bt,
                                                                       uint64_t first_mask,
                                                                       int retry, int last_pass) {
-  __shared__ uint32_t l_key[kLdsSortCap];
-  __shared__ uint64_t l_mask[kLdsSortCap];
+  __shared__ uint32_t l_key[kLdsSortCapBatch];
+  __shared__ uint64_t l_mask[kLdsSortCapBatch];
   __shared__ uint32_t s_inst[kMaxN * kMaxN + kMaxN];
   __shared__ uint32_t s_ns;
   const int b = blockIdx.x;
@@ -827,7 +829,7 @@ __global__ __launch_bounds__(kMergeBatchThreads) void k_merge_batched(Batch bt,
   const uint32_t ns = s_ns;
   merge_body(P, bt.S, bt.cap, last_pass != 0, ns, skey, smask, bt.rkey + (size_t)b * bt.S,
              bt.rmask + (size_t)b * bt.S, bt.tkey + (size_t)b * bt.S,
-             bt.tmask + (size_t)b * bt.S, l_key, l_mask);
+             bt.tmask + (size_t)b * bt.S, l_key, l_mask, (uint32_t)kLdsSortCapBatch);
 }
 
 // -------------------------------------------------------------- k_finalize

@@ -5,24 +5,32 @@
 //   log Z(beta) = -beta E0 + log sum_s exp(-beta (E(s) - E0))
 //   d log Z / d J_ij = beta <s_i s_j>,   d log Z / d h_i = beta <s_i>
 //
-// E0 is the ground energy found by the low-spectrum search, so every shifted
-// weight is at most 1.  The walk is the same Gray-code walk as the search
-// (prefix per lane, free spins 0..n-1, low blocks of 2^U steps) but keeps its
-// energy chain in fp64: only the shifted energy x = E - E0 is rounded to fp32
-// for the exponent (v_exp_f32, base 2).
+// E0 is the ground energy found by the low-spectrum search.  The walk uses the
+// decomposition of the search (prefix per lane, free spins 0..n-1, blocks of
+// the 2^U configurations of the U low spins with the high spins fixed), but it
+// does not step through a block: inside block T the energy is
+//   E(x) = K_T + sum_{f<U} phi_f s_f + Q(x),
+// linear in the low spins apart from their own couplings Q, so
+//   exp(-beta (E(x) - E0)) = P_T * prod_f c_f(s_f) * bq(x)
+// with P_T = exp(-beta (K_T - sum|phi_f| + min Q - E0)), c_f = 1 for the sign
+// that lowers phi_f s_f and exp(-2 beta |phi_f|) for the other, and
+// bq(x) = exp(-beta (Q(x) - min Q)) a per-instance table.  Every factor except
+// P_T lies in (0, 1], so nothing overflows; P_T is formed in fp64 range.
+// K_T and phi_f are recomputed per block in fp64 from the lane's prefix fields
+// and the block record (no running sum, no drift).
 //
-// Forward (kMode 0): per lane, fp32 sums of the 64 weights of a block are
-// added into fp64 per-beta totals; a wave reduction and one fp64 atomic per
-// wave give the per-instance sums.
+// Forward (kMode 0): the 64 weights of a block are an 8 x 8 contraction of
+// the factor products of spins 0-2 and 3-5 with bq; block sums are fp32, lane
+// totals fp64, one fp64 atomic per wave and beta.
 //
 // Backward (kMode 1): the gradient of sum_b g_b log Z(beta_b) needs, for every
 // pair and every spin, sum_s omega(s) s_i s_j and sum_s omega(s) s_i with the
 // combined weight omega = sum_b (g_b beta_b / Z_b) exp(-beta_b (E - E0)).
-// Inside a block the low spins take all 64 configurations, so the block
-// contributes the order <= 2 Walsh coefficients of omega over those spins
-// (total, 6 singles, 15 pairs); they are built hierarchically while the block
-// is walked (halves of a group differ in one spin).  Prefix spins are constant
-// per lane and high spins constant per block, so:
+// omega is formed for each of the 64 states of a block from the factors, and
+// the block contributes the order <= 2 Walsh coefficients of omega over the
+// low spins (total, 6 singles, 15 pairs), built hierarchically over the Gray
+// order of the block (the halves of a group differ in one spin).  Prefix spins
+// are constant per lane and high spins constant per block, so:
 //   prefix-involving moments  <- per-lane fp64 totals (Omega, A_f, M_g) times
 //                                prefix signs, reduced at the end of the lane;
 //   free x free pairs         <- per-block wave sums of the 22 coefficients
@@ -37,27 +45,51 @@ namespace sg {
 
 constexpr int kLzHigh = kLzFree - kU;
 constexpr int kNCoef = 22;   // 1 + 6 + 15 order <= 2 Walsh coefficients over U = 6
+// per beta: bq by configuration x, then by Gray step i for block parity 0 and 1
+constexpr int kLzQ = 3 * kBlockSteps;
 
 // ------------------------------------------------------------------ prep
+// One workgroup per instance: the low-low energies Q(x), their minimum, the
+// bq tables of every beta, the accumulators cleared, E0 (forward) or the
+// combined gradient weights g_b beta_b / Z~_b (backward).
 
 template <int kMode>
-__global__ void k_lz_prep(LzArgs a, const float* __restrict__ J, double* q64,
+__global__ void k_lz_prep(LzArgs a, const float* __restrict__ J, float* lzq, double* lzqmin,
                           const float* energies, float* e0_out, const double* logz,
                           const double* grad) {
+  __shared__ double s_q[kBlockSteps];
+  __shared__ double s_qmin;
   const int b = blockIdx.x;
   const int N = a.N;
   const float* Jb = J + (size_t)b * N * N;
   const int tid = threadIdx.x;
-  if (tid < 2 * kBlockSteps) {
-    const int par = tid / kBlockSteps, i = tid % kBlockSteps;
-    const uint32_t x = (uint32_t)(i ^ (i >> 1)) ^ ((uint32_t)par << (kU - 1));
+  if (tid < kBlockSteps) {
     double q = 0.0;
     for (int f = 0; f < kU; ++f)
       for (int g = f + 1; g < kU; ++g) {
-        const double sf = ((x >> f) & 1u) ? 1.0 : -1.0, sg = ((x >> g) & 1u) ? 1.0 : -1.0;
+        const double sf = ((tid >> f) & 1) ? 1.0 : -1.0, sg = ((tid >> g) & 1) ? 1.0 : -1.0;
         q -= (double)Jb[f * N + g] * sf * sg;
       }
-    q64[(size_t)b * 2 * kBlockSteps + tid] = q;
+    s_q[tid] = q;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double m = s_q[0];
+    for (int x = 1; x < kBlockSteps; ++x) m = fmin(m, s_q[x]);
+    s_qmin = m;
+    lzqmin[b] = m;
+  }
+  __syncthreads();
+  const double qmin = s_qmin;
+  for (int e = tid; e < a.nb * kLzQ; e += blockDim.x) {
+    const int k = e / kLzQ, r = e - k * kLzQ;
+    int x = r;
+    if (r >= kBlockSteps) {
+      const int i = r & (kBlockSteps - 1);
+      x = (i ^ (i >> 1)) ^ ((r >= 2 * kBlockSteps) ? (1 << (kU - 1)) : 0);
+    }
+    const double bk = (double)a.beta[k];
+    lzq[((size_t)b * kMaxBeta + k) * kLzQ + r] = (float)exp(-bk * (s_q[x] - qmin));
   }
   double* acc = a.acc + (size_t)b * a.acc_stride;
   for (int k = tid; k < a.acc_stride; k += blockDim.x) acc[k] = 0.0;
@@ -96,33 +128,22 @@ struct Coefs {
 
 constexpr int pidx(int f, int g) { return g * (g - 1) / 2 + f; }
 
+template <int NB>
 struct BlockWalk {
-  double& D;             // chain: G - E0 of the current state (fp64)
-  const double* W;       // [U] low fields of this block, sign of U-1 folded in
-  const double* q;       // [64] low-low energies of this block's parity
-  const float* c;        // [kMaxBeta] -beta / ln 2
-  const float* w;        // [kMaxBeta] combined weights a_b
-  int nb;
+  const float (*A)[8];   // [NB][8] factor products of spins 0-2, times the beta's weight
+  const float (*B)[8];   // [NB][8] factor products of spins 3-5, indexed by the Gray
+                         // code's bits (block parity folded in)
+  const float* const* bq;  // [NB] -> bq by Gray step for this block's parity
   float sgn5;            // value of spin U-1 in the block's first half
 
-  __device__ inline float weight(float x) const {
+  // combined weight of Gray step I of the block
+  template <int I>
+  __device__ inline float step() const {
+    constexpr int g = I ^ (I >> 1);
     float om = 0.0f;
 #pragma unroll
-    for (int k = 0; k < kMaxBeta; ++k)
-      if (k < nb) om = fmaf(w[k], __builtin_amdgcn_exp2f(c[k] * x), om);
+    for (int k = 0; k < NB; ++k) om = fmaf(A[k][g & 7] * B[k][g >> 3], bq[k][I], om);
     return om;
-  }
-
-  // state I of the block: step the chain to it (I > 0), return its weight
-  template <int I>
-  __device__ inline float step() {
-    if (I > 0) {
-      constexpr int f = __builtin_ctz(I > 0 ? I : 1);
-      if (f == kU - 1) D = D + W[f];
-      else if ((I >> (f + 1)) & 1) D = D + W[f];
-      else D = D - W[f];
-    }
-    return weight((float)(D + q[I]));
   }
 
   template <int K, int I0>
@@ -197,20 +218,38 @@ __device__ inline void lz_slot(int s, int H, int N, int* coef, uint32_t* mask, i
 
 // ------------------------------------------------------------------ walk
 
-template <int kMode>
+// Factor products of three spins: out[x] = prod_{j<3} (bit j of x ? cp[j] : cm[j]).
+__device__ inline void triple_products(const float* cp, const float* cm, float* out) {
+  const float t00 = cm[0] * cm[1], t10 = cp[0] * cm[1], t01 = cm[0] * cp[1], t11 = cp[0] * cp[1];
+  out[0] = t00 * cm[2]; out[1] = t10 * cm[2]; out[2] = t01 * cm[2]; out[3] = t11 * cm[2];
+  out[4] = t00 * cp[2]; out[5] = t10 * cp[2]; out[6] = t01 * cp[2]; out[7] = t11 * cp[2];
+}
+
+// 2^x for any finite x in fp64 range: 2^n (n integer) times 2^f, f in [0, 1).
+__device__ inline double exp2_wide(double x) {
+  const double n = floor(x);
+  const float f = (float)(x - n);
+  const int ni = (int)fmin(fmax(n, -2000.0), 2000.0);
+  return ldexp((double)__builtin_amdgcn_exp2f(f), ni);
+}
+
+template <int kMode, int NB>
 __global__ __launch_bounds__(256) void k_logz(LzArgs a, const float* __restrict__ J,
                                               const float* __restrict__ h,
                                               const double* __restrict__ table64,
-                                              const double* __restrict__ q64, int bpi) {
+                                              const float* __restrict__ lzq,
+                                              const double* __restrict__ lzqmin, int bpi) {
   constexpr int U = kU;
   __shared__ double s_y[kLzHigh * 256];
   __shared__ float s_c[kMode ? 4 * kNCoef * 64 : 1];
   __shared__ float s_t[kMode ? 4 * kNCoef : 1];
+  __shared__ float s_bq[NB * kLzQ];  // this instance's bq tables (uniform reads)
 
   const int b = blockIdx.x / bpi;
   const int blk = blockIdx.x - b * bpi;
   const int tid = threadIdx.x;
   const int N = a.N, n = a.n, H = n - U;
+  for (int e = tid; e < NB * kLzQ; e += 256) s_bq[e] = lzq[(size_t)b * kMaxBeta * kLzQ + e];
   const int64_t lane = (int64_t)blk * 256 + tid;
   const bool valid = lane < a.lanes;
   const uint64_t p = valid ? (uint64_t)lane : 0ull;
@@ -218,9 +257,9 @@ __global__ __launch_bounds__(256) void k_logz(LzArgs a, const float* __restrict_
   const float* ht = h + (size_t)b * N;
   const double* tab = table64 + ((size_t)b * a.table_recs + (size_t)a.table_offset) * 8;
 
-  // ---- per-lane init (fp64)
-  double WL[U];
-  double ysum = 0.0;
+  // ---- per-lane init (fp64): y_f = sum_q J_fq s_q, the field on free spin f
+  // from the prefix spins q >= n; E_P the energy of the prefix spins alone
+  double y[U];
 #pragma unroll
   for (int f = 0; f < U; ++f) {
     double acc = 0.0;
@@ -228,8 +267,7 @@ __global__ __launch_bounds__(256) void k_logz(LzArgs a, const float* __restrict_
       const double jq = (double)Jt[f * N + q];
       acc += ((p >> (q - n)) & 1ull) ? jq : -jq;
     }
-    ysum += acc;
-    WL[f] = 2.0 * acc;
+    y[f] = acc;
   }
   for (int f = U; f < n; ++f) {
     double acc = 0.0;
@@ -237,8 +275,7 @@ __global__ __launch_bounds__(256) void k_logz(LzArgs a, const float* __restrict_
       const double jq = (double)Jt[f * N + q];
       acc += ((p >> (q - n)) & 1ull) ? jq : -jq;
     }
-    ysum += acc;
-    s_y[(f - U) * 256 + tid] = 2.0 * acc;
+    s_y[(f - U) * 256 + tid] = acc;
   }
   double EP = 0.0;
   for (int q = n; q < N; ++q) {
@@ -250,20 +287,22 @@ __global__ __launch_bounds__(256) void k_logz(LzArgs a, const float* __restrict_
     }
     EP -= sq * f;
   }
-  // invalid lanes: a huge shifted energy makes every weight 0
-  double D = valid ? EP + ysum + tab[1] - (double)a.e0[b] : 1e30;
-
-  float cb[kMaxBeta], wb[kMaxBeta];
+  // E_P - sum_{f<U} s_f y_f at a block start: low spins all -1, except spin
+  // U-1 = +1 in odd blocks
+  double ylo = 0.0;
 #pragma unroll
-  for (int k = 0; k < kMaxBeta; ++k) {
-    const bool on = k < a.nb;
-    cb[k] = on ? -a.beta[k] * 1.4426950408889634f : 0.0f;
-    wb[k] = kMode == 0 ? 1.0f : (on ? (float)a.coef[(size_t)b * kMaxBeta + k] : 0.0f);
-  }
-  const double* qb0 = q64 + (size_t)b * 2 * kBlockSteps;
+  for (int f = 0; f < U - 1; ++f) ylo += y[f];
+  const double epa0 = EP + ylo + y[U - 1], epa1 = EP + ylo - y[U - 1];
+  const double base = lzqmin[b] - (double)a.e0[b];
+
+  double c2[NB];   // -beta / ln 2
+#pragma unroll
+  for (int k = 0; k < NB; ++k) c2[k] = -(double)a.beta[k] * 1.4426950408889634;
 
   // per-lane totals
-  double L[kMaxBeta] = {0.0, 0.0, 0.0, 0.0};  // forward
+  double L[NB];                                 // forward
+#pragma unroll
+  for (int k = 0; k < NB; ++k) L[k] = 0.0;
   double Om = 0.0, A[U], M[kLzHigh];            // backward
 #pragma unroll
   for (int f = 0; f < U; ++f) A[f] = 0.0;
@@ -280,45 +319,89 @@ __global__ __launch_bounds__(256) void k_logz(LzArgs a, const float* __restrict_
     for (int r = 0; r < 2; ++r)
       if (ln + 64 * r < nslots) lz_slot(ln + 64 * r, H, N, &sc[r], &sm[r], &st[r]);
   }
-  __syncthreads();  // s_y
+  __syncthreads();  // s_y, s_bq
 
   const uint32_t nblocks = 1u << (n - U);
   for (uint32_t T = 0; T < nblocks; ++T) {
+    // the bq tables are re-read from LDS every block instead of being held in
+    // registers for the whole lane
+    asm volatile("" ::: "memory");
     const double* rec = tab + (size_t)T * 8;
-    if (T != 0) {
-      const int c = __builtin_ctz(T);
-      const bool up = (T >> (c + 1)) & 1u;
-      const double y = s_y[c * 256 + tid];
-      D = up ? D + y : D - y;
-      D = D + rec[0];
+    const bool odd = T & 1u;
+    const uint32_t xh = T ^ (T >> 1);  // high spins of this block (bit k: spin U + k)
+    // energy at the block start without the low-low part, from scratch
+    double G0 = (odd ? epa1 : epa0) + rec[1];
+    for (int k = 0; k < H; ++k) {
+      const double yg = s_y[k * 256 + tid];
+      G0 = ((xh >> k) & 1u) ? G0 - yg : G0 + yg;
     }
-    double W[U];
+    // phi_f: coefficient of s_f (f < U) in the block's energy
+    double phi[U];
 #pragma unroll
-    for (int f = 0; f < U - 1; ++f) W[f] = WL[f] + rec[2 + f];
-    W[U - 1] = ((T & 1u) ? WL[U - 1] : -WL[U - 1]) + rec[2 + U - 1];
-    const double* qb = qb0 + (T & 1u) * kBlockSteps;
+    for (int f = 0; f < U - 1; ++f) phi[f] = -(y[f] + 0.5 * rec[2 + f]);
+    phi[U - 1] = -(y[U - 1] + 0.5 * (odd ? rec[2 + U - 1] : -rec[2 + U - 1]));
+    double K = odd ? G0 - phi[U - 1] : G0 + phi[U - 1];
+    double sabs = 0.0;
+#pragma unroll
+    for (int f = 0; f < U; ++f) {
+      if (f < U - 1) K += phi[f];
+      sabs += fabs(phi[f]);
+    }
+    const double Lb = K - sabs + base;  // lower bound of E - E0 over the block
+
+    float Af[NB][8], Bf[NB][8];
+    double P[NB];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+      P[k] = valid ? exp2_wide(c2[k] * Lb) : 0.0;
+      float cp[U], cm[U];
+#pragma unroll
+      for (int f = 0; f < U; ++f) {
+        const float af = __builtin_amdgcn_exp2f((float)(c2[k] * 2.0 * fabs(phi[f])));
+        cp[f] = phi[f] > 0.0 ? af : 1.0f;
+        cm[f] = phi[f] > 0.0 ? 1.0f : af;
+      }
+      triple_products(cp, cm, Af[k]);
+      triple_products(cp + 3, cm + 3, Bf[k]);
+    }
 
     if (kMode == 0) {
-      float sb[kMaxBeta] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-      for (int i = 0; i < kBlockSteps; ++i) {
-        if (i > 0) {
-          const int f = __builtin_ctz(i);
-          if (f == U - 1) D = D + W[f];
-          else D = ((i >> (f + 1)) & 1) ? D + W[f] : D - W[f];
+      for (int k = 0; k < NB; ++k) {
+        const float* q = s_bq + k * kLzQ;  // bq by configuration
+        float S = 0.0f;
+#pragma unroll
+        for (int x2 = 0; x2 < 8; ++x2) {
+          float u = 0.0f;
+#pragma unroll
+          for (int x1 = 0; x1 < 8; ++x1) u = fmaf(Af[k][x1], q[x1 + 8 * x2], u);
+          S = fmaf(Bf[k][x2], u, S);
         }
-        const float x = (float)(D + qb[i]);
-#pragma unroll
-        for (int k = 0; k < kMaxBeta; ++k)
-          if (k < a.nb) sb[k] += __builtin_amdgcn_exp2f(cb[k] * x);
+        L[k] += P[k] * (double)S;
       }
-#pragma unroll
-      for (int k = 0; k < kMaxBeta; ++k) L[k] += (double)sb[k];
     } else {
-      BlockWalk bw{D, W, qb, cb, wb, a.nb, (T & 1u) ? 1.0f : -1.0f};
-      const Coefs C = bw.walk<U, 0>();
+      // fold the beta's weight into A and the block parity into B: Gray step
+      // i has spins 3-5 at bits 3-5 of gray(i), with spin 5 flipped in odd
+      // blocks
+      const float* bqs[NB];
+#pragma unroll
+      for (int k = 0; k < NB; ++k) {
+        const float sk = (float)(a.coef[(size_t)b * kMaxBeta + k] * P[k]);
+#pragma unroll
+        for (int x1 = 0; x1 < 8; ++x1) Af[k][x1] *= sk;
+        if (odd) {
+#pragma unroll
+          for (int x2 = 0; x2 < 4; ++x2) {
+            const float t = Bf[k][x2];
+            Bf[k][x2] = Bf[k][x2 + 4];
+            Bf[k][x2 + 4] = t;
+          }
+        }
+        bqs[k] = s_bq + k * kLzQ + kBlockSteps * (odd ? 2 : 1);
+      }
+      BlockWalk<NB> bw{Af, Bf, bqs, odd ? 1.0f : -1.0f};
+      const Coefs C = bw.template walk<U, 0>();
       // per-lane totals for the prefix-involving moments
-      const uint32_t xh = T ^ (T >> 1);  // high spins of this block
       Om += (double)C.o;
 #pragma unroll
       for (int f = 0; f < U; ++f) A[f] += (double)C.s[f];
@@ -366,11 +449,9 @@ __global__ __launch_bounds__(256) void k_logz(LzArgs a, const float* __restrict_
   const bool lead = ln == 0;
   if (kMode == 0) {
 #pragma unroll
-    for (int k = 0; k < kMaxBeta; ++k) {
-      if (k < a.nb) {
-        const double t = wave_sum(L[k]);
-        if (lead) atomicAdd(acc + k, t);
-      }
+    for (int k = 0; k < NB; ++k) {
+      const double t = wave_sum(L[k]);
+      if (lead) atomicAdd(acc + k, t);
     }
     return;
   }
@@ -443,26 +524,37 @@ __global__ void k_lz_final_bwd(LzArgs a, float* grad_J, float* grad_h) {
 
 // ---------------------------------------------------------------- launchers
 
-hipError_t launch_lz_prep(int mode, const LzArgs& a, const float* J, double* q64,
+hipError_t launch_lz_prep(int mode, const LzArgs& a, const float* J, float* lzq, double* lzqmin,
                           const float* energies, float* e0_out, const double* logz,
                           const double* grad, hipStream_t st) {
   if (mode == 0)
-    hipLaunchKernelGGL(k_lz_prep<0>, dim3(a.B), dim3(256), 0, st, a, J, q64, energies, e0_out,
-                       logz, grad);
+    hipLaunchKernelGGL(k_lz_prep<0>, dim3(a.B), dim3(256), 0, st, a, J, lzq, lzqmin, energies,
+                       e0_out, logz, grad);
   else
-    hipLaunchKernelGGL(k_lz_prep<1>, dim3(a.B), dim3(256), 0, st, a, J, q64, energies, e0_out,
-                       logz, grad);
+    hipLaunchKernelGGL(k_lz_prep<1>, dim3(a.B), dim3(256), 0, st, a, J, lzq, lzqmin, energies,
+                       e0_out, logz, grad);
   return hipGetLastError();
 }
 
 hipError_t launch_logz(int mode, const LzArgs& a, const float* J, const float* h,
-                       const double* table64, const double* q64, hipStream_t st) {
+                       const double* table64, const float* lzq, const double* lzqmin,
+                       hipStream_t st) {
   const int bpi = (int)((a.lanes + 255) / 256);
   const dim3 grid((unsigned)((int64_t)bpi * a.B));
-  if (mode == 0)
-    hipLaunchKernelGGL(k_logz<0>, grid, dim3(256), 0, st, a, J, h, table64, q64, bpi);
-  else
-    hipLaunchKernelGGL(k_logz<1>, grid, dim3(256), 0, st, a, J, h, table64, q64, bpi);
+#define SG_LZ_LAUNCH(M, NBV)                                                                   \
+  hipLaunchKernelGGL((k_logz<M, NBV>), grid, dim3(256), 0, st, a, J, h, table64, lzq, lzqmin, bpi)
+  switch (mode * 8 + a.nb) {
+    case 1: SG_LZ_LAUNCH(0, 1); break;
+    case 2: SG_LZ_LAUNCH(0, 2); break;
+    case 3: SG_LZ_LAUNCH(0, 3); break;
+    case 4: SG_LZ_LAUNCH(0, 4); break;
+    case 9: SG_LZ_LAUNCH(1, 1); break;
+    case 10: SG_LZ_LAUNCH(1, 2); break;
+    case 11: SG_LZ_LAUNCH(1, 3); break;
+    case 12: SG_LZ_LAUNCH(1, 4); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef SG_LZ_LAUNCH
   return hipGetLastError();
 }
 

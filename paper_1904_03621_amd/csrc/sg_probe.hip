@@ -27,7 +27,10 @@ constexpr int kProbeThreads = 256;
   X(10, "v_min_i32 %0, %0, %1")                         \
   X(11, "v_sub_f32 %0, %1, %0")                         \
   X(12, "v_and_or_b32 %0, %0, %1, %2")                  \
-  X(13, "v_med3_f32 %0, %0, %1, %2")
+  X(13, "v_med3_f32 %0, %0, %1, %2")                    \
+  X(14, "v_pk_add_u16 %0, %0, %1")                      \
+  X(15, "v_pk_min_i16 %0, %0, %1")                      \
+  X(16, "v_exp_f32 %0, %1")
 
 template <int kOp>
 __global__ __launch_bounds__(kProbeThreads) void k_probe(uint32_t seed, uint32_t* out) {

@@ -178,3 +178,35 @@ def test_overflowing_level_is_walked_again(orc, torch_dev):
         k = len(om)
         check_f32(n, J[b, :n, :n], bm[b, :k], be[b, :k], om, oe,
                   lambda x: orc.energy(J[b, :n, :n], h[b, :n], x), "instance %d" % b)
+
+
+def test_full_workload_4096(orc, torch_dev):
+    """The full batch: 4096 instances, N_b uniform in [16, 32], J ~ N(0,1)
+    unscaled, h ~ N(0, 0.1^2), S = 64, the launch configuration the benchmark
+    times.  Every instance bit for bit against the single-instance search;
+    instances with N_b <= 22 (sampled) against the oracle."""
+    import paper_1904_03621_amd as sg
+    torch = torch_dev
+    w = I.workload("batch4096")
+    Ns, J, h, S = w["Ns"], w["J"], w["h"], w["S"]
+    B = len(Ns)
+    bm, be = run_batched(torch, Ns, J, h, S)
+    # one single-instance call per instance, all on one stream
+    Jb = [torch.from_numpy(np.ascontiguousarray(J[b, :Ns[b], :Ns[b]])).cuda() for b in range(B)]
+    hb = [torch.from_numpy(np.ascontiguousarray(h[b, :Ns[b]])).cuda() for b in range(B)]
+    sm = torch.empty((B, S), dtype=torch.int64, device="cuda")
+    se = torch.empty((B, S), dtype=torch.float32, device="cuda")
+    for b in range(B):
+        assert sg.sg_low_spectrum_f32(int(Ns[b]), Jb[b], hb[b], S, sm[b], se[b]) == 0
+    assert sg.sg_get_error() == 0
+    sm = sm.cpu().numpy().astype(np.uint64)
+    se = se.cpu().numpy()
+    diff = [b for b in range(B) if not (np.array_equal(sm[b], bm[b]) and np.array_equal(se[b], be[b]))]
+    assert not diff, "instances differing from the single search: %s" % diff[:10]
+    small = [b for b in range(B) if Ns[b] <= 22][::50]
+    assert len(small) >= 8
+    for b in small:
+        n = int(Ns[b])
+        om, oe = orc.low_spectrum(J[b, :n, :n], h[b, :n], S)
+        check_f32(n, J[b, :n, :n], bm[b], be[b], om, oe,
+                  lambda x: orc.energy(J[b, :n, :n], h[b, :n], x), "instance %d" % b)

@@ -245,3 +245,40 @@ def test_errors(torch_dev):
     # the stream is clean again
     lz, _, _, _ = sg.logz_forward(Jt, ht, torch.ones(1, device="cuda"), 4)
     assert np.all(np.isfinite(lz.cpu().numpy()))
+
+
+def test_gauge_and_permutation_invariance_n32(torch_dev):
+    """Beyond the oracle's reach (N = 32): a gauge transform J'_ij = t_i t_j J_ij,
+    h'_i = t_i h_i (t_i = +-1) and a relabelling of the spins leave log Z
+    unchanged and map the gradients the same way."""
+    import paper_1904_03621_amd as sg
+    torch = torch_dev
+    B, N = 2, 32
+    J, h = I.logz_batch(B, N, 32)
+    rng = np.random.default_rng(5)
+    t = rng.choice(np.array([-1.0, 1.0]), size=(B, N))
+    perm = np.stack([rng.permutation(N) for _ in range(B)])
+    Jg = np.zeros_like(J)
+    hg = np.zeros_like(h)
+    for b in range(B):
+        full = J[b].astype(np.float64) + J[b].astype(np.float64).T
+        fg = full * np.outer(t[b], t[b])
+        fp = fg[np.ix_(perm[b], perm[b])]
+        Jg[b] = np.triu(fp, 1).astype(np.float32)
+        hg[b] = (h[b] * t[b])[perm[b]].astype(np.float32)
+    g = np.array([[1.0, -0.5, 0.25], [0.3, 0.3, 0.3]])
+    lz, _, _, _ = gpu_forward(torch, J, h, BETAS, 16)
+    lz2, _, _, _ = gpu_forward(torch, Jg, hg, BETAS, 16)
+    assert np.all(np.abs(lz - lz2) <= 1e-6 * np.abs(lz)), (lz, lz2)
+    gJ, gh = gpu_backward(torch, J, h, BETAS, g)
+    gJ2, gh2 = gpu_backward(torch, Jg, hg, BETAS, g)
+    for b in range(B):
+        # map the transformed gradients back to the original labels and signs
+        fullg2 = gJ2[b] + gJ2[b].T
+        back = np.zeros((N, N))
+        back[np.ix_(perm[b], perm[b])] = fullg2
+        back *= np.outer(t[b], t[b])
+        hb = np.zeros(N)
+        hb[perm[b]] = gh2[b]
+        hb *= t[b]
+        check_grad(np.triu(back, 1), hb, gJ[b], gh[b], "gauge/permutation b=%d" % b)
