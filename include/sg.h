@@ -29,7 +29,12 @@
  *   - The library owns a per-(device, stream) workspace that it allocates on
  *     first use and grows when a call needs more; it is released at process
  *     exit.  Calls on one stream are ordered; calls on different streams use
- *     different workspaces and may run concurrently.
+ *     different workspaces and may run concurrently.  Two host threads must
+ *     not issue calls on the same stream at the same time.
+ *   - SG_ECAPACITY: a chunk whose candidates overflow the buffer is walked
+ *     again (up to two more times) with the threshold its partial merge
+ *     tightened; the error is reported only if the last pass still
+ *     overflows (extreme near-degeneracy).
  */
 #ifndef SG_H
 #define SG_H

@@ -493,8 +493,8 @@ sg_status lz_buffers(Workspace* w, int B, int N) {
   return SG_OK;
 }
 
-LzArgs lz_args(Workspace* w, int B, int N, int nb, int S, const float* beta, const float* e0,
-               int mode) {
+LzArgs lz_args(Workspace* w, int B, int N, int nb, int S, const float* h, const float* beta,
+               const float* e0, int mode) {
   LzArgs a{};
   a.B = B;
   a.N = N;
@@ -507,6 +507,7 @@ LzArgs lz_args(Workspace* w, int B, int N, int nb, int S, const float* beta, con
   a.lanes = (int64_t)1 << (N - a.n);
   a.table_recs = (int64_t)table_records(a.n);
   a.table_offset = (1 << (a.n - kU)) - 1;
+  a.h_in = h;
   a.beta = beta;
   a.e0 = e0;
   a.coef = w->lz_coef;
@@ -600,7 +601,7 @@ sg_status sg_logz_forward_f32(int B, int N, const float* J, const float* h, int 
   v = batch_search(w, false, bt, N, ncap, states_out, energies_out, st);
   if (v != SG_OK) return v;
   // 2. partition sums shifted by E0
-  const LzArgs a = lz_args(w, B, N, n_beta, S, beta, e0_out, 0);
+  const LzArgs a = lz_args(w, B, N, n_beta, S, h, beta, e0_out, 0);
   Batch b64 = bt;
   b64.table_recs = a.table_recs;
   HIP_TRY(launch_tables64(b64, a.n, w->table64, st));
@@ -625,7 +626,7 @@ sg_status sg_logz_backward_f32(int B, int N, const float* J, const float* h, int
   if (v != SG_OK) return v;
   v = lz_buffers(w, B, N);
   if (v != SG_OK) return v;
-  const LzArgs a = lz_args(w, B, N, n_beta, 1, beta, e0, 1);
+  const LzArgs a = lz_args(w, B, N, n_beta, 1, h, beta, e0, 1);
   Batch b64 = make_batch(w, J, h, nullptr, N, N, B, 1, a.table_recs, 1);
   HIP_TRY(launch_tables64(b64, a.n, w->table64, st));
   HIP_TRY(launch_lz_prep(1, a, J, w->lzq, w->lzqmin, nullptr, nullptr, logz, grad_logz, st));

@@ -109,6 +109,7 @@ struct LzArgs {
   int64_t lanes;        // lanes per instance: 2^(N - n)
   int64_t table_recs;   // fp64 records per instance
   int table_offset;     // first record of the table of n
+  const float* h_in;    // [B][N] fields
   const float* beta;    // [nb]
   const float* e0;      // [B] shift (ground energy)
   double* coef;         // [B][kMaxBeta]: backward weights g_b beta_b / Z_b

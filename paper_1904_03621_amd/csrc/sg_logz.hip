@@ -93,6 +93,13 @@ __global__ void k_lz_prep(LzArgs a, const float* __restrict__ J, float* lzq, dou
   }
   double* acc = a.acc + (size_t)b * a.acc_stride;
   for (int k = tid; k < a.acc_stride; k += blockDim.x) acc[k] = 0.0;
+  // non-finite couplings or fields (the forward's search reports them too)
+  bool bad = false;
+  for (int k = tid; k < N * N + N; k += blockDim.x) {
+    const float v = k < N * N ? Jb[k] : a.h_in[(size_t)b * N + (k - N * N)];
+    if (k >= N * N || (k / N) < (k % N)) bad = bad || !isfinite(v);
+  }
+  if (bad) atomicOr(a.sticky, kErrNonFinite);
   if (tid == 0) {
     for (int k = 0; k < a.nb; ++k) {
       const float bk = a.beta[k];

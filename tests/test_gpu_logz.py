@@ -243,8 +243,15 @@ def test_errors(torch_dev):
         sg.logz_forward(*to_dev(torch, J5, h5), torch.ones(1, device="cuda"), 4)
     assert ei.value.status == _lib.SG_EINVAL
     # the stream is clean again
-    lz, _, _, _ = sg.logz_forward(Jt, ht, torch.ones(1, device="cuda"), 4)
+    lz, e0, _, _ = sg.logz_forward(Jt, ht, torch.ones(1, device="cuda"), 4)
     assert np.all(np.isfinite(lz.cpu().numpy()))
+    # a NaN coupling handed to the backward alone is reported too
+    Jn = J.copy()
+    Jn[1, 2, 5] = np.nan
+    with pytest.raises(sg.SgError) as ei:
+        sg.logz_backward(to_dev(torch, Jn)[0], ht, torch.ones(1, device="cuda"), e0, lz,
+                         torch.ones((2, 1), dtype=torch.float64, device="cuda"))
+    assert ei.value.status == _lib.SG_ENONFINITE
 
 
 def test_gauge_and_permutation_invariance_n32(torch_dev):
