@@ -129,6 +129,7 @@ struct Workspace {
   uint32_t* table = nullptr;
   size_t ntable = 0;
   uint64_t* cand = nullptr;
+  uint32_t* ckey = nullptr;
   uint32_t* skey = nullptr;
   uint64_t* smask = nullptr;
   size_t ncand = 0;
@@ -240,8 +241,9 @@ sg_status ws_get(hipStream_t st, int B, size_t recs, size_t cap, int S, Workspac
   HIP_TRY(grow(&w->qtab, &w->nq, Bz * 2 * kBlockSteps));
   HIP_TRY(grow(&w->table, &w->ntable, Bz * recs * kRecWords));
   if (w->ncand < Bz * cap) {
-    size_t have_s = w->ncand, have_m = w->ncand;
+    size_t have_s = w->ncand, have_m = w->ncand, have_c = w->ncand;
     HIP_TRY(grow(&w->cand, &w->ncand, Bz * cap));
+    HIP_TRY(grow(&w->ckey, &have_c, Bz * cap));
     HIP_TRY(grow(&w->skey, &have_s, Bz * cap));
     HIP_TRY(grow(&w->smask, &have_m, Bz * cap));
   }
@@ -271,6 +273,7 @@ Batch make_batch(Workspace* w, const void* J, const void* h, const int32_t* Ns, 
   bt.table = w->table;
   bt.table_recs = recs;
   bt.cand = w->cand;
+  bt.ckey = w->ckey;
   bt.skey = w->skey;
   bt.smask = w->smask;
   bt.cap = cap;

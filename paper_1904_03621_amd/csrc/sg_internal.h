@@ -89,7 +89,8 @@ struct Batch {
   uint32_t* qtab;      // [B][2 * kBlockSteps]
   uint32_t* table;     // [B][table_recs][kRecWords]
   int64_t table_recs;
-  uint64_t* cand;      // [B][cap]
+  uint64_t* cand;      // [B][cap] candidate masks
+  uint32_t* ckey;      // [B][cap] orderable key of each candidate's walk energy
   uint32_t* skey;      // [B][cap]
   uint64_t* smask;     // [B][cap]
   uint32_t cap;

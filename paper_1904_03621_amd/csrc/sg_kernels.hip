@@ -89,8 +89,10 @@ __device__ inline bool key_less(uint32_t ka, uint64_t ma, uint32_t kb, uint64_t 
   return ka < kb || (ka == kb && ma < mb);
 }
 
-// Wave-aggregated append of one mask per active lane.
-__device__ inline void append_mask(uint64_t mask, Params* P, uint64_t* cand, uint32_t cap) {
+// Wave-aggregated append of one mask (and the orderable key of the energy
+// the walk computed for it) per active lane.
+__device__ inline void append_mask(uint64_t mask, uint32_t key, Params* P, uint64_t* cand,
+                                   uint32_t* ckey, uint32_t cap) {
   const uint64_t act = __ballot(1);
   const int lid = __lane_id();
   const int leader = __ffsll((unsigned long long)act) - 1;
@@ -102,7 +104,10 @@ __device__ inline void append_mask(uint64_t mask, Params* P, uint64_t* cand, uin
   const uint32_t slot = base + (uint32_t)__popcll(below);
   // beyond cap the mask is dropped; the merge sees cand_count > cap and asks
   // for another pass over the chunk
-  if (slot < cap) cand[slot] = mask;
+  if (slot < cap) {
+    cand[slot] = mask;
+    ckey[slot] = key;
+  }
 }
 
 // ------------------------------------------------------------------ k_prep
@@ -389,6 +394,7 @@ __global__ __launch_bounds__(kEnumBlock, 8) void k_enum(Batch bt, const void* __
   const uint32_t* tab =
       table + ((size_t)b * bt.table_recs + (size_t)ch.table_offset) * kRecWords;
   uint64_t* cand = bt.cand + (size_t)b * bt.cap;
+  uint32_t* ckey = bt.ckey + (size_t)b * bt.cap;
   const uint32_t cand_cap = bt.cap;
 
   const V* Jt = (const V*)Jv + (size_t)b * ld * ld;
@@ -564,7 +570,18 @@ __global__ __launch_bounds__(kEnumBlock, 8) void k_enum(Batch bt, const void* __
         hits &= hits - 1ull;
         const uint64_t t = ((uint64_t)T << U) | (uint64_t)i;
         const uint64_t mask = (pl << n) | (t ^ (t >> 1));
-        append_mask(mask, P, cand, cand_cap);
+        // the walk's energy of step i, from the block start: a low spin
+        // f < U-1 that is up at step i flipped an odd number of times from -1
+        // (net -W_f); spin U-1 flips once, at step 2^(U-1) (net +W_{U-1})
+        const uint32_t gi = (uint32_t)(i ^ (i >> 1));
+        V e = Gs;
+#pragma unroll
+        for (int f = 0; f < U - 1; ++f)
+          if ((gi >> f) & 1u) e = e - W[f];
+        if ((gi >> (U - 1)) & 1u) e = e + W[U - 1];
+        e = e + qv(i);
+        const uint32_t key = kInt ? key_of_i32((int32_t)e) : key_f32((float)e);
+        append_mask(mask, key, P, cand, ckey, cand_cap);
       }
     }
   }
@@ -588,7 +605,10 @@ __global__ void k_direct(Batch bt, uint64_t lo, uint64_t hi) {
   if (m >= hi) return;
   Params* P = bt.P;
   const uint32_t slot = atomicAdd(&P->cand_count, 1u);
-  if (slot < bt.cap) bt.cand[slot] = m;
+  if (slot < bt.cap) {
+    bt.cand[slot] = m;
+    bt.ckey[slot] = 0u;  // not used: the single search rescoring reads every candidate
+  }
 }
 
 // ------------------------------------------------- scoring and merging
@@ -787,8 +807,51 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge(Batch bt, int b, int re
              (uint32_t)kLdsSortCap);
 }
 
+// k-th smallest (1-based) of keys[0..cnt) for the whole workgroup: four
+// passes of 8-bit digits, most significant first, each a histogram in LDS and
+// a scan of its 256 bins.  Needs blockDim.x == 256.
+__device__ uint32_t radix_select(const uint32_t* keys, uint32_t cnt, uint32_t k, uint32_t* hist,
+                                 uint32_t* state) {
+  const uint32_t t = threadIdx.x;
+  uint32_t prefix = 0u, pmask = 0u, rem = k;
+  for (int shift = 24; shift >= 0; shift -= 8) {
+    hist[t] = 0u;
+    __syncthreads();
+    for (uint32_t j = t; j < cnt; j += blockDim.x) {
+      const uint32_t key = keys[j];
+      if ((key & pmask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    // inclusive scan of the 256 bins (Hillis-Steele)
+    uint32_t v = hist[t];
+    for (uint32_t o = 1; o < 256u; o <<= 1) {
+      const uint32_t add = t >= o ? hist[t - o] : 0u;
+      __syncthreads();
+      v += add;
+      hist[t] = v;
+      __syncthreads();
+    }
+    const uint32_t before = t == 0 ? 0u : hist[t - 1];
+    if (before < rem && rem <= v) {
+      state[0] = prefix | (t << shift);
+      state[1] = rem - before;
+    }
+    __syncthreads();
+    prefix = state[0];
+    rem = state[1];
+    pmask |= 255u << shift;
+    __syncthreads();
+  }
+  return prefix;
+}
+
 // Batch: one workgroup per instance scores its own candidates of the chunk
-// starting at first_mask, then merges the survivors into its record.
+// starting at first_mask, then merges the survivors into its record.  When
+// there are many candidates, only those whose walk energy is within twice the
+// margin of the S-th smallest walk energy are rescored: the walk energy is
+// within the margin of the exact one, so the S-th smallest exact energy of the
+// chunk is at most that S-th walk energy plus the margin, and no state at or
+// below it can have a walk energy beyond twice the margin.
 template <bool kInt>
 __global__ __launch_bounds__(kMergeBatchThreads) void k_merge_batched(Batch bt,
                                                                       uint64_t first_mask,
@@ -796,6 +859,8 @@ __global__ __launch_bounds__(kMergeBatchThreads) void k_merge_batched(Batch bt,
   __shared__ uint32_t l_key[kLdsSortCapBatch];
   __shared__ uint64_t l_mask[kLdsSortCapBatch];
   __shared__ uint32_t s_inst[kMaxN * kMaxN + kMaxN];
+  __shared__ uint32_t s_hist[kMergeBatchThreads];
+  __shared__ uint32_t s_sel[2];
   __shared__ uint32_t s_ns;
   const int b = blockIdx.x;
   const int N = inst_N(bt, b);
@@ -806,13 +871,25 @@ __global__ __launch_bounds__(kMergeBatchThreads) void k_merge_batched(Batch bt,
   if (threadIdx.x == 0) s_ns = 0;
   __syncthreads();
   const uint64_t* cand = bt.cand + (size_t)b * bt.cap;
+  const uint32_t* ckey = bt.ckey + (size_t)b * bt.cap;
   uint32_t* skey = bt.skey + (size_t)b * bt.cap;
   uint64_t* smask = bt.smask + (size_t)b * bt.cap;
   const uint32_t cnt = min(P->cand_count, bt.cap);
   const uint32_t thr_key = P->thr_key;
   const uint64_t thr_mask = P->thr_mask;
   const bool full = P->rec_count != 0 && thr_key != 0xFFFFFFFFu;
+  uint32_t sel = 0xFFFFFFFFu;  // rescore candidates whose walk key is <= sel
+  if (cnt > 2u * (uint32_t)bt.S + 256u) {
+    const uint32_t kf = radix_select(ckey, cnt, (uint32_t)bt.S, s_hist, s_sel);
+    if (kInt || P->margin == 0.0f) {
+      sel = kf;  // walk energies are exact
+    } else {
+      const float ef = __uint_as_float(bits_of_f32_key(kf));
+      sel = key_f32(f32_up((double)ef + 2.0 * (double)P->margin));
+    }
+  }
   for (uint32_t j = threadIdx.x; j < cnt; j += blockDim.x) {
+    if (ckey[j] > sel) continue;
     const uint64_t m = cand[j];
     const uint32_t key = exact_key<kInt>(s_inst, s_inst + N * N, N, N, m);
     bool keep = !full || key_less(key, m, thr_key, thr_mask);
