@@ -119,8 +119,8 @@ sg_status sg_low_spectrum_range_i32(int N, const int32_t *J, const int32_t *h, i
  * search as sg_low_spectrum_f32 / _i32 and gets the same result.
  *
  *   B            number of instances, >= 1
- *   N_dev        device int32[B]: spins of instance b, 6 <= N_b <= N_max
- *   N_max        largest N_b (row stride of J), 6 <= N_max <= 40
+ *   N_dev        device int32[B]: spins of instance b, 7 <= N_b <= N_max
+ *   N_max        largest N_b (row stride of J), 7 <= N_max <= 40
  *   J            device float[B][N_max][N_max] (int32 for _i32); instance b
  *                uses its leading N_b x N_b block, strict upper triangle
  *   h            device float[B][N_max]; instance b uses its first N_b
@@ -150,7 +150,7 @@ sg_status sg_low_spectrum_batched_i32(int B, const int32_t *N_dev, int N_max, co
  * with E0 the lowest energy, so that no weight exceeds 1.
  *
  *   B            number of instances, >= 1
- *   N            spins of every instance, 6 <= N <= 40
+ *   N            spins of every instance, 7 <= N <= 40
  *   J            device float[B][N][N], strict upper triangle read
  *   h            device float[B][N]
  *   n_beta       number of inverse temperatures, 1 <= n_beta <= 4

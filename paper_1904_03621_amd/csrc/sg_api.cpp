@@ -73,7 +73,9 @@ struct PlanChunk {
 // so that the expected number of candidates per chunk stays near S, until
 // the chunk reaches `fill` lanes of 2^nmax states; from then on chunks have
 // fill lanes each.  Every chunk is [first, first + L 2^n) with first a
-// multiple of 2^n, and lanes cover consecutive prefixes.
+// multiple of 2^n, and lanes cover consecutive prefixes.  Ends of the range
+// that are not multiples of a block (2^U states) form chunks with n = 0: one
+// thread per state, every state a candidate.
 std::vector<PlanChunk> plan_chunks(int N, int S, uint64_t lo, uint64_t hi, int64_t fill) {
   std::vector<PlanChunk> out;
   const int nmax = std::min(kMaxFree, N);
@@ -82,9 +84,13 @@ std::vector<PlanChunk> plan_chunks(int N, int S, uint64_t lo, uint64_t hi, int64
   uint64_t target = 4096;
   while (target < (uint64_t)S) target <<= 1;
   const uint64_t big = (uint64_t)fill << nmax;
-  uint64_t cur = lo;
-  while (cur < hi) {
-    const uint64_t rem = hi - cur;
+  const uint64_t blk = (uint64_t)kBlockSteps;
+  uint64_t lo_b = (lo + blk - 1) & ~(blk - 1), hi_b = hi & ~(blk - 1);
+  if (lo_b >= hi_b) lo_b = hi_b = hi;  // no whole block: one direct chunk
+  if (lo < lo_b) out.push_back(PlanChunk{lo, 0, (int64_t)(lo_b - lo)});
+  uint64_t cur = lo_b;
+  while (cur < hi_b) {
+    const uint64_t rem = hi_b - cur;
     PlanChunk c{};
     c.first_mask = cur;
     const uint64_t unit = (uint64_t)1 << nmax;
@@ -111,6 +117,7 @@ std::vector<PlanChunk> plan_chunks(int N, int S, uint64_t lo, uint64_t hi, int64
     cur += (uint64_t)c.lanes << c.n;
     target = std::max<uint64_t>(target, 2 * (cur - lo));
   }
+  if (hi_b < hi && cur < hi) out.push_back(PlanChunk{cur, 0, (int64_t)(hi - cur)});
   return out;
 }
 
@@ -285,7 +292,9 @@ Batch make_batch(Workspace* w, const void* J, const void* h, const int32_t* Ns, 
   return bt;
 }
 
+// Records of the concatenated per-block tables for n = U .. ncap.
 size_t table_records(int ncap) { return ((size_t)1 << (ncap - kU + 1)) - 1; }
+size_t lz_table_records(int ncap) { return ((size_t)1 << (ncap - kLzU + 1)) - 1; }
 
 // ------------------------------------------------------------------ search
 
@@ -335,44 +344,43 @@ sg_status run_search(bool isint, int N, const void* J, const void* h, int S, uin
 
   HIP_TRY(launch_prep(isint, bt, st));
   const int score_grid = std::max(1, w->cus) * 4;
-  int64_t nchunks = 0;
   int kmax = 0, nmaxu = 0;
   w->ev_used = 0;
   w->last_launches = 0;
-  if (N < kU) {
-    HIP_TRY(launch_direct(bt, lo, hi, st));
-    HIP_TRY(launch_score(isint, bt, 0, score_grid, N, 0, st));
-    HIP_TRY(launch_merge(bt, 0, 0, true, st));
-    nchunks = 1;
-    w->last_states = (double)(hi - lo);
-  } else {
-    HIP_TRY(launch_tables(isint, bt, ncap, st));
-    const std::vector<PlanChunk> plan = plan_chunks(N, S, lo, hi, w->fill[isint ? 1 : 0]);
-    double states = 0.0;
-    for (const PlanChunk& pc : plan) {
-      Chunk ch{};
-      ch.first_mask = pc.first_mask;
-      ch.prefix_base = pc.first_mask >> pc.n;
-      ch.lanes = pc.lanes;
-      ch.n = pc.n;
-      ch.table_offset = (1 << (pc.n - kU)) - 1;
-      // a chunk with more states than candidate slots may overflow: it gets
-      // up to kRetries repeated passes, each run only if the last overflowed
-      const uint64_t cstates = (uint64_t)pc.lanes << pc.n;
-      const int passes = cstates > (uint64_t)cap ? 1 + kRetries : 1;
-      for (int r = 0; r < passes; ++r) {
-        ch.retry = r;
-        HIP_TRY(enum_timed(w, isint, bt, ch, 1, st));
-        HIP_TRY(launch_score(isint, bt, 0, score_grid, N, r, st));
-        HIP_TRY(launch_merge(bt, 0, r, r == passes - 1, st));
-      }
-      states += (double)cstates;
-      kmax = std::max(kmax, N - pc.n);
-      nmaxu = std::max(nmaxu, pc.n);
+  if (N >= kU) HIP_TRY(launch_tables(isint, bt, ncap, st));
+  const std::vector<PlanChunk> plan = plan_chunks(N, S, lo, hi, w->fill[isint ? 1 : 0]);
+  double states = 0.0;
+  for (const PlanChunk& pc : plan) {
+    if (pc.n == 0) {
+      // a range end shorter than a block: one thread per state
+      HIP_TRY(launch_direct(bt, pc.first_mask, pc.first_mask + (uint64_t)pc.lanes, st));
+      HIP_TRY(launch_score(isint, bt, 0, score_grid, N, 0, st));
+      HIP_TRY(launch_merge(bt, 0, 0, true, st));
+      states += (double)pc.lanes;
+      continue;
     }
-    nchunks = (int64_t)plan.size();
-    w->last_states = states;
+    Chunk ch{};
+    ch.first_mask = pc.first_mask;
+    ch.prefix_base = pc.first_mask >> pc.n;
+    ch.lanes = pc.lanes;
+    ch.n = pc.n;
+    ch.table_offset = (1 << (pc.n - kU)) - 1;
+    // a chunk with more states than candidate slots may overflow: it gets
+    // up to kRetries repeated passes, each run only if the last overflowed
+    const uint64_t cstates = (uint64_t)pc.lanes << pc.n;
+    const int passes = cstates > (uint64_t)cap ? 1 + kRetries : 1;
+    for (int r = 0; r < passes; ++r) {
+      ch.retry = r;
+      HIP_TRY(enum_timed(w, isint, bt, ch, 1, st));
+      HIP_TRY(launch_score(isint, bt, 0, score_grid, N, r, st));
+      HIP_TRY(launch_merge(bt, 0, r, r == passes - 1, st));
+    }
+    states += (double)cstates;
+    kmax = std::max(kmax, N - pc.n);
+    nmaxu = std::max(nmaxu, pc.n);
   }
+  const int64_t nchunks = (int64_t)plan.size();
+  w->last_states = states;
   HIP_TRY(launch_finalize(isint, bt, states_out, energies_out, st));
   w->last_chunks = nchunks;
   w->last_kmax = kmax;
@@ -460,7 +468,7 @@ sg_status run_batched(bool isint, int B, const int32_t* Ns, int Nmax, const void
                       void* stream) {
   g_last_error.clear();
   if (B < 1) return fail(SG_EINVAL, "B must be >= 1");
-  if (Nmax < kU || Nmax > 40) return fail(SG_EINVAL, "N_max must be in [6, 40]");
+  if (Nmax < kU || Nmax > 40) return fail(SG_EINVAL, "N_max must be in [7, 40]");
   if (S < 1 || S > SG_MAX_S_BATCHED) return fail(SG_EINVAL, "S must be in [1, SG_MAX_S_BATCHED]");
   if (!Ns || !J || !h || !states_out || !energies_out)
     return fail(SG_EINVAL, "null pointer argument");
@@ -479,7 +487,7 @@ sg_status run_batched(bool isint, int B, const int32_t* Ns, int Nmax, const void
 
 sg_status lz_validate(int B, int N, const void* J, const void* h, int nb, const void* beta) {
   if (B < 1) return fail(SG_EINVAL, "B must be >= 1");
-  if (N < kU || N > 40) return fail(SG_EINVAL, "N must be in [6, 40]");
+  if (N < kU || N > 40) return fail(SG_EINVAL, "N must be in [7, 40]");
   if (nb < 1 || nb > kMaxBeta) return fail(SG_EINVAL, "n_beta must be in [1, 4]");
   if (!J || !h || !beta) return fail(SG_EINVAL, "null pointer argument");
   return SG_OK;
@@ -488,8 +496,8 @@ sg_status lz_validate(int B, int N, const void* J, const void* h, int nb, const 
 sg_status lz_buffers(Workspace* w, int B, int N) {
   const size_t Bz = (size_t)B;
   const size_t stride = std::max<size_t>(kMaxBeta, (size_t)N * N + N);
-  HIP_TRY(grow(&w->table64, &w->ntable64, Bz * table_records(std::min(kLzFree, N)) * 8));
-  HIP_TRY(grow(&w->lzq, &w->nlzq, Bz * kMaxBeta * 3 * kBlockSteps));
+  HIP_TRY(grow(&w->table64, &w->ntable64, Bz * lz_table_records(std::min(kLzFree, N)) * 8));
+  HIP_TRY(grow(&w->lzq, &w->nlzq, Bz * kMaxBeta * 3 * kLzSteps));
   HIP_TRY(grow(&w->lzqmin, &w->nlzqmin, Bz));
   HIP_TRY(grow(&w->lz_acc, &w->nlz_acc, Bz * stride));
   HIP_TRY(grow(&w->lz_coef, &w->nlz_coef, Bz * kMaxBeta));
@@ -504,12 +512,12 @@ LzArgs lz_args(Workspace* w, int B, int N, int nb, int S, const float* h, const 
   // free spins per lane: at most kLzFree, fewer when the batch alone would
   // not give every resident lane of the device a prefix
   a.n = std::min(kLzFree, N);
-  while (a.n > kU && (int64_t)B * ((int64_t)1 << (N - a.n)) < w->fill[0]) --a.n;
+  while (a.n > kLzU && (int64_t)B * ((int64_t)1 << (N - a.n)) < w->fill[0]) --a.n;
   a.nb = nb;
   a.S = S;
   a.lanes = (int64_t)1 << (N - a.n);
-  a.table_recs = (int64_t)table_records(a.n);
-  a.table_offset = (1 << (a.n - kU)) - 1;
+  a.table_recs = (int64_t)lz_table_records(a.n);
+  a.table_offset = (1 << (a.n - kLzU)) - 1;
   a.h_in = h;
   a.beta = beta;
   a.e0 = e0;
@@ -718,7 +726,7 @@ double sg_probe_valu(int op, int waves_per_simd) {
 
 int sg_debug_plan(int N, int S, uint64_t lo, uint64_t hi, int64_t lanes_fill,
                   uint64_t* first_mask, int32_t* free_bits, int64_t* lanes, int cap) {
-  if (N < kU || N > SG_MAX_N || S < 1 || lo >= hi || hi > ((uint64_t)1 << N) || (lo % 64) != 0 ||
+  if (N < 1 || N > SG_MAX_N || S < 1 || lo >= hi || hi > ((uint64_t)1 << N) || (lo % 64) != 0 ||
       lanes_fill < 1)
     return -1;
   const std::vector<PlanChunk> plan = plan_chunks(N, S, lo, hi, lanes_fill);

@@ -18,13 +18,17 @@
 
 namespace sg {
 
-constexpr int kU = 6;                 // low spins per block: 2^6 = 64 steps
+constexpr int kU = 7;                 // low spins per search block: 2^7 = 128 steps
 constexpr int kBlockSteps = 1 << kU;
 constexpr int kMaxFree = 22;          // largest n (free spins per lane)
 constexpr int kMaxHigh = kMaxFree - kU;
-constexpr int kRecWords = 8;          // per-block table record (32 B)
+constexpr int kRecWords = 16;         // per-block table record (64 B: cB, R, Wu_0..U-1)
 constexpr int kReanchorLog2 = 10;     // fp32: fresh G every 2^10 flips
 constexpr int kReanchorBlocks = 1 << (kReanchorLog2 - kU);
+// The log Z walk uses blocks of its own: 6 low spins (64 configurations),
+// fp64 records of 8 doubles (cB, R, Wu_0..5).
+constexpr int kLzU = 6;
+constexpr int kLzSteps = 1 << kLzU;
 constexpr int kWaveLanes = 64;
 constexpr int kEnumBlock = 256;       // threads per enumeration workgroup
 constexpr int kMergeThreads = 1024;   // threads of the single-workgroup merge
@@ -86,7 +90,7 @@ struct Batch {
   int B;
   int S;
   Params* P;           // [B]
-  uint32_t* qtab;      // [B][2 * kBlockSteps]
+  uint32_t* qtab;      // [B][2 * kBlockSteps] low-low energies by block parity and step
   uint32_t* table;     // [B][table_recs][kRecWords]
   int64_t table_recs;
   uint64_t* cand;      // [B][cap] candidate masks

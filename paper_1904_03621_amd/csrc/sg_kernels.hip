@@ -209,7 +209,7 @@ __global__ void k_prep(Batch bt) {
     // and energies are all bounded by 2 Bv; the computed ones stay below
     // 2 Bv + margin < 2.1 Bv (margin < 0.01 Bv below), so each fp32
     // rounding is at most uH = H 2^-24, H the power of two above 2.1 Bv.
-    // Between two re-anchors (R = 2^10 / 2^U blocks) G takes per block 63
+    // Between two re-anchors (R = 2^10 / 2^U blocks) G takes per block 2^U - 1
     // rounded inner adds, 2 rounded boundary adds and a rounded boundary
     // constant, and the block's W values carry three roundings each with net
     // weight at most 1 per block (a spin's flips alternate in sign).  The
@@ -227,7 +227,8 @@ __global__ void k_prep(Batch bt) {
         const double uH = H * 5.9604644775390625e-08;  // 2^-24
         const double R = (double)kReanchorBlocks;
         const double rounds =
-            R * (63.0 + 3.0 * U + 3.0) + (kMaxFree + 3.0) + kMaxFree * 0.5 + 4.0 + 4.0;
+            R * (kBlockSteps - 1.0 + 3.0 * U + 3.0) + (kMaxFree + 3.0) + kMaxFree * 0.5 + 4.0 +
+            4.0;
         margin = rounds * uH;
       }
     }
@@ -262,22 +263,23 @@ __global__ void k_prep(Batch bt) {
 //                 odd T, -1 for even T (old value of spin U-1 when the inner
 //                 step 2^(U-1) flips it).
 // Tables for n = U .. nmax are concatenated; the table of n starts at record
-// 2^(n-U) - 1.  grid.y indexes the instance.
+// 2^(n-U) - 1.  grid.y indexes the instance.  The search uses U = kU (words
+// of kRecWords); the log Z walk (kF64) U = kLzU and records of 8 doubles.
 
 template <bool kInt, bool kF64>
 __global__ void k_tables(Batch bt, int ncap, void* out) {
+  constexpr int U = kF64 ? kLzU : kU;
   const int b = blockIdx.y;
   const int N = inst_N(bt, b);
-  if (N < kU || N > bt.ld) return;
+  if (N < U || N > bt.ld) return;
   const int nmax = min(ncap, N);
-  const int64_t total = ((int64_t)1 << (nmax - kU + 1)) - 1;
+  const int64_t total = ((int64_t)1 << (nmax - U + 1)) - 1;
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= total) return;
   // which n: records of n occupy [2^(n-U) - 1, 2^(n-U+1) - 1)
-  int n = kU;
-  while (((int64_t)1 << (n - kU + 1)) - 1 <= r) ++n;
-  const uint32_t T = (uint32_t)(r - (((int64_t)1 << (n - kU)) - 1));
-  const int U = kU;
+  int n = U;
+  while (((int64_t)1 << (n - U + 1)) - 1 <= r) ++n;
+  const uint32_t T = (uint32_t)(r - (((int64_t)1 << (n - U)) - 1));
   const int ld = bt.ld;
   const uint32_t x = gray32(T << U);
   using Tv = typename std::conditional<kInt, int32_t, float>::type;
@@ -307,7 +309,7 @@ __global__ void k_tables(Batch bt, int ncap, void* out) {
   for (int a = 0; a < U; ++a)
     for (int c = a + 1; c < U; ++c) q -= J(a, c) * S(a) * S(c);
   const double R = eff - q;
-  double wu[kU];
+  double wu[U];
   for (int f = 0; f < U; ++f) {
     double s = H(f);
     for (int g = U; g < n; ++g) s += J(f, g) * S(g);
@@ -491,9 +493,9 @@ __global__ __launch_bounds__(kEnumBlock, 8) void k_enum(Batch bt, const void* __
 
   for (uint32_t T = 0; T < nblocks; ++T) {
     const uint32_t* rec = tab + (size_t)T * kRecWords;
-    V rw[kRecWords];
+    V rw[2 + U];
 #pragma unroll
-    for (int k = 0; k < kRecWords; ++k)
+    for (int k = 0; k < 2 + U; ++k)
       rw[k] = kInt ? (V)(int32_t)rec[k] : (V)__uint_as_float(rec[k]);
     const V ycur = ynext;
     if (T + 1 < nblocks) ynext = s_y[__builtin_ctz(T + 1) * kEnumBlock + tid];
@@ -526,7 +528,7 @@ __global__ __launch_bounds__(kEnumBlock, 8) void k_enum(Batch bt, const void* __
     for (int f = 0; f < U - 1; ++f) W[f] = WL[f] + rw[2 + f];
     W[U - 1] = ((T & 1u) ? WL[U - 1] : -WL[U - 1]) + rw[2 + U - 1];
 
-    // 63 inner steps: one add per state, one 3-input min per two states
+    // 2^U - 1 inner steps: one add per state, one 3-input min per two states
     const V Gs = G;
     V m = G;
 #pragma unroll
@@ -547,27 +549,32 @@ __global__ __launch_bounds__(kEnumBlock, 8) void k_enum(Batch bt, const void* __
     const bool pass = m <= fastThr;
     if (__ballot(pass) != 0ull) {
       // re-walk of this block, testing every state, for the lanes whose
-      // bound passed; the opaque copy keeps the compiler from holding the 64
+      // bound passed; the opaque copy keeps the compiler from holding the
       // values of the fast walk live across the branch
       ++slow;
       const uint32_t* q = qtab + (T & 1u) * kBlockSteps;
       V g2 = Gs;
       asm volatile("" : "+v"(g2));
-      uint64_t hits = 0;
+      constexpr int kHitWords = kBlockSteps / 64;
+      uint64_t hits[kHitWords];
+#pragma unroll
+      for (int w = 0; w < kHitWords; ++w) hits[w] = 0ull;
       auto qv = [&](int i) -> V { return kInt ? (V)(int32_t)q[i] : (V)__uint_as_float(q[i]); };
-      if (g2 + qv(0) <= thrE) hits |= 1ull;
+      if (g2 + qv(0) <= thrE) hits[0] |= 1ull;
 #pragma unroll
       for (int i = 1; i < kBlockSteps; ++i) {
         const int f = __builtin_ctz(i);
         if (f == U - 1) g2 = g2 + W[f];
         else g2 = ((i >> (f + 1)) & 1) ? g2 + W[f] : g2 - W[f];
-        if (g2 + qv(i) <= thrE) hits |= (1ull << i);
+        if (g2 + qv(i) <= thrE) hits[i >> 6] |= (1ull << (i & 63));
       }
-      if (!valid || !pass) hits = 0;
       const uint64_t pl = ch.prefix_base + (uint64_t)lane;
-      while (hits) {
-        const int i = __builtin_ctzll(hits);
-        hits &= hits - 1ull;
+#pragma unroll
+      for (int w = 0; w < kHitWords; ++w) {
+       uint64_t hw = (valid && pass) ? hits[w] : 0ull;
+       while (hw) {
+        const int i = 64 * w + __builtin_ctzll(hw);
+        hw &= hw - 1ull;
         const uint64_t t = ((uint64_t)T << U) | (uint64_t)i;
         const uint64_t mask = (pl << n) | (t ^ (t >> 1));
         // the walk's energy of step i, from the block start: a low spin
@@ -582,6 +589,7 @@ __global__ __launch_bounds__(kEnumBlock, 8) void k_enum(Batch bt, const void* __
         e = e + qv(i);
         const uint32_t key = kInt ? key_of_i32((int32_t)e) : key_f32((float)e);
         append_mask(mask, key, P, cand, ckey, cand_cap);
+       }
       }
     }
   }
@@ -936,7 +944,7 @@ hipError_t launch_prep(bool isint, const Batch& bt, hipStream_t st) {
 }
 
 hipError_t launch_tables(bool isint, const Batch& bt, int ncap, hipStream_t st) {
-  const int64_t total = ((int64_t)1 << (ncap - kU + 1)) - 1;
+  const int64_t total = ((int64_t)1 << (ncap - kU + 1)) - 1;  // search records
   const dim3 grid((unsigned)((total + 255) / 256), (unsigned)bt.B);
   if (isint) hipLaunchKernelGGL((k_tables<true, false>), grid, dim3(256), 0, st, bt, ncap, nullptr);
   else hipLaunchKernelGGL((k_tables<false, false>), grid, dim3(256), 0, st, bt, ncap, nullptr);
@@ -945,7 +953,7 @@ hipError_t launch_tables(bool isint, const Batch& bt, int ncap, hipStream_t st) 
 
 // fp64 records (8 doubles each) of an fp32 batch, for the log Z walk.
 hipError_t launch_tables64(const Batch& bt, int ncap, double* out, hipStream_t st) {
-  const int64_t total = ((int64_t)1 << (ncap - kU + 1)) - 1;
+  const int64_t total = ((int64_t)1 << (ncap - kLzU + 1)) - 1;
   const dim3 grid((unsigned)((total + 255) / 256), (unsigned)bt.B);
   hipLaunchKernelGGL((k_tables<false, true>), grid, dim3(256), 0, st, bt, ncap, (void*)out);
   return hipGetLastError();

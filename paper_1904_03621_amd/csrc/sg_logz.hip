@@ -43,10 +43,10 @@
 
 namespace sg {
 
-constexpr int kLzHigh = kLzFree - kU;
+constexpr int kLzHigh = kLzFree - kLzU;
 constexpr int kNCoef = 22;   // 1 + 6 + 15 order <= 2 Walsh coefficients over U = 6
 // per beta: bq by configuration x, then by Gray step i for block parity 0 and 1
-constexpr int kLzQ = 3 * kBlockSteps;
+constexpr int kLzQ = 3 * kLzSteps;
 
 // ------------------------------------------------------------------ prep
 // One workgroup per instance: the low-low energies Q(x), their minimum, the
@@ -57,16 +57,16 @@ template <int kMode>
 __global__ void k_lz_prep(LzArgs a, const float* __restrict__ J, float* lzq, double* lzqmin,
                           const float* energies, float* e0_out, const double* logz,
                           const double* grad) {
-  __shared__ double s_q[kBlockSteps];
+  __shared__ double s_q[kLzSteps];
   __shared__ double s_qmin;
   const int b = blockIdx.x;
   const int N = a.N;
   const float* Jb = J + (size_t)b * N * N;
   const int tid = threadIdx.x;
-  if (tid < kBlockSteps) {
+  if (tid < kLzSteps) {
     double q = 0.0;
-    for (int f = 0; f < kU; ++f)
-      for (int g = f + 1; g < kU; ++g) {
+    for (int f = 0; f < kLzU; ++f)
+      for (int g = f + 1; g < kLzU; ++g) {
         const double sf = ((tid >> f) & 1) ? 1.0 : -1.0, sg = ((tid >> g) & 1) ? 1.0 : -1.0;
         q -= (double)Jb[f * N + g] * sf * sg;
       }
@@ -75,7 +75,7 @@ __global__ void k_lz_prep(LzArgs a, const float* __restrict__ J, float* lzq, dou
   __syncthreads();
   if (tid == 0) {
     double m = s_q[0];
-    for (int x = 1; x < kBlockSteps; ++x) m = fmin(m, s_q[x]);
+    for (int x = 1; x < kLzSteps; ++x) m = fmin(m, s_q[x]);
     s_qmin = m;
     lzqmin[b] = m;
   }
@@ -84,9 +84,9 @@ __global__ void k_lz_prep(LzArgs a, const float* __restrict__ J, float* lzq, dou
   for (int e = tid; e < a.nb * kLzQ; e += blockDim.x) {
     const int k = e / kLzQ, r = e - k * kLzQ;
     int x = r;
-    if (r >= kBlockSteps) {
-      const int i = r & (kBlockSteps - 1);
-      x = (i ^ (i >> 1)) ^ ((r >= 2 * kBlockSteps) ? (1 << (kU - 1)) : 0);
+    if (r >= kLzSteps) {
+      const int i = r & (kLzSteps - 1);
+      x = (i ^ (i >> 1)) ^ ((r >= 2 * kLzSteps) ? (1 << (kLzU - 1)) : 0);
     }
     const double bk = (double)a.beta[k];
     lzq[((size_t)b * kMaxBeta + k) * kLzQ + r] = (float)exp(-bk * (s_q[x] - qmin));
@@ -129,8 +129,8 @@ __global__ void k_lz_prep(LzArgs a, const float* __restrict__ J, float* lzq, dou
 
 struct Coefs {
   float o;
-  float s[kU];
-  float p[kU * (kU - 1) / 2];
+  float s[kLzU];
+  float p[kLzU * (kLzU - 1) / 2];
 };
 
 constexpr int pidx(int f, int g) { return g * (g - 1) / 2 + f; }
@@ -172,7 +172,7 @@ struct BlockWalk {
       for (int f1 = 1; f1 < g; ++f1)
 #pragma unroll
         for (int f0 = 0; f0 < f1; ++f0) r.p[pidx(f0, f1)] = a.p[pidx(f0, f1)] + b.p[pidx(f0, f1)];
-      if (g == kU - 1) {
+      if (g == kLzU - 1) {
         r.s[g] = sgn5 * (a.o - b.o);
 #pragma unroll
         for (int f = 0; f < g; ++f) r.p[pidx(f, g)] = sgn5 * (a.s[f] - b.s[f]);
@@ -201,26 +201,26 @@ __device__ inline void lz_slot(int s, int H, int N, int* coef, uint32_t* mask, i
     int g = 1;
     while (pidx(0, g + 1) <= s) ++g;
     const int f = s - pidx(0, g);
-    *coef = 1 + kU + s;
+    *coef = 1 + kLzU + s;
     *mask = 0;
     *target = f * N + g;
     return;
   }
   s -= 15;
-  if (s < kU * H) {
-    const int f = s % kU, k = s / kU;
+  if (s < kLzU * H) {
+    const int f = s % kLzU, k = s / kLzU;
     *coef = 1 + f;
     *mask = 1u << k;
-    *target = f * N + (kU + k);
+    *target = f * N + (kLzU + k);
     return;
   }
-  s -= kU * H;
+  s -= kLzU * H;
   int k1 = 1;
   while (pidx(0, k1 + 1) <= s) ++k1;
   const int k0 = s - pidx(0, k1);
   *coef = 0;
   *mask = (1u << k0) | (1u << k1);
-  *target = (kU + k0) * N + (kU + k1);
+  *target = (kLzU + k0) * N + (kLzU + k1);
 }
 
 // ------------------------------------------------------------------ walk
@@ -246,7 +246,7 @@ __global__ __launch_bounds__(256) void k_logz(LzArgs a, const float* __restrict_
                                               const double* __restrict__ table64,
                                               const float* __restrict__ lzq,
                                               const double* __restrict__ lzqmin, int bpi) {
-  constexpr int U = kU;
+  constexpr int U = kLzU;
   __shared__ double s_y[kLzHigh * 256];
   __shared__ float s_c[kMode ? 4 * kNCoef * 64 : 1];
   __shared__ float s_t[kMode ? 4 * kNCoef : 1];
@@ -404,7 +404,7 @@ __global__ __launch_bounds__(256) void k_logz(LzArgs a, const float* __restrict_
             Bf[k][x2 + 4] = t;
           }
         }
-        bqs[k] = s_bq + k * kLzQ + kBlockSteps * (odd ? 2 : 1);
+        bqs[k] = s_bq + k * kLzQ + kLzSteps * (odd ? 2 : 1);
       }
       BlockWalk<NB> bw{Af, Bf, bqs, odd ? 1.0f : -1.0f};
       const Coefs C = bw.template walk<U, 0>();

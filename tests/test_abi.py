@@ -66,8 +66,8 @@ def test_validation_is_synchronous(L, case):
 
 
 @pytest.mark.parametrize("case", [
-    dict(B=0), dict(N=5), dict(N=41), dict(nb=0), dict(nb=5), dict(S=0), dict(S=4097),
-    dict(S=65, N=6), dict(null=True),
+    dict(B=0), dict(N=6), dict(N=41), dict(nb=0), dict(nb=5), dict(S=0), dict(S=4097),
+    dict(S=129, N=7), dict(null=True),
 ])
 def test_batched_and_logz_validation_is_synchronous(L, case):
     lib = L.lib()
@@ -78,7 +78,7 @@ def test_batched_and_logz_validation_is_synchronous(L, case):
     if "S" not in case:
         st = lib.sg_logz_backward_f32(B, N, p, p, nb, p, p, p, p, p, p, 0)
         assert st == L.SG_EINVAL and L.last_error() != ""
-    if "nb" not in case and not (N == 6 and S == 65):
+    if "nb" not in case and not (N == 7 and S == 129):
         st = lib.sg_low_spectrum_batched_f32(B, p, N, p, p, S, p, p, 0)
         assert st == L.SG_EINVAL and L.last_error() != ""
 
@@ -97,7 +97,9 @@ def _check_plan(L, N, S, lo, hi, fill):
     first_states = None
     for (first, n, lanes) in plan:
         assert first == cur, "chunks must tile the range in ascending order"
-        assert 6 <= n <= nmax
+        # n = 0: a range end shorter than a 128-state block, one thread per state
+        assert n == 0 or 7 <= n <= nmax
+        assert n > 0 or lanes < 256
         assert first % (1 << n) == 0, "prefix base must be whole"
         assert lanes >= 1
         size = lanes << n

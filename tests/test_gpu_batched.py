@@ -53,7 +53,7 @@ def run_single(torch, J, h, S):
 @pytest.mark.parametrize("isint", [True, False])
 def test_small_batch_vs_oracle_and_single(orc, torch_dev, isint):
     B, S = 40, 32
-    Ns, J, h = make_batch(B, 6, 20, 3, isint)
+    Ns, J, h = make_batch(B, 7, 20, 3, isint)
     bm, be = run_batched(torch_dev, Ns, J, h, S)
     for b in range(B):
         n = int(Ns[b])
@@ -119,7 +119,7 @@ def test_bad_instance_size_reported(torch_dev):
     import paper_1904_03621_amd as sg
     from paper_1904_03621_amd import _lib
     Ns, J, h = make_batch(4, 8, 12, 6, True)
-    Ns[2] = 3  # below 6
+    Ns[2] = 6  # below 7
     with pytest.raises(sg.SgError) as ei:
         run_batched(torch_dev, Ns, J, h, 8)
     assert ei.value.status == _lib.SG_EINVAL
@@ -162,7 +162,7 @@ def test_overflowing_level_is_walked_again(orc, torch_dev):
     J0, h0 = I.random_f32_dense(N, 71, j_scale=1.0 / np.sqrt(N), h_scale=0.1)
     h0 = h0.copy()
     h0[N - 1] = 3.0
-    Ns, J, h = make_batch(B, 6, 10, 12, False, Nmax=N)
+    Ns, J, h = make_batch(B, 7, 10, 12, False, Nmax=N)
     Ns[0] = N
     J[0], h[0] = J0, h0
     bm, be = run_batched(torch, Ns, J, h, S)

@@ -60,7 +60,7 @@ def check_grad(gJ, gh, gJ_ref, gh_ref, what):
     assert np.all(gJ[low] == 0.0), "%s: grad_J nonzero on or below the diagonal" % what
 
 
-@pytest.mark.parametrize("N", [6, 7, 9, 13, 14, 15, 17, 20])
+@pytest.mark.parametrize("N", [7, 8, 9, 13, 14, 15, 17, 20])
 def test_forward_backward_vs_oracle(orc, torch_dev, N):
     B = 3
     J, h = I.logz_batch(B, N, 40 + N)
@@ -238,9 +238,9 @@ def test_errors(torch_dev):
     with pytest.raises(sg.SgError) as ei:
         sg.logz_forward(Jt, ht, torch.ones(5, device="cuda"), 4)
     assert ei.value.status == _lib.SG_EINVAL
-    J5, h5 = I.logz_batch(1, 5, 1)
+    J6, h6 = I.logz_batch(1, 6, 1)
     with pytest.raises(sg.SgError) as ei:
-        sg.logz_forward(*to_dev(torch, J5, h5), torch.ones(1, device="cuda"), 4)
+        sg.logz_forward(*to_dev(torch, J6, h6), torch.ones(1, device="cuda"), 4)
     assert ei.value.status == _lib.SG_EINVAL
     # the stream is clean again
     lz, e0, _, _ = sg.logz_forward(Jt, ht, torch.ones(1, device="cuda"), 4)
