@@ -249,6 +249,46 @@ int oracle_low_spectrum_i64(int N, const int64_t *J, const int64_t *h, int S,
     return out;
 }
 
+/* ------------------------------------------------------- density of states */
+
+/*
+ * Density of states of an integer instance: counts[k] = number of masks m in
+ * [lo, hi) with E(m) = e_min + k (Eq. 1), k in [0, n_bins).  Every mask is
+ * evaluated from scratch; each thread keeps its own histogram.  Returns 0, or
+ * -1 if some energy falls outside [e_min, e_min + n_bins).
+ */
+int oracle_dos_i64(int N, const int64_t *J, const int64_t *h, int64_t e_min, int n_bins,
+                   uint64_t lo, uint64_t hi, uint64_t *counts, int nthreads)
+{
+    if (n_bins <= 0 || hi < lo) return -1;
+    int T = oracle_threads(nthreads);
+    uint64_t *part = (uint64_t *)calloc((size_t)n_bins * T, sizeof(uint64_t));
+    int outside = 0;
+    uint64_t span = hi - lo;
+#pragma omp parallel num_threads(T) reduction(| : outside)
+    {
+        int t = 0;
+#ifdef _OPENMP
+        t = omp_get_thread_num();
+#endif
+        uint64_t a = lo + span / T * t + (t < (int)(span % T) ? t : span % T);
+        uint64_t b = a + span / T + (t < (int)(span % T) ? 1 : 0);
+        uint64_t *c = part + (size_t)n_bins * t;
+        for (uint64_t m = a; m < b; ++m) {
+            int64_t k = oracle_energy_i64(N, J, h, m) - e_min;
+            if (k < 0 || k >= n_bins) outside = 1;
+            else c[k] += 1;
+        }
+    }
+    for (int k = 0; k < n_bins; ++k) {
+        uint64_t v = 0;
+        for (int t = 0; t < T; ++t) v += part[(size_t)n_bins * t + k];
+        counts[k] = v;
+    }
+    free(part);
+    return outside ? -1 : 0;
+}
+
 /* ------------------------------------------------------- log Z and moments */
 
 /* Neumaier (improved Kahan) compensated summation step. */

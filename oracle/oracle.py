@@ -56,6 +56,9 @@ def _load(path: str):
     L.oracle_low_spectrum_i64.argtypes = [ctypes.c_int, _c_i64p, _c_i64p, ctypes.c_int,
                                           ctypes.c_uint64, ctypes.c_uint64, _c_u64p,
                                           _c_i64p, ctypes.c_int]
+    L.oracle_dos_i64.restype = ctypes.c_int
+    L.oracle_dos_i64.argtypes = [ctypes.c_int, _c_i64p, _c_i64p, ctypes.c_int64, ctypes.c_int,
+                                 ctypes.c_uint64, ctypes.c_uint64, _c_u64p, ctypes.c_int]
     L.oracle_logz_f64.restype = ctypes.c_int
     L.oracle_logz_f64.argtypes = [ctypes.c_int, _c_dp, _c_dp, ctypes.c_int, _c_dp,
                                   _c_dp, _c_dp, _c_dp, _c_dp, ctypes.c_int]
@@ -161,6 +164,32 @@ def low_spectrum(J, h, S: int, lo: int = 0, hi: int | None = None, nthreads: int
         n = lib().oracle_low_spectrum_f64(N, _ptr(Ja, _c_dp), _ptr(ha, _c_dp), S, lo, hi,
                                           _ptr(masks, _c_u64p), _ptr(es, _c_dp), nthreads)
     return masks[:n], es[:n]
+
+
+def energy_bound(J, h) -> int:
+    """sum_{i<j} |J_ij| + sum_i |h_i| of an integer instance: |E| never exceeds it."""
+    N = len(h)
+    Ja, ha = _i64(J), _i64(h)
+    return int(np.abs(np.triu(Ja.reshape(N, N), 1)).sum() + np.abs(ha).sum())
+
+
+def density_of_states(J, h, e_min: int | None = None, n_bins: int | None = None,
+                      lo: int = 0, hi: int | None = None, nthreads: int = 0):
+    """(e_min, counts) with counts[k] the number of masks in [lo, hi) whose
+    energy is e_min + k.  By default the bins span [-B, B], B = energy_bound."""
+    N = len(h)
+    if hi is None:
+        hi = 1 << N
+    if e_min is None:
+        bnd = energy_bound(J, h)
+        e_min, n_bins = -bnd, 2 * bnd + 1
+    Ja, ha = _i64(J), _i64(h)
+    counts = np.zeros(n_bins, dtype=np.uint64)
+    rc = lib().oracle_dos_i64(N, _ptr(Ja, _c_i64p), _ptr(ha, _c_i64p), e_min, n_bins, lo, hi,
+                              _ptr(counts, _c_u64p), nthreads)
+    if rc != 0:
+        raise ValueError("an energy falls outside the bins")
+    return e_min, counts
 
 
 def logz(J, h, betas, moments: bool = False, nthreads: int = 0):

@@ -304,9 +304,47 @@ def pin_logz_e0(orc):
     assert abs(lz[0] - (-40.0 * e0 + math.log(2.0))) < 1e-9
 
 
+def pin_dos_ferromagnet(orc):
+    """Density of states of the complete-graph ferromagnet: the C(N, c) states
+    of popcount c share the energy -J((N - 2c)^2 - N)/2."""
+    N = 12
+    J, h = I.ferromagnet(N, 1, np.int32)
+    e_min, counts = orc.density_of_states(J, h)
+    want = np.zeros_like(counts)
+    for c in range(N + 1):
+        want[-((N - 2 * c) ** 2 - N) // 2 - e_min] += math.comb(N, c)
+    assert np.array_equal(counts, want)
+    assert int(counts.sum()) == 1 << N
+
+
+def pin_dos_distinct_levels(orc):
+    """Two instances whose 2^N energies are all distinct and known: free spins
+    with h_i = 2^i (E = -(2^N - 1) + 2k, once each) and an open chain with
+    |K_i| = 2^i, h = 0 (the 2^(N-1) bond patterns, each level twice)."""
+    N = 10
+    J, h = I.free_spins_pow2_fields(N)
+    e_min, counts = orc.density_of_states(J, h)
+    want = np.zeros_like(counts)
+    for k in range(1 << N):
+        want[-((1 << N) - 1) + 2 * k - e_min] += 1
+    assert np.array_equal(counts, want)
+    J = np.zeros((N, N), dtype=np.int32)
+    for i in range(N - 1):
+        J[i, i + 1] = (1 << i) * (1 if i % 3 else -1)
+    h = np.zeros(N, dtype=np.int32)
+    e_min, counts = orc.density_of_states(J, h)
+    want = np.zeros_like(counts)
+    for b in range(1 << (N - 1)):
+        want[-((1 << (N - 1)) - 1) + 2 * b - e_min] += 2
+    assert np.array_equal(counts, want)
+    # a slice of the masks counts only that slice
+    e_min2, part = orc.density_of_states(J, h, e_min, len(counts), 256, 768)
+    assert int(part.sum()) == 512
+
+
 ALL_PINS = [
     pin_listing1, pin_encoding_eq5, pin_qubo_identity, pin_full_sort,
     pin_range_merge, pin_ferromagnet, pin_mattis, pin_free_pow2,
     pin_global_flip, pin_gauge, pin_chain_logz, pin_free_logz,
-    pin_ferro_logz, pin_logz_fd, pin_logz_e0,
+    pin_ferro_logz, pin_logz_fd, pin_logz_e0, pin_dos_ferromagnet, pin_dos_distinct_levels,
 ]

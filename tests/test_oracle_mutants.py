@@ -62,6 +62,10 @@ MUTANTS = {
                                 "mss[((size_t)b * N + i) * N + j] += w * s[i] * s[i];"),
     "grad_missing_beta": _first("g[b] * beta[b] * mss", "g[b] * mss"),
     "qubo_a_factor": _first("4.0 * J[(size_t)i * N + j]", "2.0 * J[(size_t)i * N + j]"),
+    "dos_bin_offset": _first("int64_t k = oracle_energy_i64(N, J, h, m) - e_min;",
+                             "int64_t k = oracle_energy_i64(N, J, h, m) - e_min + 1;"),
+    "dos_thread_slice": _first("uint64_t b = a + span / T + (t < (int)(span % T) ? 1 : 0);",
+                               "uint64_t b = a + span / T;", nth=2),
 }
 
 
