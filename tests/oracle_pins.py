@@ -337,9 +337,11 @@ def pin_dos_distinct_levels(orc):
     for b in range(1 << (N - 1)):
         want[-((1 << (N - 1)) - 1) + 2 * b - e_min] += 2
     assert np.array_equal(counts, want)
-    # a slice of the masks counts only that slice
-    e_min2, part = orc.density_of_states(J, h, e_min, len(counts), 256, 768)
-    assert int(part.sum()) == 512
+    # a slice of the masks counts exactly that slice, whatever the thread split
+    for nt in (0, 3):
+        _, part = orc.density_of_states(J, h, e_min, len(counts), 256, 771, nthreads=nt)
+        assert int(part.sum()) == 515
+        assert np.all(part <= counts)
 
 
 ALL_PINS = [
