@@ -209,6 +209,37 @@ def bench_logz(torch, sg, reps: int, baseline: bool = True) -> dict:
     return out
 
 
+def bench_dos(torch, sg, reps: int) -> dict:
+    """Exact density of states of a 40-spin Chimera-like instance (1 x 5 unit
+    cells, couplers uniform in {-1, +1}, h = 0, seed 6): all 2^40 states."""
+    import instances as I
+    J, h = I.chimera_pm1(1, 5, 6)
+    dev = torch.device("cuda:0")
+    Jt, ht = (torch.from_numpy(x).to(dev) for x in (J, h))
+    N = J.shape[0]
+    B = int(np.abs(np.triu(J.astype(np.int64), 1)).sum() + np.abs(h.astype(np.int64)).sum())
+    counts = torch.empty(2 * B + 1, dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def run():
+        st = sg.sg_density_of_states_i32(N, Jt, ht, -B, 2 * B + 1, counts, stream)
+        if st != 0:
+            raise sg.SgError(st, "sg_density_of_states_i32", sg._lib.last_error())
+
+    run()
+    t = min(_sync_time(torch, run) for _ in range(reps))
+    err = sg.sg_get_error(stream)
+    if err != 0:
+        raise sg.SgError(err, "device", sg._lib.last_error())
+    c = counts.cpu().numpy()
+    ok = bool(c.sum() == (1 << N) and np.all(c % 2 == 0))
+    print("dos done", file=sys.stderr, flush=True)
+    return {"workload": "Chimera-like 1x5 cells (40 spins), J = +-1 uniform, h = 0, seed 6; "
+                        "all 2^40 states counted by energy",
+            "value": float(1 << N) / t, "unit": "spin configs/s", "ms": t * 1e3,
+            "check": "ok" if ok else "FAILED"}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -219,7 +250,7 @@ def main() -> int:
                     help="skip the batched and log Z measurements")
     ap.add_argument("--valu-probe", action="store_true",
                     help="print the measured issue rate of each probed VALU instruction")
-    ap.add_argument("--leg", choices=["batched", "logz"],
+    ap.add_argument("--leg", choices=["batched", "logz", "dos"],
                     help="run only this extension's batched calls (warm-up + 1 timed; for "
                          "profiling) and print their times")
     ap.add_argument("--traffic-probe", action="store_true",
@@ -242,6 +273,9 @@ def main() -> int:
         print(json.dumps({"valu_lane_ops_per_s": rates, "waves_per_simd": 8}), flush=True)
         return 0
     if args.leg:
+        if args.leg == "dos":
+            print(json.dumps({"dos": bench_dos(torch, sg, 1)}), flush=True)
+            return 0
         fn = bench_batched if args.leg == "batched" else bench_logz
         print(json.dumps({args.leg: fn(torch, sg, 1, baseline=False)}), flush=True)
         return 0
@@ -344,6 +378,7 @@ def main() -> int:
     if not args.no_extensions:
         out["batched"] = bench_batched(torch, sg, 3)
         out["logz"] = bench_logz(torch, sg, 3)
+        out["dos"] = bench_dos(torch, sg, 2)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(J, h)
     print(json.dumps(out), flush=True)

@@ -196,6 +196,59 @@ sg_status sg_logz_backward_f32(int B, int N, const float *J, const float *h, int
                                void *stream);
 
 /*
+ * QUBO front end (Sec. 2, Eqs. 2-3): the S lowest of
+ *     F(q) = - sum_{i<j} a_ij q_i q_j - sum_i b_i q_i ,   q_i in {0, 1},
+ * over all 2^N binary vectors, found by the Ising search on the instance of
+ * Eq. (3) (J = a/4, h_i = b_i/2 + sum_{j!=i} a_ij/4, formed on the device in
+ * fp64 and rounded to fp32) and rescored in the QUBO form.
+ *
+ *   N            1 <= N <= SG_MAX_N
+ *   A            device float[N][N], strict upper triangle a_ij (i < j) read
+ *   b            device float[N]
+ *   S            1 <= S <= SG_MAX_S_BATCHED, S <= 2^N
+ *   states_out   device uint64[S]: bit i = q_i
+ *   energies_out device float[S]: F in fp64 rounded to fp32, ascending by
+ *                (F, mask)
+ *
+ * When h has to be rounded to fp32 the set may differ from the exact QUBO
+ * answer only among states within N ulp of the S-th value; integer a and b
+ * (and any dyadic ones of moderate range) are exact.  Errors as for
+ * sg_low_spectrum_f32.
+ */
+sg_status sg_low_spectrum_qubo_f32(int N, const float *A, const float *b, int S,
+                                   uint64_t *states_out, float *energies_out, void *stream);
+
+/* Largest number of energy bins of sg_density_of_states_i32. */
+#define SG_MAX_DOS_BINS 8192
+
+/*
+ * Exact density of states of an integer instance: the number of the 2^N
+ * configurations at each energy of Eq. (1), all enumerated (the quantity the
+ * entropic population annealing comparison of Sec. 5.2 estimates).
+ *
+ *   N            1 <= N <= SG_MAX_N; int32 J (N x N, strict upper triangle
+ *                read) and h as for sg_low_spectrum_i32, with
+ *                sum|J| + sum|h| < 2^28 (else SG_EOVERFLOW via sg_get_error)
+ *   e_min        energy of bin 0
+ *   n_bins       1 <= n_bins <= SG_MAX_DOS_BINS
+ *   counts_out   device uint64[n_bins]: counts_out[k] = number of
+ *                configurations with E = e_min + k (overwritten)
+ *
+ * The bins must cover [-B, B] with B = sum_{i<j}|J_ij| + sum_i|h_i| (which no
+ * |E| exceeds; sg_energy_bound_i32 computes it), else SG_EINVAL via
+ * sg_get_error and the counts stay zero.  Work is enqueued on `stream`.
+ */
+sg_status sg_density_of_states_i32(int N, const int32_t *J, const int32_t *h, long long e_min,
+                                   int n_bins, unsigned long long *counts_out, void *stream);
+
+/*
+ * B = sum_{i<j} |J_ij| + sum_i |h_i| of an int32 instance, written to the
+ * device int64 `bound_out` (enqueued on `stream`).
+ */
+sg_status sg_energy_bound_i32(int N, const int32_t *J, const int32_t *h, long long *bound_out,
+                              void *stream);
+
+/*
  * Sizes the library's workspace of (current device, stream) for every later
  * call on that stream with B <= B_max, N <= N_max and S <= S_max (single,
  * batched and log Z calls).  Calls within those limits then allocate nothing,
@@ -204,6 +257,19 @@ sg_status sg_logz_backward_f32(int B, int N, const float *J, const float *h, int
  * workspace is owned by the library and lives until the process ends.
  */
 sg_status sg_reserve(int B_max, int N_max, int S_max, void *stream);
+
+/*
+ * Tuner of the batched search: times sg_low_spectrum_batched_f32 on this
+ * batch for each level geometry it can use (free spins per lane n =
+ * log2(level size) - shift, shift in 9..15) and keeps the fastest for later
+ * batched calls on this device with the same N_max and S; *shift_out is the
+ * choice.  Results do not depend on the geometry (the search is exact).
+ * Synchronous; allocates scratch and runs the search 21 times; call it before
+ * capturing a graph of batched calls (the geometry fixes the launch sequence).
+ * Arguments as for sg_low_spectrum_batched_f32.
+ */
+sg_status sg_tune_batched_f32(int B, const int32_t *N_dev, int N_max, const float *J,
+                              const float *h, int S, int *shift_out, void *stream);
 
 /* Waits for `stream`, then returns and clears the sticky device error of the
  * calls enqueued on it (SG_OK if none). */

@@ -23,6 +23,7 @@ STATUS_NAMES = {
 SG_MAX_N = 56
 SG_MAX_S = 1 << 20
 SG_MAX_S_BATCHED = 4096
+SG_MAX_DOS_BINS = 8192
 
 # every symbol include/sg.h declares
 EXPORTS = [
@@ -30,6 +31,8 @@ EXPORTS = [
     "sg_low_spectrum_range_f32", "sg_low_spectrum_range_i32",
     "sg_low_spectrum_batched_f32", "sg_low_spectrum_batched_i32",
     "sg_logz_forward_f32", "sg_logz_backward_f32", "sg_reserve",
+    "sg_density_of_states_i32", "sg_energy_bound_i32", "sg_tune_batched_f32",
+    "sg_low_spectrum_qubo_f32",
     "sg_get_error", "sg_last_error", "sg_get_run_info", "sg_debug_plan",
     "sg_set_kernel_timing", "sg_probe_valu",
 ]
@@ -94,6 +97,14 @@ def lib() -> ctypes.CDLL:
         L.sg_logz_forward_f32.argtypes = [i32, i32, vp, vp, i32, vp, i32, vp, vp, vp, vp, vp]
         L.sg_logz_backward_f32.restype = i32
         L.sg_logz_backward_f32.argtypes = [i32, i32, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]
+        L.sg_density_of_states_i32.restype = i32
+        L.sg_density_of_states_i32.argtypes = [i32, vp, vp, ctypes.c_longlong, i32, vp, vp]
+        L.sg_energy_bound_i32.restype = i32
+        L.sg_energy_bound_i32.argtypes = [i32, vp, vp, vp, vp]
+        L.sg_low_spectrum_qubo_f32.restype = i32
+        L.sg_low_spectrum_qubo_f32.argtypes = [i32, vp, vp, i32, vp, vp, vp]
+        L.sg_tune_batched_f32.restype = i32
+        L.sg_tune_batched_f32.argtypes = [i32, vp, i32, vp, vp, i32, vp, vp]
         L.sg_reserve.restype = i32
         L.sg_reserve.argtypes = [i32, i32, i32, vp]
         L.sg_get_error.restype = i32
@@ -180,6 +191,29 @@ def sg_logz_backward_f32(B, N, J, h, n_beta, beta, e0, logz, grad_logz, grad_J, 
     return lib().sg_logz_backward_f32(B, N, _ptr(J), _ptr(h), n_beta, _ptr(beta), _ptr(e0),
                                       _ptr(logz), _ptr(grad_logz), _ptr(grad_J), _ptr(grad_h),
                                       _stream(stream))
+
+
+def sg_density_of_states_i32(N, J, h, e_min, n_bins, counts_out, stream=None) -> int:
+    return lib().sg_density_of_states_i32(N, _ptr(J), _ptr(h), e_min, n_bins, _ptr(counts_out),
+                                          _stream(stream))
+
+
+def sg_energy_bound_i32(N, J, h, bound_out, stream=None) -> int:
+    return lib().sg_energy_bound_i32(N, _ptr(J), _ptr(h), _ptr(bound_out), _stream(stream))
+
+
+def sg_low_spectrum_qubo_f32(N, A, b, S, states_out, energies_out, stream=None) -> int:
+    return lib().sg_low_spectrum_qubo_f32(N, _ptr(A), _ptr(b), S, _ptr(states_out),
+                                          _ptr(energies_out), _stream(stream))
+
+
+def sg_tune_batched_f32(B, N_dev, N_max, J, h, S, stream=None) -> int:
+    """Runs the tuner; returns the chosen level shift (raises on failure)."""
+    out = ctypes.c_int(0)
+    st = lib().sg_tune_batched_f32(B, _ptr(N_dev), N_max, _ptr(J), _ptr(h), S,
+                                   ctypes.byref(out), _stream(stream))
+    check(st, "sg_tune_batched_f32")
+    return out.value
 
 
 def sg_reserve(B_max, N_max, S_max, stream=None) -> int:

@@ -170,5 +170,46 @@ def logz(J, h, beta, S: int = 32):
     return _LOGZ.apply(J, h, beta, S)
 
 
+def low_spectrum_qubo(A, b, S: int, stream=None, check: bool = True):
+    """S lowest binary vectors of the QUBO F(q) = -sum_{i<j} a_ij q_i q_j -
+    sum_i b_i q_i (A [N, N] upper triangle, b [N], float32, GPU): returns masks
+    int64[S] (bit i = q_i) and F float32[S], ascending by (F, mask)."""
+    import torch
+    A, b = _prep(A, b)
+    if A.dtype != torch.float32:
+        raise ValueError("the QUBO front end takes float32 A and b")
+    N = A.shape[0]
+    states = torch.empty(S, dtype=torch.int64, device=A.device)
+    energies = torch.empty(S, dtype=torch.float32, device=A.device)
+    _lib.check(_lib.sg_low_spectrum_qubo_f32(N, A, b, S, states, energies, stream),
+               "sg_low_spectrum_qubo_f32")
+    if check:
+        _lib.check(_lib.sg_get_error(stream), "device")
+    return states, energies
+
+
+def density_of_states(J, h, e_min=None, n_bins=None, stream=None, check: bool = True):
+    """Exact density of states of an int32 instance (J [N, N], h [N], GPU):
+    returns (e_min, counts int64[n_bins]) with counts[k] the number of
+    configurations at energy e_min + k.  By default the bins span [-B, B],
+    B = sum|J_ij| (i<j) + sum|h_i|, computed on the device."""
+    import torch
+    J, h = _prep(J, h)
+    if J.dtype != torch.int32:
+        raise ValueError("the density of states needs int32 J and h")
+    N = J.shape[0]
+    if e_min is None:
+        bound = torch.empty(1, dtype=torch.int64, device=J.device)
+        _lib.check(_lib.sg_energy_bound_i32(N, J, h, bound, stream), "sg_energy_bound_i32")
+        B = int(bound.item())
+        e_min, n_bins = -B, 2 * B + 1
+    counts = torch.empty(n_bins, dtype=torch.int64, device=J.device)
+    st = _lib.sg_density_of_states_i32(N, J, h, int(e_min), int(n_bins), counts, stream)
+    _lib.check(st, "sg_density_of_states_i32")
+    if check:
+        _lib.check(_lib.sg_get_error(stream), "device")
+    return int(e_min), counts
+
+
 def run_info(stream=None) -> dict:
     return _lib.sg_get_run_info(stream)

@@ -10,6 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsgpu.so")
 SOURCES = [os.path.join(CSRC, "sg_kernels.hip"), os.path.join(CSRC, "sg_logz.hip"),
+           os.path.join(CSRC, "sg_dos.hip"), os.path.join(CSRC, "sg_qubo.hip"),
            os.path.join(CSRC, "sg_probe.hip"),
            os.path.join(CSRC, "sg_api.cpp")]
 HEADERS = [os.path.join(CSRC, "sg_internal.h"),

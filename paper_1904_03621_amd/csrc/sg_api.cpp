@@ -8,6 +8,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -37,6 +38,18 @@ hipError_t launch_logz(int mode, const LzArgs& a, const float* J, const float* h
                        hipStream_t st);
 hipError_t launch_lz_final(int mode, const LzArgs& a, double* logz, float* grad_J, float* grad_h,
                            hipStream_t st);
+hipError_t launch_dos_prologue(const Batch& bt, long long e_min, int n_bins,
+                               unsigned long long* counts, hipStream_t st);
+hipError_t launch_dos(const Batch& bt, const Chunk& ch, long long e_min, int n_bins,
+                      unsigned long long* counts, hipStream_t st);
+hipError_t launch_dos_direct(const Batch& bt, long long e_min, unsigned long long* counts,
+                             hipStream_t st);
+hipError_t launch_energy_bound(int N, const int32_t* J, const int32_t* h, long long* out,
+                               hipStream_t st);
+hipError_t launch_qubo_to_ising(int N, const float* A, const float* b, float* J, float* h,
+                                hipStream_t st);
+hipError_t launch_qubo_finish(int N, const float* A, const float* b, int S, const uint64_t* found,
+                              uint64_t* states_out, float* energies_out, hipStream_t st);
 }  // namespace sg
 
 using namespace sg;
@@ -148,6 +161,15 @@ struct Workspace {
   // log Z walk
   double* table64 = nullptr;
   size_t ntable64 = 0;
+  // QUBO front end: the Ising instance and the states found before rescoring
+  float* qJ = nullptr;
+  size_t nqJ = 0;
+  float* qh = nullptr;
+  size_t nqh = 0;
+  uint64_t* qfound = nullptr;
+  size_t nqfound = 0;
+  float* qenergy = nullptr;
+  size_t nqenergy = 0;
   float* lzq = nullptr;        // [B][4][3 * 64] exp(-beta (Q - min Q)) tables
   size_t nlzq = 0;
   double* lzqmin = nullptr;    // [B] min Q
@@ -388,12 +410,27 @@ sg_status run_search(bool isint, int N, const void* J, const void* h, int S, uin
   return SG_OK;
 }
 
+// Level geometry of the batched search: n = log2(level size) - shift free
+// spins per lane (clamped).  The default suits the 256-CU device; the tuner
+// (sg_tune_batched_f32) may pick another shift per (device, N_max, S).
+constexpr int kShiftDefault = 12;
+constexpr int kShiftMin = 9, kShiftMax = 15;
+std::map<std::tuple<int, int, int>, int> g_shift;  // (device, N_max, S) -> shift
+
+int batch_shift(int Nmax, int S) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return kShiftDefault;
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_shift.find(std::make_tuple(dev, Nmax, S));
+  return it == g_shift.end() ? kShiftDefault : it->second;
+}
+
 // Chunk levels of a batched search.  Level 0 is [0, first) with
 // first = max(S, 64) rounded up to a power of two (every state of it is a
 // candidate, so it is kept small); level j >= 1 is [first 2^(j-1), first 2^j),
 // so every level is as large as everything before it and brings about S
 // candidates.  All instances with states in a level run it in the same launch,
-// with the same geometry: n = clamp(log2(size) - 12, U, 17) free spins per
+// with the same geometry: n = clamp(log2(size) - shift, U, 17) free spins per
 // lane.
 struct Level {
   uint64_t first;
@@ -401,7 +438,7 @@ struct Level {
   int64_t lanes;
 };
 
-std::vector<Level> batch_levels(int Nmax, int S) {
+std::vector<Level> batch_levels(int Nmax, int S, int shift) {
   std::vector<Level> out;
   uint64_t size0 = kBlockSteps;
   while (size0 < (uint64_t)S) size0 <<= 1;
@@ -409,7 +446,7 @@ std::vector<Level> batch_levels(int Nmax, int S) {
   uint64_t first = 0, size = size0;
   while (first < full) {
     const int a = ilog2_floor(size);
-    int n = std::max(kU, std::min(kBatchFreeCap, a - 12));
+    int n = std::max(kU, std::min(kBatchFreeCap, a - shift));
     n = std::min(n, a);
     out.push_back(Level{first, n, (int64_t)(size >> n)});
     first += size;
@@ -424,7 +461,7 @@ sg_status batch_search(Workspace* w, bool isint, const Batch& bt, int Nmax, int 
                        uint64_t* states_out, void* energies_out, hipStream_t st) {
   HIP_TRY(launch_prep(isint, bt, st));
   HIP_TRY(launch_tables(isint, bt, ncap, st));
-  const std::vector<Level> levels = batch_levels(Nmax, bt.S);
+  const std::vector<Level> levels = batch_levels(Nmax, bt.S, batch_shift(Nmax, bt.S));
   w->ev_used = 0;
   w->last_launches = 0;
   double states = 0.0;
@@ -669,6 +706,138 @@ sg_status sg_reserve(int B_max, int N_max, int S_max, void* stream) {
     v = lz_buffers(w, B_max, N_max);
     if (v != SG_OK) return v;
   }
+  return SG_OK;
+}
+
+sg_status sg_energy_bound_i32(int N, const int32_t* J, const int32_t* h, long long* bound_out,
+                              void* stream) {
+  g_last_error.clear();
+  if (N < 1 || N > SG_MAX_N) return fail(SG_EINVAL, "N must be in [1, SG_MAX_N]");
+  if (!J || !h || !bound_out) return fail(SG_EINVAL, "null pointer argument");
+  HIP_TRY(launch_energy_bound(N, J, h, bound_out, (hipStream_t)stream));
+  return SG_OK;
+}
+
+sg_status sg_density_of_states_i32(int N, const int32_t* J, const int32_t* h, long long e_min,
+                                   int n_bins, unsigned long long* counts_out, void* stream) {
+  g_last_error.clear();
+  if (N < 1 || N > SG_MAX_N) return fail(SG_EINVAL, "N must be in [1, SG_MAX_N]");
+  if (n_bins < 1 || n_bins > SG_MAX_DOS_BINS)
+    return fail(SG_EINVAL, "n_bins must be in [1, SG_MAX_DOS_BINS]");
+  if (!J || !h || !counts_out) return fail(SG_EINVAL, "null pointer argument");
+  hipStream_t st = (hipStream_t)stream;
+  const size_t recs = table_records(kMaxFree);
+  Workspace* w = nullptr;
+  sg_status v = ws_get(st, 1, recs, 1, 1, &w);
+  if (v != SG_OK) return v;
+  const Batch bt = make_batch(w, J, h, nullptr, N, N, 1, 1, (int64_t)recs, 1);
+  HIP_TRY(launch_prep(true, bt, st));
+  HIP_TRY(launch_dos_prologue(bt, e_min, n_bins, counts_out, st));
+  w->ev_used = 0;
+  w->last_launches = 0;
+  double states = 0.0;
+  if (N < kU) {
+    HIP_TRY(launch_dos_direct(bt, e_min, counts_out, st));
+    states = (double)((uint64_t)1 << N);
+  } else {
+    // n free spins per lane: at most kMaxFree, fewer while the prefixes would
+    // not give every resident lane one; launches of at most `fill` lanes
+    const int64_t fill = w->fill[1];
+    int n = std::min(kMaxFree, N);
+    while (n > kU && ((int64_t)1 << (N - n)) < fill) --n;
+    HIP_TRY(launch_tables(true, bt, n, st));
+    const uint64_t prefixes = (uint64_t)1 << (N - n);
+    for (uint64_t base = 0; base < prefixes; base += (uint64_t)fill) {
+      Chunk ch{};
+      ch.prefix_base = base;
+      ch.first_mask = base << n;
+      ch.lanes = (int64_t)std::min<uint64_t>((uint64_t)fill, prefixes - base);
+      ch.n = n;
+      ch.table_offset = (1 << (n - kU)) - 1;
+      HIP_TRY(launch_dos(bt, ch, e_min, n_bins, counts_out, st));
+      ++w->last_launches;
+      states += (double)ch.lanes * (double)((uint64_t)1 << n);
+    }
+  }
+  w->last_chunks = w->last_launches;
+  w->last_states = states;
+  return SG_OK;
+}
+
+sg_status sg_tune_batched_f32(int B, const int32_t* N_dev, int N_max, const float* J,
+                              const float* h, int S, int* shift_out, void* stream) {
+  g_last_error.clear();
+  if (!shift_out) return fail(SG_EINVAL, "null pointer argument");
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  hipStream_t st = (hipStream_t)stream;
+  uint64_t* tm = nullptr;
+  float* te = nullptr;
+  HIP_TRY(hipMalloc(&tm, sizeof(uint64_t) * (size_t)std::max(B, 1) * std::max(S, 1)));
+  HIP_TRY(hipMalloc(&te, sizeof(float) * (size_t)std::max(B, 1) * std::max(S, 1)));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  const auto key = std::make_tuple(dev, N_max, S);
+  float best_ms = 0.0f;
+  int best = kShiftDefault;
+  sg_status v = SG_OK;
+  for (int shift = kShiftMin; shift <= kShiftMax && v == SG_OK; ++shift) {
+    {
+      std::lock_guard<std::mutex> lk(g_mu);
+      g_shift[key] = shift;
+    }
+    v = sg_low_spectrum_batched_f32(B, N_dev, N_max, J, h, S, tm, te, stream);  // warm-up
+    if (v != SG_OK) break;
+    float ms = 0.0f;
+    for (int r = 0; r < 2 && v == SG_OK; ++r) {
+      if (hipEventRecord(e0, st) != hipSuccess) v = fail(SG_EHIP, "hipEventRecord");
+      if (v == SG_OK) v = sg_low_spectrum_batched_f32(B, N_dev, N_max, J, h, S, tm, te, stream);
+      if (v == SG_OK && hipEventRecord(e1, st) != hipSuccess) v = fail(SG_EHIP, "hipEventRecord");
+      if (v == SG_OK && hipEventSynchronize(e1) != hipSuccess) v = fail(SG_EHIP, "sync");
+      float t = 0.0f;
+      if (v == SG_OK && hipEventElapsedTime(&t, e0, e1) != hipSuccess) v = fail(SG_EHIP, "time");
+      ms += t;
+    }
+    if (v == SG_OK && sg_get_error(stream) != SG_OK) v = SG_EINVAL;
+    if (v == SG_OK && (shift == kShiftMin || ms < best_ms)) {
+      best_ms = ms;
+      best = shift;
+    }
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (v == SG_OK) g_shift[key] = best;
+    else g_shift.erase(key);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(tm);
+  (void)hipFree(te);
+  if (v != SG_OK) return v;
+  *shift_out = best;
+  return SG_OK;
+}
+
+sg_status sg_low_spectrum_qubo_f32(int N, const float* A, const float* b, int S,
+                                   uint64_t* states_out, float* energies_out, void* stream) {
+  g_last_error.clear();
+  if (N < 1 || N > SG_MAX_N) return fail(SG_EINVAL, "N must be in [1, SG_MAX_N]");
+  if (S < 1 || S > kQuboSortCap || (N < 63 && (uint64_t)S > ((uint64_t)1 << N)))
+    return fail(SG_EINVAL, "S must be in [1, min(SG_MAX_S_BATCHED, 2^N)]");
+  if (!A || !b || !states_out || !energies_out) return fail(SG_EINVAL, "null pointer argument");
+  hipStream_t st = (hipStream_t)stream;
+  Workspace* w = nullptr;
+  sg_status v = ws_get(st, 1, 1, 1, 1, &w);
+  if (v != SG_OK) return v;
+  HIP_TRY(grow(&w->qJ, &w->nqJ, (size_t)N * N));
+  HIP_TRY(grow(&w->qh, &w->nqh, (size_t)N));
+  HIP_TRY(grow(&w->qfound, &w->nqfound, (size_t)S));
+  HIP_TRY(grow(&w->qenergy, &w->nqenergy, (size_t)S));
+  HIP_TRY(launch_qubo_to_ising(N, A, b, w->qJ, w->qh, st));
+  v = run_search(false, N, w->qJ, w->qh, S, 0, (uint64_t)1 << N, w->qfound, w->qenergy, stream);
+  if (v != SG_OK) return v;
+  HIP_TRY(launch_qubo_finish(N, A, b, S, w->qfound, states_out, energies_out, st));
   return SG_OK;
 }
 

@@ -36,6 +36,7 @@ constexpr int kMergeBatchThreads = 256;  // threads per instance in the batched 
 constexpr int kBatchFreeCap = 17;     // largest n of a batched search
 constexpr int kLdsSortCap = 4096;     // survivors sorted in LDS up to this
 constexpr int kLdsSortCapBatch = 1024;  // the same for the per-instance batched merge
+constexpr int kQuboSortCap = 4096;    // states of a QUBO search (sorted in LDS)
 constexpr int kMaxN = 56;
 
 // Sticky device error bits (mapped to sg_status on the host).
@@ -72,6 +73,7 @@ struct Params {
   // threshold (at most kRetries times)
   uint32_t redo;
   uint32_t stat_redo;       // repeated passes taken
+  double bound;             // sum_{i<j} |J_ij| + sum_i |h_i| (no |E| exceeds it)
 };
 
 // Extra passes over a chunk whose candidates overflowed the buffer.

@@ -243,6 +243,7 @@ __global__ void k_prep(Batch bt) {
     P->surv_count = 0;
     P->redo = 0;
     P->stat_redo = 0;
+    P->bound = Bv;
     P->stat_candidates = 0;
     P->stat_slow = 0;
     P->max_drift_bits = 0;

@@ -83,6 +83,18 @@ def test_batched_and_logz_validation_is_synchronous(L, case):
         assert st == L.SG_EINVAL and L.last_error() != ""
 
 
+@pytest.mark.parametrize("case", [dict(N=0), dict(N=57), dict(n_bins=0), dict(n_bins=8193),
+                                  dict(null=True)])
+def test_dos_validation_is_synchronous(L, case):
+    lib = L.lib()
+    N, n_bins = case.get("N", 12), case.get("n_bins", 100)
+    p = 0 if case.get("null") else 4096  # never dereferenced: validation fails first
+    assert lib.sg_density_of_states_i32(N, p, p, -50, n_bins, p, 0) == L.SG_EINVAL
+    assert L.last_error() != ""
+    if "n_bins" not in case:
+        assert lib.sg_energy_bound_i32(N, p, p, p, 0) == L.SG_EINVAL
+
+
 @pytest.mark.parametrize("args", [(0, 20, 8), (4, 0, 8), (4, 57, 8), (4, 20, 0),
                                   (4, 20, (1 << 20) + 1)])
 def test_reserve_validation(L, args):

@@ -210,3 +210,18 @@ def test_full_workload_4096(orc, torch_dev):
         om, oe = orc.low_spectrum(J[b, :n, :n], h[b, :n], S)
         check_f32(n, J[b, :n, :n], bm[b], be[b], om, oe,
                   lambda x: orc.energy(J[b, :n, :n], h[b, :n], x), "instance %d" % b)
+
+
+def test_tuner_keeps_results(torch_dev):
+    """The tuner times every level geometry and keeps the fastest; the search is
+    exact, so the results are the same before and after tuning."""
+    import paper_1904_03621_amd as sg
+    torch = torch_dev
+    B, S = 96, 16
+    Ns, J, h = make_batch(B, 10, 23, 13, False, Nmax=24)
+    Nt, Jt, ht = (torch.from_numpy(x).cuda() for x in (Ns, J, h))
+    m0, e0 = sg.low_spectrum_batched(Nt, Jt, ht, S)
+    shift = sg.sg_tune_batched_f32(B, Nt, J.shape[1], Jt, ht, S)
+    assert 9 <= shift <= 15
+    m1, e1 = sg.low_spectrum_batched(Nt, Jt, ht, S)
+    assert torch.equal(m0, m1) and torch.equal(e0, e1)
