@@ -34,17 +34,23 @@ COPY_BYTES = 512 << 20
 # (KiB per dispatch, averaged over the 447 dispatches of one search), scaled by
 # what the same counters read for the 512 MiB copy (fetch x2.0, write x1.0);
 # valid for the k_enum source with this SHA-256 prefix only
-TRAFFIC = {"kenum_sha256_16": "3e060cfefc8c40cb", "fetch_kib": 2157436.5 / 447,
+TRAFFIC = {"kenum_sha256_16": "9f8e50b3d43542d7", "fetch_kib": 2157436.5 / 447,
            "write_kib": 45094.5 / 447, "fetch_factor": 524288.0 / 262162.0, "write_factor": 1.0,
            "profile": "profiles/k_enum_f32_dense48_counters.md"}
 
 
 def kenum_source_hash() -> str:
+    """SHA-256 prefix of the k_enum function's source with comments and
+    whitespace removed (layout and comment edits do not change the kernel)."""
     import hashlib
+    import re
     src = open(os.path.join(ROOT, "paper_1904_03621_amd", "csrc", "sg_kernels.hip")).read()
     i = src.index("void k_enum(Batch bt")
     j = src.index("\n}\n", i)
-    return hashlib.sha256(src[i:j].encode()).hexdigest()[:16]
+    body = re.sub(r"//[^\n]*", "", src[i:j])
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    body = re.sub(r"\s+", "", body)
+    return hashlib.sha256(body.encode()).hexdigest()[:16]
 
 
 def traffic_per_launch():

@@ -572,25 +572,25 @@ __global__ __launch_bounds__(kEnumBlock, 8) void k_enum(Batch bt, const void* __
       const uint64_t pl = ch.prefix_base + (uint64_t)lane;
 #pragma unroll
       for (int w = 0; w < kHitWords; ++w) {
-       uint64_t hw = (valid && pass) ? hits[w] : 0ull;
-       while (hw) {
-        const int i = 64 * w + __builtin_ctzll(hw);
-        hw &= hw - 1ull;
-        const uint64_t t = ((uint64_t)T << U) | (uint64_t)i;
-        const uint64_t mask = (pl << n) | (t ^ (t >> 1));
-        // the walk's energy of step i, from the block start: a low spin
-        // f < U-1 that is up at step i flipped an odd number of times from -1
-        // (net -W_f); spin U-1 flips once, at step 2^(U-1) (net +W_{U-1})
-        const uint32_t gi = (uint32_t)(i ^ (i >> 1));
-        V e = Gs;
+        uint64_t hw = (valid && pass) ? hits[w] : 0ull;
+        while (hw) {
+          const int i = 64 * w + __builtin_ctzll(hw);
+          hw &= hw - 1ull;
+          const uint64_t t = ((uint64_t)T << U) | (uint64_t)i;
+          const uint64_t mask = (pl << n) | (t ^ (t >> 1));
+          // the walk's energy of step i, from the block start: a low spin
+          // f < U-1 that is up at step i flipped an odd number of times from
+          // -1 (net -W_f); spin U-1 flips once, at step 2^(U-1) (net +W_{U-1})
+          const uint32_t gi = (uint32_t)(i ^ (i >> 1));
+          V e = Gs;
 #pragma unroll
-        for (int f = 0; f < U - 1; ++f)
-          if ((gi >> f) & 1u) e = e - W[f];
-        if ((gi >> (U - 1)) & 1u) e = e + W[U - 1];
-        e = e + qv(i);
-        const uint32_t key = kInt ? key_of_i32((int32_t)e) : key_f32((float)e);
-        append_mask(mask, key, P, cand, ckey, cand_cap);
-       }
+          for (int f = 0; f < U - 1; ++f)
+            if ((gi >> f) & 1u) e = e - W[f];
+          if ((gi >> (U - 1)) & 1u) e = e + W[U - 1];
+          e = e + qv(i);
+          const uint32_t key = kInt ? key_of_i32((int32_t)e) : key_f32((float)e);
+          append_mask(mask, key, P, cand, ckey, cand_cap);
+        }
       }
     }
   }

@@ -225,3 +225,14 @@ def test_tuner_keeps_results(torch_dev):
     assert 9 <= shift <= 15
     m1, e1 = sg.low_spectrum_batched(Nt, Jt, ht, S)
     assert torch.equal(m0, m1) and torch.equal(e0, e1)
+
+
+def test_maximum_S_batched(orc, torch_dev):
+    """S = SG_MAX_S_BATCHED (4096) over instances of 12..16 spins."""
+    B, S = 12, 4096
+    Ns, J, h = make_batch(B, 12, 16, 14, True)
+    bm, be = run_batched(torch_dev, Ns, J, h, S)
+    for b in range(B):
+        n = int(Ns[b])
+        om, oe = orc.low_spectrum(J[b, :n, :n], h[b, :n], S)
+        check_int(bm[b], be[b], om, oe, "batch S=4096 instance %d" % b)

@@ -185,3 +185,29 @@ def test_validation_errors(torch_dev):
         gpu_search(torch_dev, J, h, 257)       # S > 2^N
     with pytest.raises(sg.SgError):
         gpu_search(torch_dev, J, h, 4, 10, 64)  # lo not 64-aligned
+
+
+def test_maximum_S_single(orc, torch_dev):
+    """S = SG_MAX_S (2^20) on the N = 24 integer workload: bit-exact."""
+    J, h = I.random_int_dense(24, 1)
+    compare(orc, torch_dev, J, h, 1 << 20, what="N=24 S=2^20")
+
+
+def test_maximum_N_range(orc, torch_dev):
+    """N = SG_MAX_N = 56 through the range API: a 2^20-mask slice high in the
+    space (masks above 2^55) against the oracle on the same slice."""
+    N = 56
+    J, h = I.random_int_dense(N, 56)
+    lo = (1 << 55) + (3 << 40)
+    compare(orc, torch_dev, J, h, 64, lo, lo + (1 << 20), what="N=56 slice")
+    Jf, hf = I.random_f32_dense(N, 57)
+    compare(orc, torch_dev, Jf, hf, 64, lo, lo + (1 << 20), what="N=56 f32 slice")
+
+
+def test_every_state_at_block_boundaries(orc, torch_dev):
+    """N = 7 and 8 (one and two 128-state blocks): every state, both paths."""
+    for N in (7, 8):
+        J, h = I.random_int_dense(N, 300 + N)
+        compare(orc, torch_dev, J, h, 1 << N, what="int N=%d all" % N)
+        Jf, hf = I.random_f32_dense(N, 310 + N, j_scale=1.0, h_scale=0.3)
+        compare(orc, torch_dev, Jf, hf, 1 << N, what="f32 N=%d all" % N)
