@@ -406,38 +406,57 @@ __global__ __launch_bounds__(kEnumBlock, 8) void k_enum(Batch bt, const void* __
   // ---- per-lane init (exact in int64 / fp64) --------------------------------
   // y_f = sum_{q >= n} J_fq s_q (field on free spin f from the prefix);
   // E_P = energy of the prefix spins alone.  WL_f = 2 y_f for the low spins,
-  // Y_g = 2 y_g for the high ones.
+  // Y_g = 2 y_g for the high ones.  Every lane reads the same couplings, so
+  // they are staged in LDS first (in the space of the high fields, which are
+  // written only once the stage has been read): the serial sums then wait on
+  // LDS rather than on scalar-cache misses.
+  V* s_stage = s_y;  // N*N couplings (row stride N), then the N fields
+  for (int k = tid; k < N * N + N; k += kEnumBlock)
+    s_stage[k] = k < N * N ? Jt[(k / N) * ld + (k % N)] : ht[k - N * N];
+  __syncthreads();
   V WL[U];
   A ysum = 0;
 #pragma unroll
   for (int f = 0; f < U; ++f) {
     A acc = 0;
+#pragma unroll 4
     for (int q = n; q < N; ++q) {
-      const A jq = (A)Jt[f * ld + q];
+      const A jq = (A)s_stage[f * N + q];
       acc += ((p >> (q - n)) & 1ull) ? jq : -jq;
     }
     ysum += acc;
     WL[f] = valid ? (V)(2 * acc) : (V)0;
   }
-  for (int f = U; f < n; ++f) {
-    A acc = 0;
-    for (int q = n; q < N; ++q) {
-      const A jq = (A)Jt[f * ld + q];
-      acc += ((p >> (q - n)) & 1ull) ? jq : -jq;
+  V yh[kMaxHigh];
+#pragma unroll
+  for (int k = 0; k < kMaxHigh; ++k) {
+    yh[k] = (V)0;
+    if (k < n - U) {
+      A acc = 0;
+#pragma unroll 4
+      for (int q = n; q < N; ++q) {
+        const A jq = (A)s_stage[(U + k) * N + q];
+        acc += ((p >> (q - n)) & 1ull) ? jq : -jq;
+      }
+      ysum += acc;
+      yh[k] = valid ? (V)(2 * acc) : (V)0;
     }
-    ysum += acc;
-    s_y[(f - U) * kEnumBlock + tid] = valid ? (V)(2 * acc) : (V)0;
   }
   A EP = 0;
   for (int q = n; q < N; ++q) {
     const A sq = ((p >> (q - n)) & 1ull) ? (A)1 : (A)-1;
-    A f = (A)ht[q];
+    A f = (A)s_stage[N * N + q];
+#pragma unroll 4
     for (int r = q + 1; r < N; ++r) {
-      const A jr = (A)Jt[q * ld + r];
+      const A jr = (A)s_stage[q * N + r];
       f += ((p >> (r - n)) & 1ull) ? jr : -jr;
     }
     EP -= sq * f;
   }
+  __syncthreads();  // every lane has read the stage
+#pragma unroll
+  for (int k = 0; k < kMaxHigh; ++k)
+    if (k < n - U) s_y[k * kEnumBlock + tid] = yh[k];
   V G;
   {
     const uint32_t r0 = tab[1];
