@@ -144,7 +144,7 @@ sg_status sg_low_spectrum_batched_i32(int B, const int32_t *N_dev, int N_max, co
  * Exact log partition function of B instances of N spins (fp32 couplings):
  *   Z_b(beta) = sum over all 2^N states s of exp(-beta E_b(s)),
  * the normaliser of the Boltzmann distribution at inverse temperature beta
- * (Sec. 5.2, Eq. 8) for the energy of Eq. (1).  The S lowest states are found
+ * (Sec. 5.2, Eq. 10) for the energy of Eq. (1).  The S lowest states are found
  * first (the batched search); log Z is then computed as
  *   log Z = -beta E0 + log sum_s exp(-beta (E(s) - E0)),
  * with E0 the lowest energy, so that no weight exceeds 1.
@@ -177,7 +177,7 @@ sg_status sg_logz_forward_f32(int B, int N, const float *J, const float *h, int 
  *   dL/dJ_ij = sum_k g[b][k] beta_k <s_i s_j>_k   (i < j)
  *   dL/dh_i  = sum_k g[b][k] beta_k <s_i>_k
  * with <.>_k the average under the Boltzmann distribution at beta_k (Sec. 5.2,
- * Eq. 8).  The enumeration is walked again (no per-state storage) with the
+ * Eq. 10).  The enumeration is walked again (no per-state storage) with the
  * combined weight sum_k (g[b][k] beta_k / Z_k) exp(-beta_k E(s)).
  *
  *   B, N, J, h, n_beta, beta  as for sg_logz_forward_f32
@@ -260,13 +260,14 @@ sg_status sg_reserve(int B_max, int N_max, int S_max, void *stream);
 
 /*
  * Tuner of the batched search: times sg_low_spectrum_batched_f32 on this
- * batch for each level geometry it can use (free spins per lane n =
- * log2(level size) - shift, shift in 9..15) and keeps the fastest for later
- * batched calls on this device with the same N_max and S; *shift_out is the
- * choice.  Results do not depend on the geometry (the search is exact).
- * Synchronous; allocates scratch and runs the search 21 times; call it before
- * capturing a graph of batched calls (the geometry fixes the launch sequence).
- * Arguments as for sg_low_spectrum_batched_f32.
+ * batch for the level geometries around the default (free spins per lane n =
+ * log2(level size) - shift; by default shift = max(12, ceil(log2(2 L / B))),
+ * L the device's resident lanes; the tuner tries that shift -3 .. +3) and keeps the
+ * fastest for later batched calls on this device with the same B, N_max and
+ * S; *shift_out is the choice.  Results do not depend on the geometry (the
+ * search is exact).  Synchronous; allocates scratch and runs the search 21
+ * times; call it before capturing a graph of batched calls (the geometry fixes
+ * the launch sequence).  Arguments as for sg_low_spectrum_batched_f32.
  */
 sg_status sg_tune_batched_f32(int B, const int32_t *N_dev, int N_max, const float *J,
                               const float *h, int S, int *shift_out, void *stream);

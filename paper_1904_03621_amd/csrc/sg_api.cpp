@@ -411,22 +411,35 @@ sg_status run_search(bool isint, int N, const void* J, const void* h, int S, uin
 }
 
 // Level geometry of the batched search: n = log2(level size) - shift free
-// spins per lane (clamped).  The default suits the 256-CU device; the tuner
-// (sg_tune_batched_f32) may pick another shift per (device, N_max, S).
-constexpr int kShiftDefault = 12;
-constexpr int kShiftMin = 9, kShiftMax = 15;
-std::map<std::tuple<int, int, int>, int> g_shift;  // (device, N_max, S) -> shift
+// spins per lane (clamped), i.e. 2^shift lanes per instance.  The default is
+// 2^12 lanes per instance, the fastest geometry measured on 4096 instances of
+// 16..32 spins (fewer free spins per lane spend more of each lane on its
+// set-up; more leave too few lanes once the smaller instances have finished),
+// and more when B is too small for B 2^shift to reach twice the device's
+// resident lanes.  The tuner (sg_tune_batched_f32) may pick another shift per
+// (device, B, N_max, S).
+constexpr int kShiftFloor = 12;
+constexpr int kShiftSpan = 3;  // the tuner tries default - 3 .. default + 3
+std::map<std::tuple<int, int, int, int>, int> g_shift;  // (device, B, N_max, S) -> shift
 
-int batch_shift(int Nmax, int S) {
+int default_shift(int B, int64_t fill) {
+  int shift = 0;
+  while (shift < 40 && ((int64_t)B << shift) < 2 * fill) ++shift;
+  return std::max(shift, kShiftFloor);
+}
+
+int batch_shift(int B, int Nmax, int S, int64_t fill) {
   int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return kShiftDefault;
-  std::lock_guard<std::mutex> lk(g_mu);
-  auto it = g_shift.find(std::make_tuple(dev, Nmax, S));
-  return it == g_shift.end() ? kShiftDefault : it->second;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_shift.find(std::make_tuple(dev, B, Nmax, S));
+    if (it != g_shift.end()) return it->second;
+  }
+  return default_shift(B, fill);
 }
 
 // Chunk levels of a batched search.  Level 0 is [0, first) with
-// first = max(S, 64) rounded up to a power of two (every state of it is a
+// first = max(S, 128) rounded up to a power of two (every state of it is a
 // candidate, so it is kept small); level j >= 1 is [first 2^(j-1), first 2^j),
 // so every level is as large as everything before it and brings about S
 // candidates.  All instances with states in a level run it in the same launch,
@@ -461,7 +474,8 @@ sg_status batch_search(Workspace* w, bool isint, const Batch& bt, int Nmax, int 
                        uint64_t* states_out, void* energies_out, hipStream_t st) {
   HIP_TRY(launch_prep(isint, bt, st));
   HIP_TRY(launch_tables(isint, bt, ncap, st));
-  const std::vector<Level> levels = batch_levels(Nmax, bt.S, batch_shift(Nmax, bt.S));
+  const std::vector<Level> levels =
+      batch_levels(Nmax, bt.S, batch_shift(bt.B, Nmax, bt.S, w->fill[isint ? 1 : 0]));
   w->ev_used = 0;
   w->last_launches = 0;
   double states = 0.0;
@@ -768,27 +782,35 @@ sg_status sg_tune_batched_f32(int B, const int32_t* N_dev, int N_max, const floa
                               const float* h, int S, int* shift_out, void* stream) {
   g_last_error.clear();
   if (!shift_out) return fail(SG_EINVAL, "null pointer argument");
+  if (B < 1 || S < 1) return fail(SG_EINVAL, "B and S must be >= 1");
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
   hipStream_t st = (hipStream_t)stream;
+  Workspace* w = nullptr;
+  sg_status v = ws_get(st, B, 1, 1, 1, &w);
+  if (v != SG_OK) return v;
+  const auto key = std::make_tuple(dev, B, N_max, S);
+  const int centre = default_shift(B, w->fill[0]);
+  const int lo_shift = std::max(0, centre - kShiftSpan), hi_shift = centre + kShiftSpan;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_shift.erase(key);
+  }
   uint64_t* tm = nullptr;
   float* te = nullptr;
-  HIP_TRY(hipMalloc(&tm, sizeof(uint64_t) * (size_t)std::max(B, 1) * std::max(S, 1)));
-  HIP_TRY(hipMalloc(&te, sizeof(float) * (size_t)std::max(B, 1) * std::max(S, 1)));
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  HIP_TRY(hipEventCreate(&e0));
-  HIP_TRY(hipEventCreate(&e1));
-  const auto key = std::make_tuple(dev, N_max, S);
+  if (hipMalloc(&tm, sizeof(uint64_t) * (size_t)B * S) != hipSuccess ||
+      hipMalloc(&te, sizeof(float) * (size_t)B * S) != hipSuccess ||
+      hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    v = fail(SG_ENOMEM, "tuner scratch allocation failed");
   float best_ms = 0.0f;
-  int best = kShiftDefault;
-  sg_status v = SG_OK;
-  for (int shift = kShiftMin; shift <= kShiftMax && v == SG_OK; ++shift) {
+  int best = centre;
+  for (int shift = lo_shift; shift <= hi_shift && v == SG_OK; ++shift) {
     {
       std::lock_guard<std::mutex> lk(g_mu);
       g_shift[key] = shift;
     }
     v = sg_low_spectrum_batched_f32(B, N_dev, N_max, J, h, S, tm, te, stream);  // warm-up
-    if (v != SG_OK) break;
     float ms = 0.0f;
     for (int r = 0; r < 2 && v == SG_OK; ++r) {
       if (hipEventRecord(e0, st) != hipSuccess) v = fail(SG_EHIP, "hipEventRecord");
@@ -799,8 +821,8 @@ sg_status sg_tune_batched_f32(int B, const int32_t* N_dev, int N_max, const floa
       if (v == SG_OK && hipEventElapsedTime(&t, e0, e1) != hipSuccess) v = fail(SG_EHIP, "time");
       ms += t;
     }
-    if (v == SG_OK && sg_get_error(stream) != SG_OK) v = SG_EINVAL;
-    if (v == SG_OK && (shift == kShiftMin || ms < best_ms)) {
+    if (v == SG_OK) v = sg_get_error(stream);
+    if (v == SG_OK && (shift == lo_shift || ms < best_ms)) {
       best_ms = ms;
       best = shift;
     }
@@ -810,10 +832,10 @@ sg_status sg_tune_batched_f32(int B, const int32_t* N_dev, int N_max, const floa
     if (v == SG_OK) g_shift[key] = best;
     else g_shift.erase(key);
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  (void)hipFree(tm);
-  (void)hipFree(te);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (tm) (void)hipFree(tm);
+  if (te) (void)hipFree(te);
   if (v != SG_OK) return v;
   *shift_out = best;
   return SG_OK;

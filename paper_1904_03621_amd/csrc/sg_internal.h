@@ -36,6 +36,7 @@ constexpr int kMergeBatchThreads = 256;  // threads per instance in the batched 
 constexpr int kBatchFreeCap = 17;     // largest n of a batched search
 constexpr int kLdsSortCap = 4096;     // survivors sorted in LDS up to this
 constexpr int kLdsSortCapBatch = 1024;  // the same for the per-instance batched merge
+constexpr int kRankByCount = 512;     // merges of up to this many entries rank by counting
 constexpr int kQuboSortCap = 4096;    // states of a QUBO search (sorted in LDS)
 constexpr int kMaxN = 56;
 

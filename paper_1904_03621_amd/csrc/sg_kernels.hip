@@ -36,17 +36,24 @@ __device__ inline const T* inst_h(const Batch& bt, int b) {
 __device__ inline uint32_t gray32(uint32_t t) { return t ^ (t >> 1); }
 
 // Energy of one state from scratch, Eq. (1), fixed i<j order; J has row
-// stride ld.
+// stride ld.  A row's couplings are read eight at a time before they are
+// summed (in the same order), so the reads overlap instead of each waiting
+// on the previous add; s_j J_ij is formed as +-J_ij (exact).
 __device__ inline double energy_f64(const float* J, const float* h, int N, int ld, uint64_t m) {
   double e = 0.0;
   for (int i = 0; i < N; ++i) {
-    const double si = ((m >> i) & 1ull) ? 1.0 : -1.0;
+    const float* row = J + i * ld;
     double f = (double)h[i];
-    for (int j = i + 1; j < N; ++j) {
-      const double sj = ((m >> j) & 1ull) ? 1.0 : -1.0;
-      f += (double)J[i * ld + j] * sj;
+    int j = i + 1;
+    for (; j + 8 <= N; j += 8) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = row[j + u];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) f += ((m >> (j + u)) & 1ull) ? (double)v[u] : -(double)v[u];
     }
-    e -= si * f;
+    for (; j < N; ++j) f += ((m >> j) & 1ull) ? (double)row[j] : -(double)row[j];
+    e -= ((m >> i) & 1ull) ? f : -f;
   }
   return e;
 }
@@ -55,13 +62,18 @@ __device__ inline int32_t energy_i32(const int32_t* J, const int32_t* h, int N, 
                                      uint64_t m) {
   int32_t e = 0;
   for (int i = 0; i < N; ++i) {
-    const int32_t si = ((m >> i) & 1ull) ? 1 : -1;
+    const int32_t* row = J + i * ld;
     int32_t f = h[i];
-    for (int j = i + 1; j < N; ++j) {
-      const int32_t sj = ((m >> j) & 1ull) ? 1 : -1;
-      f += J[i * ld + j] * sj;
+    int j = i + 1;
+    for (; j + 8 <= N; j += 8) {
+      int32_t v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = row[j + u];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) f += ((m >> (j + u)) & 1ull) ? v[u] : -v[u];
     }
-    e -= si * f;
+    for (; j < N; ++j) f += ((m >> j) & 1ull) ? row[j] : -row[j];
+    e -= ((m >> i) & 1ull) ? f : -f;
   }
   return e;
 }
@@ -393,7 +405,9 @@ __global__ __launch_bounds__(kEnumBlock, 8) void k_enum(Batch bt, const void* __
   const int ld = bt.ld;
   const int64_t lane = (int64_t)blk * kEnumBlock + tid;
   const bool valid = lane < lanes;
-  const uint64_t p = ch.prefix_base + (uint64_t)(valid ? lane : 0);
+  // the workgroup's lanes hold the consecutive prefixes p0 .. p0 + 255
+  const uint64_t p0 = ch.prefix_base + (uint64_t)blk * kEnumBlock;
+  const uint64_t p = p0 + (uint64_t)(valid ? tid : 0);
   const uint32_t* tab =
       table + ((size_t)b * bt.table_recs + (size_t)ch.table_offset) * kRecWords;
   uint64_t* cand = bt.cand + (size_t)b * bt.cap;
@@ -406,23 +420,64 @@ __global__ __launch_bounds__(kEnumBlock, 8) void k_enum(Batch bt, const void* __
   // ---- per-lane init (exact in int64 / fp64) --------------------------------
   // y_f = sum_{q >= n} J_fq s_q (field on free spin f from the prefix);
   // E_P = energy of the prefix spins alone.  WL_f = 2 y_f for the low spins,
-  // Y_g = 2 y_g for the high ones.  Every lane reads the same couplings, so
-  // they are staged in LDS first (in the space of the high fields, which are
-  // written only once the stage has been read): the serial sums then wait on
-  // LDS rather than on scalar-cache misses.
+  // Y_g = 2 y_g for the high ones.
+  // The prefix spins split into the kLaneBits lowest ("L": spins n .. n+kl-1,
+  // different in every lane) and the rest ("H": spins n+kl .. N-1, bits of
+  // p >> kLaneBits, which is h0 or h0 + 1 in a workgroup).  The H parts --
+  // the fields F of H on the free and L spins and the energy E_H of H alone --
+  // are summed once per workgroup for both values of p >> kLaneBits; a lane
+  // adds only the kl L spins on top.  The couplings are staged in LDS first
+  // (in the space of the high fields, which are written only once the stage
+  // has been read).
+  constexpr int kLaneBits = 8;  // log2(kEnumBlock)
+  const int kl = min(N - n, kLaneBits);
+  const int qh = n + kl;      // first H spin
+  const int nf = n + kl;      // spins that take a field from H
+  const uint64_t h0 = p0 >> kLaneBits;
+  __shared__ A s_F[2][kMaxFree + kLaneBits];
+  __shared__ A s_R[2][kMaxN];
+  __shared__ A s_EH[2];
   V* s_stage = s_y;  // N*N couplings (row stride N), then the N fields
   for (int k = tid; k < N * N + N; k += kEnumBlock)
     s_stage[k] = k < N * N ? Jt[(k / N) * ld + (k % N)] : ht[k - N * N];
   __syncthreads();
+  for (int t = tid; t < 2 * nf; t += kEnumBlock) {
+    const int c = t >= nf, i = t - c * nf;
+    const uint64_t hb = h0 + (uint64_t)c;
+    A acc = 0;
+    for (int q = qh; q < N; ++q) {
+      const A jq = (A)s_stage[i * N + q];
+      acc += ((hb >> (q - qh)) & 1ull) ? jq : -jq;
+    }
+    s_F[c][i] = acc;
+  }
+  for (int t = tid; t < 2 * (N - qh); t += kEnumBlock) {
+    const int c = t >= N - qh, q = qh + t - c * (N - qh);
+    const uint64_t hb = h0 + (uint64_t)c;
+    A f = (A)s_stage[N * N + q];
+    for (int r = q + 1; r < N; ++r) {
+      const A jr = (A)s_stage[q * N + r];
+      f += ((hb >> (r - qh)) & 1ull) ? jr : -jr;
+    }
+    s_R[c][q - qh] = ((hb >> (q - qh)) & 1ull) ? f : -f;
+  }
+  __syncthreads();
+  if (tid < 2) {
+    A e = 0;
+    for (int q = 0; q < N - qh; ++q) e -= s_R[tid][q];
+    s_EH[tid] = e;
+  }
+  __syncthreads();
+  const int c = (int)((p >> kLaneBits) - h0);  // 0 or 1
+  const uint32_t pl = (uint32_t)p;             // bit j: spin n + j (j < kl)
   V WL[U];
   A ysum = 0;
 #pragma unroll
   for (int f = 0; f < U; ++f) {
-    A acc = 0;
-#pragma unroll 4
-    for (int q = n; q < N; ++q) {
-      const A jq = (A)s_stage[f * N + q];
-      acc += ((p >> (q - n)) & 1ull) ? jq : -jq;
+    A acc = s_F[c][f];
+    for (int j = 0; j < kl; ++j) {
+      const A jq = (A)s_stage[f * N + n + j];
+      acc += ((pl >> j) & 1u) ? jq : -jq;
     }
     ysum += acc;
     WL[f] = valid ? (V)(2 * acc) : (V)0;
@@ -432,26 +487,24 @@ __global__ __launch_bounds__(kEnumBlock, 8) void k_enum(Batch bt, const void* __
   for (int k = 0; k < kMaxHigh; ++k) {
     yh[k] = (V)0;
     if (k < n - U) {
-      A acc = 0;
-#pragma unroll 4
-      for (int q = n; q < N; ++q) {
-        const A jq = (A)s_stage[(U + k) * N + q];
-        acc += ((p >> (q - n)) & 1ull) ? jq : -jq;
+      A acc = s_F[c][U + k];
+      for (int j = 0; j < kl; ++j) {
+        const A jq = (A)s_stage[(U + k) * N + n + j];
+        acc += ((pl >> j) & 1u) ? jq : -jq;
       }
       ysum += acc;
       yh[k] = valid ? (V)(2 * acc) : (V)0;
     }
   }
-  A EP = 0;
-  for (int q = n; q < N; ++q) {
-    const A sq = ((p >> (q - n)) & 1ull) ? (A)1 : (A)-1;
-    A f = (A)s_stage[N * N + q];
-#pragma unroll 4
-    for (int r = q + 1; r < N; ++r) {
-      const A jr = (A)s_stage[q * N + r];
-      f += ((p >> (r - n)) & 1ull) ? jr : -jr;
+  A EP = s_EH[c];
+  for (int j = 0; j < kl; ++j) {
+    const int q = n + j;
+    A f = (A)s_stage[N * N + q] + s_F[c][q];
+    for (int r = j + 1; r < kl; ++r) {
+      const A jr = (A)s_stage[q * N + n + r];
+      f += ((pl >> r) & 1u) ? jr : -jr;
     }
-    EP -= sq * f;
+    EP -= ((pl >> j) & 1u) ? f : -f;
   }
   __syncthreads();  // every lane has read the stage
 #pragma unroll
@@ -751,11 +804,14 @@ __device__ inline bool in_record(const uint32_t* rkey, const uint64_t* rmask, ui
   return r < rn && rkey[r] == key && rmask[r] == m;
 }
 
-// The whole workgroup: sort the ns survivors (skey, smask) -- bitonic sort
-// in LDS when they fit, in global memory otherwise -- and merge them with
-// the sorted record (rank of an element = its index plus the number of
-// smaller elements in the other list; keys are distinct because masks are),
-// keeping the first S; publish the S-th key as the threshold.
+// The whole workgroup: merge the ns survivors (skey, smask) with the sorted
+// record, keeping the first S, and publish the S-th key as the threshold.
+// Keys are distinct because masks are, so an entry's place is its rank among
+// all of them.  Up to kRankByCount entries in all, the record and the
+// survivors are put side by side in LDS and every rank is counted directly;
+// beyond, the survivors are sorted (bitonic, in LDS when they fit, in global
+// memory otherwise) and an element's rank is its index plus the number of
+// smaller elements in the other list.
 __device__ void merge_body(Params* P, int S, uint32_t cap, bool last_pass, uint32_t ns,
                            uint32_t* skey, uint64_t* smask, uint32_t* rkey, uint64_t* rmask,
                            uint32_t* tkey, uint64_t* tmask, uint32_t* l_key, uint64_t* l_mask,
@@ -763,35 +819,54 @@ __device__ void merge_body(Params* P, int S, uint32_t cap, bool last_pass, uint3
   const uint32_t rn = P->rec_count;
   __syncthreads();
   if (ns > 0) {
-    uint32_t P2 = 1;
-    while (P2 < ns) P2 <<= 1;
-    uint32_t* ks;
-    uint64_t* ms;
-    if (P2 <= lds_cap) {
-      for (uint32_t t = threadIdx.x; t < P2; t += blockDim.x) {
-        l_key[t] = t < ns ? skey[t] : 0xFFFFFFFFu;
-        l_mask[t] = t < ns ? smask[t] : ~0ull;
-      }
-      ks = l_key;
-      ms = l_mask;
-    } else {
-      for (uint32_t t = ns + threadIdx.x; t < P2 && t < cap; t += blockDim.x) {
-        skey[t] = 0xFFFFFFFFu;
-        smask[t] = ~0ull;
-      }
-      ks = skey;
-      ms = smask;
-    }
-    __syncthreads();
-    bitonic_sort(ks, ms, P2);
     const uint32_t nn = min((uint32_t)S, rn + ns);
-    for (uint32_t a = threadIdx.x; a < rn; a += blockDim.x) {
-      const uint32_t r = a + rank_in(ks, ms, ns, rkey[a], rmask[a]);
-      if (r < nn) { tkey[r] = rkey[a]; tmask[r] = rmask[a]; }
-    }
-    for (uint32_t c = threadIdx.x; c < ns; c += blockDim.x) {
-      const uint32_t r = c + rank_in(rkey, rmask, rn, ks[c], ms[c]);
-      if (r < nn) { tkey[r] = ks[c]; tmask[r] = ms[c]; }
+    const uint32_t tot = rn + ns;
+    if (tot <= kRankByCount && tot <= lds_cap) {
+      // few entries: the record and the survivors side by side in LDS, each
+      // entry's rank counted against all of them
+      for (uint32_t t = threadIdx.x; t < tot; t += blockDim.x) {
+        const bool in_rec = t < rn;
+        l_key[t] = in_rec ? rkey[t] : skey[t - rn];
+        l_mask[t] = in_rec ? rmask[t] : smask[t - rn];
+      }
+      __syncthreads();
+      for (uint32_t t = threadIdx.x; t < tot; t += blockDim.x) {
+        const uint32_t kx = l_key[t];
+        const uint64_t mx = l_mask[t];
+        uint32_t r = 0;
+        for (uint32_t u = 0; u < tot; ++u) r += key_less(l_key[u], l_mask[u], kx, mx) ? 1u : 0u;
+        if (r < nn) { tkey[r] = kx; tmask[r] = mx; }
+      }
+    } else {
+      uint32_t P2 = 1;
+      while (P2 < ns) P2 <<= 1;
+      uint32_t* ks;
+      uint64_t* ms;
+      if (P2 <= lds_cap) {
+        for (uint32_t t = threadIdx.x; t < P2; t += blockDim.x) {
+          l_key[t] = t < ns ? skey[t] : 0xFFFFFFFFu;
+          l_mask[t] = t < ns ? smask[t] : ~0ull;
+        }
+        ks = l_key;
+        ms = l_mask;
+      } else {
+        for (uint32_t t = ns + threadIdx.x; t < P2 && t < cap; t += blockDim.x) {
+          skey[t] = 0xFFFFFFFFu;
+          smask[t] = ~0ull;
+        }
+        ks = skey;
+        ms = smask;
+      }
+      __syncthreads();
+      bitonic_sort(ks, ms, P2);
+      for (uint32_t a = threadIdx.x; a < rn; a += blockDim.x) {
+        const uint32_t r = a + rank_in(ks, ms, ns, rkey[a], rmask[a]);
+        if (r < nn) { tkey[r] = rkey[a]; tmask[r] = rmask[a]; }
+      }
+      for (uint32_t c = threadIdx.x; c < ns; c += blockDim.x) {
+        const uint32_t r = c + rank_in(rkey, rmask, rn, ks[c], ms[c]);
+        if (r < nn) { tkey[r] = ks[c]; tmask[r] = ms[c]; }
+      }
     }
     __syncthreads();
     for (uint32_t a = threadIdx.x; a < nn; a += blockDim.x) {
