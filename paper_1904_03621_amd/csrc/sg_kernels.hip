@@ -469,7 +469,7 @@ __global__ __launch_bounds__(kEnumBlock, 8) void k_enum(Batch bt, const void* __
   }
   __syncthreads();
   const int c = (int)((p >> kLaneBits) - h0);  // 0 or 1
-  const uint32_t pl = (uint32_t)p;             // bit j: spin n + j (j < kl)
+  const uint32_t plo = (uint32_t)p;            // bit j: spin n + j (j < kl)
   V WL[U];
   A ysum = 0;
 #pragma unroll
@@ -477,7 +477,7 @@ __global__ __launch_bounds__(kEnumBlock, 8) void k_enum(Batch bt, const void* __
     A acc = s_F[c][f];
     for (int j = 0; j < kl; ++j) {
       const A jq = (A)s_stage[f * N + n + j];
-      acc += ((pl >> j) & 1u) ? jq : -jq;
+      acc += ((plo >> j) & 1u) ? jq : -jq;
     }
     ysum += acc;
     WL[f] = valid ? (V)(2 * acc) : (V)0;
@@ -490,7 +490,7 @@ __global__ __launch_bounds__(kEnumBlock, 8) void k_enum(Batch bt, const void* __
       A acc = s_F[c][U + k];
       for (int j = 0; j < kl; ++j) {
         const A jq = (A)s_stage[(U + k) * N + n + j];
-        acc += ((pl >> j) & 1u) ? jq : -jq;
+        acc += ((plo >> j) & 1u) ? jq : -jq;
       }
       ysum += acc;
       yh[k] = valid ? (V)(2 * acc) : (V)0;
@@ -502,9 +502,9 @@ __global__ __launch_bounds__(kEnumBlock, 8) void k_enum(Batch bt, const void* __
     A f = (A)s_stage[N * N + q] + s_F[c][q];
     for (int r = j + 1; r < kl; ++r) {
       const A jr = (A)s_stage[q * N + n + r];
-      f += ((pl >> r) & 1u) ? jr : -jr;
+      f += ((plo >> r) & 1u) ? jr : -jr;
     }
-    EP -= ((pl >> j) & 1u) ? f : -f;
+    EP -= ((plo >> j) & 1u) ? f : -f;
   }
   __syncthreads();  // every lane has read the stage
 #pragma unroll
@@ -954,7 +954,9 @@ __device__ uint32_t radix_select(const uint32_t* keys, uint32_t cnt, uint32_t k,
 // margin of the S-th smallest walk energy are rescored: the walk energy is
 // within the margin of the exact one, so the S-th smallest exact energy of the
 // chunk is at most that S-th walk energy plus the margin, and no state at or
-// below it can have a walk energy beyond twice the margin.
+// below it can have a walk energy beyond twice the margin.  A chunk that
+// overflowed its candidate buffer (and will be walked again) merges only
+// the candidates of its S smallest walk energies.
 template <bool kInt>
 __global__ __launch_bounds__(kMergeBatchThreads) void k_merge_batched(Batch bt,
                                                                       uint64_t first_mask,
@@ -965,13 +967,17 @@ __global__ __launch_bounds__(kMergeBatchThreads) void k_merge_batched(Batch bt,
   __shared__ uint32_t s_hist[kMergeBatchThreads];
   __shared__ uint32_t s_sel[2];
   __shared__ uint32_t s_ns;
+  __shared__ uint32_t s_list;
   const int b = blockIdx.x;
   const int N = inst_N(bt, b);
   if (N < kU || N > bt.ld || (N < 63 && first_mask >= (1ull << N))) return;
   Params* P = bt.P + b;
   if (retry && !P->redo) return;
   stage_instance<kInt>(bt, b, N, s_inst);
-  if (threadIdx.x == 0) s_ns = 0;
+  if (threadIdx.x == 0) {
+    s_ns = 0;
+    s_list = 0;
+  }
   __syncthreads();
   const uint64_t* cand = bt.cand + (size_t)b * bt.cap;
   const uint32_t* ckey = bt.ckey + (size_t)b * bt.cap;
@@ -984,28 +990,61 @@ __global__ __launch_bounds__(kMergeBatchThreads) void k_merge_batched(Batch bt,
   uint32_t sel = 0xFFFFFFFFu;  // rescore candidates whose walk key is <= sel
   if (cnt > 2u * (uint32_t)bt.S + 256u) {
     const uint32_t kf = radix_select(ckey, cnt, (uint32_t)bt.S, s_hist, s_sel);
-    if (kInt || P->margin == 0.0f) {
-      sel = kf;  // walk energies are exact
+    // walk energies are exact, or the chunk overflowed and is walked again:
+    // its S best walk energies lower the threshold for that pass, and what
+    // they leave out is found then
+    const bool again = P->cand_count > bt.cap && !last_pass;
+    if (kInt || P->margin == 0.0f || again) {
+      sel = kf;
     } else {
       const float ef = __uint_as_float(bits_of_f32_key(kf));
       sel = key_f32(f32_up((double)ef + 2.0 * (double)P->margin));
     }
   }
-  for (uint32_t j = threadIdx.x; j < cnt; j += blockDim.x) {
-    if (ckey[j] > sel) continue;
-    const uint64_t m = cand[j];
-    const uint32_t key = exact_key<kInt>(s_inst, s_inst + N * N, N, N, m);
-    bool keep = !full || key_less(key, m, thr_key, thr_mask);
-    if (keep && retry)
-      keep = !in_record(bt.rkey + (size_t)b * bt.S, bt.rmask + (size_t)b * bt.S, P->rec_count,
-                        key, m);
-    if (keep) {
-      const uint32_t slot = atomicAdd(&s_ns, 1u);
-      skey[slot] = key;
-      smask[slot] = m;
+  // The preselected candidates are gathered in LDS (l_mask, free until the
+  // merge) before they are rescored, so that the lanes of a wave rescore
+  // one each: a rescoring costs O(N^2) and a wave pays it for any active
+  // lane.  Windows of 2 x 256 candidates are scanned; the gathered ones are
+  // rescored once there are 256 or at the end (at most 255 + 512 held).
+  constexpr uint32_t kWin = 2 * kMergeBatchThreads;
+  constexpr uint32_t kFlush = kMergeBatchThreads;
+  static_assert(kFlush - 1 + kWin <= (uint32_t)kLdsSortCapBatch, "gather list exceeds l_mask");
+  const uint32_t rn0 = P->rec_count;
+  for (uint32_t w0 = 0; w0 < cnt; w0 += kWin) {
+    const uint32_t w1 = min(cnt, w0 + kWin);
+    for (uint32_t j = w0 + threadIdx.x; j < w1; j += blockDim.x) {
+      const bool take = ckey[j] <= sel;
+      const uint64_t act = __ballot(take);
+      if (take) {  // one LDS atomic per wave
+        const int lid = __lane_id();
+        const int leader = __ffsll((unsigned long long)act) - 1;
+        uint32_t base = 0;
+        if (lid == leader) base = atomicAdd(&s_list, (uint32_t)__popcll(act));
+        base = __shfl(base, leader);
+        l_mask[base + (uint32_t)__popcll(act & ((1ull << lid) - 1ull))] = cand[j];
+      }
+    }
+    __syncthreads();
+    const uint32_t L = s_list;
+    const bool flush = L >= kFlush || w1 == cnt;
+    __syncthreads();  // every thread has read s_list
+    if (flush) {
+      if (threadIdx.x == 0) s_list = 0;
+      for (uint32_t q = threadIdx.x; q < L; q += blockDim.x) {
+        const uint64_t m = l_mask[q];
+        const uint32_t key = exact_key<kInt>(s_inst, s_inst + N * N, N, N, m);
+        bool keep = !full || key_less(key, m, thr_key, thr_mask);
+        if (keep && retry)
+          keep = !in_record(bt.rkey + (size_t)b * bt.S, bt.rmask + (size_t)b * bt.S, rn0, key, m);
+        if (keep) {
+          const uint32_t slot = atomicAdd(&s_ns, 1u);
+          skey[slot] = key;
+          smask[slot] = m;
+        }
+      }
+      __syncthreads();  // l_mask read before the next window writes it
     }
   }
-  __syncthreads();
   const uint32_t ns = s_ns;
   merge_body(P, bt.S, bt.cap, last_pass != 0, ns, skey, smask, bt.rkey + (size_t)b * bt.S,
              bt.rmask + (size_t)b * bt.S, bt.tkey + (size_t)b * bt.S,
