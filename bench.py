@@ -34,8 +34,8 @@ COPY_BYTES = 512 << 20
 # (KiB per dispatch, averaged over the 447 dispatches of one search), scaled by
 # what the same counters read for the 512 MiB copy (fetch x2.0, write x1.0);
 # valid for the k_enum source with this SHA-256 prefix only
-TRAFFIC = {"kenum_sha256_16": "e56228b95e74c635", "fetch_kib": 2168155.125 / 447,
-           "write_kib": 45099.5625 / 447, "fetch_factor": 524288.0 / 262162.0, "write_factor": 1.0,
+TRAFFIC = {"kenum_sha256_16": "1bf24ee096849524", "fetch_kib": 2166426.9375 / 447,
+           "write_kib": 45032.03125 / 447, "fetch_factor": 524288.0 / 262162.0, "write_factor": 1.0,
            "profile": "profiles/k_enum_f32_dense48_counters.md"}
 
 
@@ -133,12 +133,42 @@ def bench_batched(torch, sg, reps: int, baseline: bool = True) -> dict:
         raise sg.SgError(err, "device", sg._lib.last_error())
     identical = bool(torch.equal(bm, sm) and torch.equal(be, se))
     states = float(np.sum(2.0 ** Ns.astype(np.float64)))
+    # the same comparison on the instances of each N bin alone (a batch of
+    # that bin, row stride its largest N, against its per-instance calls)
+    bins = []
+    for lo_n, hi_n in ((16, 19), (20, 23), (24, 27), (28, 32)):
+        idx = np.nonzero((Ns >= lo_n) & (Ns <= hi_n))[0]
+        nb, nmax_b = len(idx), int(Ns[idx].max())
+        Nt_b = torch.from_numpy(np.ascontiguousarray(Ns[idx])).to(dev)
+        Jt_b = torch.from_numpy(np.ascontiguousarray(J[idx][:, :nmax_b, :nmax_b])).to(dev)
+        ht_b = torch.from_numpy(np.ascontiguousarray(h[idx][:, :nmax_b])).to(dev)
+        bm_b = torch.empty((nb, S), dtype=torch.int64, device=dev)
+        be_b = torch.empty((nb, S), dtype=torch.float32, device=dev)
+
+        def batched_bin():
+            st = sg.sg_low_spectrum_batched_f32(nb, Nt_b, nmax_b, Jt_b, ht_b, S, bm_b, be_b,
+                                                stream)
+            if st != 0:
+                raise sg.SgError(st, "sg_low_spectrum_batched_f32", sg._lib.last_error())
+
+        def per_instance_bin():
+            for r, b in enumerate(idx):
+                st = sg.sg_low_spectrum_f32(int(Ns[b]), Jb[b], hb[b], S, sm[r], se[r], stream)
+                if st != 0:
+                    raise sg.SgError(st, "sg_low_spectrum_f32", sg._lib.last_error())
+
+        batched_bin()
+        tb = min(_sync_time(torch, batched_bin) for _ in range(reps))
+        tp = _sync_time(torch, per_instance_bin)
+        same = bool(torch.equal(bm_b, sm[:nb]) and torch.equal(be_b, se[:nb]))
+        bins.append({"N": "%d-%d" % (lo_n, hi_n), "instances": nb, "batched_ms": tb * 1e3,
+                     "per_instance_ms": tp * 1e3, "speedup": tp / tb, "identical": same})
     print("batched done", file=sys.stderr, flush=True)
     return {"workload": "4096 dense fp32 instances, N_b uniform in [16,32], J ~ N(0,1), "
                         "h ~ N(0,0.1^2), seed 4, S=64 each",
             "value": states / t_b, "unit": "spin configs/s", "ms": t_b * 1e3,
             "per_instance_ms": t_p * 1e3, "speedup": t_p / t_b, "identical": identical,
-            "states": states}
+            "states": states, "bins": bins}
 
 
 def bench_logz(torch, sg, reps: int, baseline: bool = True) -> dict:

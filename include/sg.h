@@ -57,9 +57,10 @@ typedef enum {
     SG_ECAPACITY = 8      /* candidate buffer overflowed; result incomplete   */
 } sg_status;
 
-/* Largest number of spins accepted (Sec. 1 / abstract: N <= 50 in practice;
- * masks are 64-bit). */
-#define SG_MAX_N 56
+/* Largest number of spins accepted (Sec. 3: a state is the 64-bit code of its
+ * spins; one bit short of that keeps every mask a non-negative signed 64-bit
+ * integer, while range ends, unsigned, reach 2^63). */
+#define SG_MAX_N 63
 /* Largest S accepted by the single-instance search. */
 #define SG_MAX_S (1 << 20)
 /* Largest S accepted by the batched search. */

@@ -20,7 +20,7 @@ STATUS_NAMES = {
     0: "SG_OK", 1: "SG_EINVAL", 2: "SG_ENONFINITE", 3: "SG_EOVERFLOW", 4: "SG_ENOMEM",
     5: "SG_EHIP", 6: "SG_EUNSUPPORTED", 7: "SG_EDRIFT", 8: "SG_ECAPACITY",
 }
-SG_MAX_N = 56
+SG_MAX_N = 63
 SG_MAX_S = 1 << 20
 SG_MAX_S_BATCHED = 4096
 SG_MAX_DOS_BINS = 8192

@@ -2,7 +2,7 @@
 
 ``J`` and ``h`` are torch tensors on the GPU (float32 or int32); ``J`` is
 dense N x N of which the strict upper triangle is read.  Masks come back as
-int64 tensors (values < 2^56, bit i = spin i, set bit = spin up).
+int64 tensors (values < 2^63, bit i = spin i, set bit = spin up).
 """
 
 from __future__ import annotations

@@ -519,7 +519,7 @@ sg_status run_batched(bool isint, int B, const int32_t* Ns, int Nmax, const void
                       void* stream) {
   g_last_error.clear();
   if (B < 1) return fail(SG_EINVAL, "B must be >= 1");
-  if (Nmax < kU || Nmax > 40) return fail(SG_EINVAL, "N_max must be in [7, 40]");
+  if (Nmax < kU || Nmax > kMaxNBatched) return fail(SG_EINVAL, "N_max must be in [7, 40]");
   if (S < 1 || S > SG_MAX_S_BATCHED) return fail(SG_EINVAL, "S must be in [1, SG_MAX_S_BATCHED]");
   if (!Ns || !J || !h || !states_out || !energies_out)
     return fail(SG_EINVAL, "null pointer argument");
@@ -710,7 +710,7 @@ sg_status sg_reserve(int B_max, int N_max, int S_max, void* stream) {
   sg_status v = ws_get(st, 1, table_records(kMaxFree), cap, S_max, &w);
   if (v != SG_OK) return v;
   // batched search and log Z
-  if (N_max >= kU && N_max <= 40 && S_max <= SG_MAX_S_BATCHED) {
+  if (N_max >= kU && N_max <= kMaxNBatched && S_max <= SG_MAX_S_BATCHED) {
     // the per-instance slots grow as B shrinks: size for the largest B * cap
     uint64_t slots = 0;
     for (int b = 1; b <= B_max; ++b) slots = std::max(slots, (uint64_t)b * batch_cap(b, S_max));

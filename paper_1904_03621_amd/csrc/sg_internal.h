@@ -38,7 +38,8 @@ constexpr int kLdsSortCap = 4096;     // survivors sorted in LDS up to this
 constexpr int kLdsSortCapBatch = 1024;  // the same for the per-instance batched merge
 constexpr int kRankByCount = 512;     // merges of up to this many entries rank by counting
 constexpr int kQuboSortCap = 4096;    // states of a QUBO search (sorted in LDS)
-constexpr int kMaxN = 56;
+constexpr int kMaxN = 63;            // largest N (masks are 64-bit, signed in the bindings)
+constexpr int kMaxNBatched = 40;     // largest N_max of a batched search
 
 // Sticky device error bits (mapped to sg_status on the host).
 enum : uint32_t {

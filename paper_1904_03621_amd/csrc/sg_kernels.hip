@@ -426,9 +426,11 @@ __global__ __launch_bounds__(kEnumBlock, 8) void k_enum(Batch bt, const void* __
   // p >> kLaneBits, which is h0 or h0 + 1 in a workgroup).  The H parts --
   // the fields F of H on the free and L spins and the energy E_H of H alone --
   // are summed once per workgroup for both values of p >> kLaneBits; a lane
-  // adds only the kl L spins on top.  The couplings are staged in LDS first
-  // (in the space of the high fields, which are written only once the stage
-  // has been read).
+  // adds only the kl L spins on top.  Every coupling read here has its
+  // column among the prefix spins, so the stage holds columns n .. N-1 of J
+  // (row stride kp = N - n) and the prefix spins' fields: N kp + kp <= 63 x 56
+  // + 56 values, which fit in the space of the high fields (written only once
+  // the stage has been read).
   constexpr int kLaneBits = 8;  // log2(kEnumBlock)
   const int kl = min(N - n, kLaneBits);
   const int qh = n + kl;      // first H spin
@@ -437,16 +439,20 @@ __global__ __launch_bounds__(kEnumBlock, 8) void k_enum(Batch bt, const void* __
   __shared__ A s_F[2][kMaxFree + kLaneBits];
   __shared__ A s_R[2][kMaxN];
   __shared__ A s_EH[2];
-  V* s_stage = s_y;  // N*N couplings (row stride N), then the N fields
-  for (int k = tid; k < N * N + N; k += kEnumBlock)
-    s_stage[k] = k < N * N ? Jt[(k / N) * ld + (k % N)] : ht[k - N * N];
+  const int kp = N - n;
+  static_assert(kMaxN * (kMaxN - kU) + (kMaxN - kU) <= kMaxHigh * kEnumBlock,
+                "coupling stage exceeds s_y");
+  V* s_stage = s_y;  // s_stage[i kp + q - n] = J_iq (q >= n); then h_q at N kp + q - n
+  const V* s_hp = s_stage + N * kp;
+  for (int k = tid; k < N * kp + kp; k += kEnumBlock)
+    s_stage[k] = k < N * kp ? Jt[(k / kp) * ld + n + (k % kp)] : ht[n + k - N * kp];
   __syncthreads();
   for (int t = tid; t < 2 * nf; t += kEnumBlock) {
     const int c = t >= nf, i = t - c * nf;
     const uint64_t hb = h0 + (uint64_t)c;
     A acc = 0;
     for (int q = qh; q < N; ++q) {
-      const A jq = (A)s_stage[i * N + q];
+      const A jq = (A)s_stage[i * kp + q - n];
       acc += ((hb >> (q - qh)) & 1ull) ? jq : -jq;
     }
     s_F[c][i] = acc;
@@ -454,9 +460,9 @@ __global__ __launch_bounds__(kEnumBlock, 8) void k_enum(Batch bt, const void* __
   for (int t = tid; t < 2 * (N - qh); t += kEnumBlock) {
     const int c = t >= N - qh, q = qh + t - c * (N - qh);
     const uint64_t hb = h0 + (uint64_t)c;
-    A f = (A)s_stage[N * N + q];
+    A f = (A)s_hp[q - n];
     for (int r = q + 1; r < N; ++r) {
-      const A jr = (A)s_stage[q * N + r];
+      const A jr = (A)s_stage[q * kp + r - n];
       f += ((hb >> (r - qh)) & 1ull) ? jr : -jr;
     }
     s_R[c][q - qh] = ((hb >> (q - qh)) & 1ull) ? f : -f;
@@ -476,7 +482,7 @@ __global__ __launch_bounds__(kEnumBlock, 8) void k_enum(Batch bt, const void* __
   for (int f = 0; f < U; ++f) {
     A acc = s_F[c][f];
     for (int j = 0; j < kl; ++j) {
-      const A jq = (A)s_stage[f * N + n + j];
+      const A jq = (A)s_stage[f * kp + j];
       acc += ((plo >> j) & 1u) ? jq : -jq;
     }
     ysum += acc;
@@ -489,7 +495,7 @@ __global__ __launch_bounds__(kEnumBlock, 8) void k_enum(Batch bt, const void* __
     if (k < n - U) {
       A acc = s_F[c][U + k];
       for (int j = 0; j < kl; ++j) {
-        const A jq = (A)s_stage[(U + k) * N + n + j];
+        const A jq = (A)s_stage[(U + k) * kp + j];
         acc += ((plo >> j) & 1u) ? jq : -jq;
       }
       ysum += acc;
@@ -499,9 +505,9 @@ __global__ __launch_bounds__(kEnumBlock, 8) void k_enum(Batch bt, const void* __
   A EP = s_EH[c];
   for (int j = 0; j < kl; ++j) {
     const int q = n + j;
-    A f = (A)s_stage[N * N + q] + s_F[c][q];
+    A f = (A)s_hp[j] + s_F[c][q];
     for (int r = j + 1; r < kl; ++r) {
-      const A jr = (A)s_stage[q * N + n + r];
+      const A jr = (A)s_stage[q * kp + r];
       f += ((plo >> r) & 1u) ? jr : -jr;
     }
     EP -= ((plo >> j) & 1u) ? f : -f;
@@ -963,7 +969,7 @@ __global__ __launch_bounds__(kMergeBatchThreads) void k_merge_batched(Batch bt,
                                                                       int retry, int last_pass) {
   __shared__ uint32_t l_key[kLdsSortCapBatch];
   __shared__ uint64_t l_mask[kLdsSortCapBatch];
-  __shared__ uint32_t s_inst[kMaxN * kMaxN + kMaxN];
+  __shared__ uint32_t s_inst[kMaxNBatched * kMaxNBatched + kMaxNBatched];
   __shared__ uint32_t s_hist[kMergeBatchThreads];
   __shared__ uint32_t s_sel[2];
   __shared__ uint32_t s_ns;

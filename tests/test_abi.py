@@ -44,7 +44,7 @@ def test_binding_names_match(L):
 
 
 @pytest.mark.parametrize("case", [
-    dict(N=0), dict(N=57), dict(S=0), dict(S=(1 << 20) + 1), dict(N=4, S=17),
+    dict(N=0), dict(N=64), dict(S=0), dict(S=(1 << 20) + 1), dict(N=4, S=17),
     dict(lo=10), dict(lo=64, hi=64), dict(hi=(1 << 20) + 64, N=20), dict(lo=0, hi=100, N=20),
     dict(lo=128, hi=192, S=65, N=20), dict(null=True),
 ])
@@ -53,7 +53,7 @@ def test_validation_is_synchronous(L, case):
     N = case.get("N", 20)
     S = case.get("S", 10)
     lo = case.get("lo", 0)
-    hi = case.get("hi", 1 << max(min(N, 56), 0) if 0 < N <= 56 else 64)
+    hi = case.get("hi", 1 << N if 0 < N <= 63 else 64)
     p = 0 if case.get("null") else 4096  # never dereferenced: validation fails first
     if "lo" in case or "hi" in case:
         st = lib.sg_low_spectrum_range_f32(N, p, p, S, lo, hi, p, p, 0)
@@ -83,7 +83,7 @@ def test_batched_and_logz_validation_is_synchronous(L, case):
         assert st == L.SG_EINVAL and L.last_error() != ""
 
 
-@pytest.mark.parametrize("case", [dict(N=0), dict(N=57), dict(n_bins=0), dict(n_bins=8193),
+@pytest.mark.parametrize("case", [dict(N=0), dict(N=64), dict(n_bins=0), dict(n_bins=8193),
                                   dict(null=True)])
 def test_dos_validation_is_synchronous(L, case):
     lib = L.lib()
@@ -95,7 +95,7 @@ def test_dos_validation_is_synchronous(L, case):
         assert lib.sg_energy_bound_i32(N, p, p, p, 0) == L.SG_EINVAL
 
 
-@pytest.mark.parametrize("args", [(0, 20, 8), (4, 0, 8), (4, 57, 8), (4, 20, 0),
+@pytest.mark.parametrize("args", [(0, 20, 8), (4, 0, 8), (4, 64, 8), (4, 20, 0),
                                   (4, 20, (1 << 20) + 1)])
 def test_reserve_validation(L, args):
     assert L.lib().sg_reserve(*args, 0) == L.SG_EINVAL
@@ -132,6 +132,8 @@ def _check_plan(L, N, S, lo, hi, fill):
     (6, 1, 0, 64, 1 << 19),
     (10, 1024, 0, 1024, 64),
     (40, 1 << 20, 0, 1 << 40, 1 << 19),
+    (63, 100, (1 << 63) - (1 << 44), 1 << 63, 1 << 19),   # the largest N, top of the space
+    (63, 64, (1 << 62) + 64 * 777, (1 << 62) + (1 << 33), 1 << 19),
 ])
 def test_plan_tiles_range(L, N, S, lo, hi, fill):
     plan, first = _check_plan(L, N, S, lo, hi, fill)

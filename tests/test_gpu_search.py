@@ -193,15 +193,18 @@ def test_maximum_S_single(orc, torch_dev):
     compare(orc, torch_dev, J, h, 1 << 20, what="N=24 S=2^20")
 
 
-def test_maximum_N_range(orc, torch_dev):
-    """N = SG_MAX_N = 56 through the range API: a 2^20-mask slice high in the
-    space (masks above 2^55) against the oracle on the same slice."""
-    N = 56
-    J, h = I.random_int_dense(N, 56)
-    lo = (1 << 55) + (3 << 40)
-    compare(orc, torch_dev, J, h, 64, lo, lo + (1 << 20), what="N=56 slice")
-    Jf, hf = I.random_f32_dense(N, 57)
-    compare(orc, torch_dev, Jf, hf, 64, lo, lo + (1 << 20), what="N=56 f32 slice")
+@pytest.mark.parametrize("N,lo,hi", [
+    (56, (1 << 55) + (3 << 40), (1 << 55) + (3 << 40) + (1 << 20)),
+    (63, (1 << 63) - (1 << 20), 1 << 63),                  # SG_MAX_N, last masks
+    (63, (1 << 62) + (5 << 44) + 64 * 12345, (1 << 62) + (5 << 44) + 64 * 12345 + 3000000),
+])
+def test_maximum_N_range(orc, torch_dev, N, lo, hi):
+    """Large N through the range API, up to N = SG_MAX_N = 63 and the range end
+    2^63: slices high in the space against the oracle on the same slice."""
+    J, h = I.random_int_dense(N, N)
+    compare(orc, torch_dev, J, h, 64, lo, hi, what="N=%d slice" % N)
+    Jf, hf = I.random_f32_dense(N, N + 1)
+    compare(orc, torch_dev, Jf, hf, 64, lo, hi, what="N=%d f32 slice" % N)
 
 
 def test_every_state_at_block_boundaries(orc, torch_dev):
