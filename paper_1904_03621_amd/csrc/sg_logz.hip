@@ -45,6 +45,7 @@ namespace sg {
 
 constexpr int kLzHigh = kLzFree - kLzU;
 constexpr int kNCoef = 22;   // 1 + 6 + 15 order <= 2 Walsh coefficients over U = 6
+constexpr int kCoefStride = 24;  // a row's coefficient sums in LDS (16-byte rows)
 // per beta: bq by configuration x, then by Gray step i for block parity 0 and 1
 constexpr int kLzQ = 3 * kLzSteps;
 
@@ -186,6 +187,16 @@ struct BlockWalk {
   }
 };
 
+// sum over the 16 lanes of a row (DPP row shifts; the row's last lane gets
+// the total, the others partial sums)
+__device__ inline float row_total(float v) {
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xF, 0xF, true));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x112, 0xF, 0xF, true));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x114, 0xF, 0xF, true));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x118, 0xF, 0xF, true));
+  return v;
+}
+
 // wave sum of a double (every lane gets the total)
 __device__ inline double wave_sum(double v) {
 #pragma unroll
@@ -240,15 +251,24 @@ __device__ inline double exp2_wide(double x) {
   return ldexp((double)__builtin_amdgcn_exp2f(f), ni);
 }
 
+// Workgroups per CU to fit: the backward for up to three beta keeps 3 waves
+// per SIMD (168 VGPRs, 3 values spilled), 28% faster than 2 waves without a
+// spill; with four beta it keeps 2 rather than spill more.  The forward fits 4
+// or more waves either way (5 measured no faster than 4).
 template <int kMode, int NB>
-__global__ __launch_bounds__(256) void k_logz(LzArgs a, const float* __restrict__ J,
+constexpr int lz_min_blocks() {
+  return kMode == 1 && NB == 4 ? 2 : 3;
+}
+
+template <int kMode, int NB>
+__global__ __launch_bounds__(256, (lz_min_blocks<kMode, NB>())) void k_logz(LzArgs a, const float* __restrict__ J,
                                               const float* __restrict__ h,
                                               const double* __restrict__ table64,
                                               const float* __restrict__ lzq,
                                               const double* __restrict__ lzqmin, int bpi) {
   constexpr int U = kLzU;
   __shared__ double s_y[kLzHigh * 256];
-  __shared__ float s_c[kMode ? 4 * kNCoef * 64 : 1];
+  __shared__ __align__(16) float s_c[kMode ? 4 * 4 * kCoefStride : 1];
   __shared__ float s_t[kMode ? 4 * kNCoef : 1];
   __shared__ float s_bq[NB * kLzQ];  // this instance's bq tables (uniform reads)
 
@@ -415,24 +435,31 @@ __global__ __launch_bounds__(256) void k_logz(LzArgs a, const float* __restrict_
 #pragma unroll
       for (int k = 0; k < kLzHigh; ++k)
         if (k < H) M[k] += ((xh >> k) & 1u) ? (double)C.o : -(double)C.o;
-      // wave sums of the 22 coefficients (transpose through LDS)
-      float* cw = s_c + wv * kNCoef * 64;
-      cw[0 * 64 + ln] = C.o;
+      // wave sums of the 22 coefficients: each is first summed over the 16
+      // lanes of its row by DPP shifts (the row's last lane ends with the
+      // total), the 4 row totals go through LDS (one 24-float row each), and
+      // lane c < 22 adds the four totals of coefficient c
+      float cv[kCoefStride];
+      cv[0] = row_total(C.o);
 #pragma unroll
-      for (int f = 0; f < U; ++f) cw[(1 + f) * 64 + ln] = C.s[f];
+      for (int f = 0; f < U; ++f) cv[1 + f] = row_total(C.s[f]);
 #pragma unroll
-      for (int k = 0; k < 15; ++k) cw[(1 + U + k) * 64 + ln] = C.p[k];
+      for (int k = 0; k < 15; ++k) cv[1 + U + k] = row_total(C.p[k]);
+      cv[kNCoef] = 0.0f;
+      cv[kNCoef + 1] = 0.0f;
+      if ((ln & 15) == 15) {
+        float* cw = s_c + (wv * 4 + (ln >> 4)) * kCoefStride;
+#pragma unroll
+        for (int j = 0; j < kCoefStride; j += 4)
+          *(float4*)(cw + j) = make_float4(cv[j], cv[j + 1], cv[j + 2], cv[j + 3]);
+      }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       if (ln < kNCoef) {
-        float t0 = 0.0f, t1 = 0.0f, t2 = 0.0f, t3 = 0.0f;
-        const float* row = cw + ln * 64;
-#pragma unroll
-        for (int j = 0; j < 64; j += 4) {
-          t0 += row[j]; t1 += row[j + 1]; t2 += row[j + 2]; t3 += row[j + 3];
-        }
-        s_t[wv * kNCoef + ln] = (t0 + t1) + (t2 + t3);
+        const float* col = s_c + wv * 4 * kCoefStride + ln;
+        s_t[wv * kNCoef + ln] = (col[0] + col[kCoefStride]) +
+                                (col[2 * kCoefStride] + col[3 * kCoefStride]);
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
