@@ -34,8 +34,8 @@ COPY_BYTES = 512 << 20
 # (KiB per dispatch, averaged over the 447 dispatches of one search), scaled by
 # what the same counters read for the 512 MiB copy (fetch x2.0, write x1.0);
 # valid for the k_enum source with this SHA-256 prefix only
-TRAFFIC = {"kenum_sha256_16": "1bf24ee096849524", "fetch_kib": 2166426.9375 / 447,
-           "write_kib": 45032.03125 / 447, "fetch_factor": 524288.0 / 262162.0, "write_factor": 1.0,
+TRAFFIC = {"kenum_sha256_16": "615e9128bbcfe8e0", "fetch_kib": 2169628.625 / 447,
+           "write_kib": 41254.28125 / 447, "fetch_factor": 524288.0 / 262162.0, "write_factor": 1.0,
            "profile": "profiles/k_enum_f32_dense48_counters.md"}
 
 
@@ -276,6 +276,65 @@ def bench_dos(torch, sg, reps: int) -> dict:
             "check": "ok" if ok else "FAILED"}
 
 
+def bench_plain(torch, sg) -> dict:
+    """The two other single-instance workloads: N=24 integer dense, S=100 (3
+    runs, bit-exact against the oracle) and the 48-spin Chimera-like instance
+    (2 x 3 unit cells, couplers uniform in {-1, +1}, h = 0, seed 3), S=10000,
+    int32 (one run; every state rescored by the oracle, complete energy levels
+    even under the global flip)."""
+    import instances as I
+    from oracle import oracle
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    out = {}
+    for name, runs in (("int24", 3), ("chimera48", 1)):
+        w = I.workload(name)
+        N, S = w["N"], w["S"]
+        Jt, ht = (torch.from_numpy(x).to(dev) for x in (w["J"], w["h"]))
+        m_t = torch.empty(S, dtype=torch.int64, device=dev)
+        e_t = torch.empty(S, dtype=torch.int32, device=dev)
+
+        def run():
+            st = sg.sg_low_spectrum_i32(N, Jt, ht, S, m_t, e_t, stream)
+            if st != 0:
+                raise sg.SgError(st, "sg_low_spectrum_i32", sg._lib.last_error())
+
+        best, frac = None, None
+        for _ in range(runs):
+            t = _sync_time(torch, run)
+            info = sg.sg_get_run_info(stream)
+            if best is None or t < best:
+                best = t
+                launches = max(info["enum_launches"], 1)
+                avg = info["enum_ms"] / launches
+                if avg > 0:
+                    frac = (OPS_PER_STATE * info["enum_states"] / launches) / (avg * 1e-3) \
+                        / PEAK_LANE_OPS
+        err = sg.sg_get_error(stream)
+        if err != 0:
+            raise sg.SgError(err, "device", sg._lib.last_error())
+        m = m_t.cpu().numpy().astype(np.uint64)
+        e = e_t.cpu().numpy().astype(np.int64)
+        if name == "int24":
+            om, oe = oracle.low_spectrum(w["J"], w["h"], S)
+            ok = bool(np.array_equal(m, om) and np.array_equal(e, oe))
+        else:
+            eo = np.array([oracle.energy(w["J"], w["h"], int(x)) for x in m])
+            _, cnt = np.unique(e[e < e[-1]], return_counts=True)
+            ok = bool(np.array_equal(eo, e) and np.all(np.diff(e) >= 0)
+                      and len(set(m.tolist())) == S and np.all(cnt % 2 == 0))
+        out[name] = {"value": float(1 << N) / best, "unit": "spin configs/s", "ms": best * 1e3,
+                     "N": N, "S": S, "dtype": "i32", "roofline_frac": frac,
+                     "ground_energy": int(e[0]), "check": "ok" if ok else "FAILED"}
+    out["int24"]["workload"] = ("one fully connected instance, N=24, J_ij, h_i uniform "
+                                "integers in [-7, 7], seed 1; S=100, bit-exact vs the oracle")
+    out["chimera48"]["workload"] = ("Chimera-like 2x3 unit cells (48 spins, 124 couplers "
+                                    "uniform in {-1, +1}), h = 0, seed 3; all 2^48 states, "
+                                    "S=10000")
+    print("plain configs done", file=sys.stderr, flush=True)
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -412,6 +471,7 @@ def main() -> int:
                      if k in ("chunks", "candidates", "slow_blocks", "margin", "max_drift")},
     }
     if not args.no_extensions:
+        out.update(bench_plain(torch, sg))
         out["batched"] = bench_batched(torch, sg, 3)
         out["logz"] = bench_logz(torch, sg, 3)
         out["dos"] = bench_dos(torch, sg, 2)

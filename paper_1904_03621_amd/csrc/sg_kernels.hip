@@ -101,27 +101,6 @@ __device__ inline bool key_less(uint32_t ka, uint64_t ma, uint32_t kb, uint64_t 
   return ka < kb || (ka == kb && ma < mb);
 }
 
-// Wave-aggregated append of one mask (and the orderable key of the energy
-// the walk computed for it) per active lane.
-__device__ inline void append_mask(uint64_t mask, uint32_t key, Params* P, uint64_t* cand,
-                                   uint32_t* ckey, uint32_t cap) {
-  const uint64_t act = __ballot(1);
-  const int lid = __lane_id();
-  const int leader = __ffsll((unsigned long long)act) - 1;
-  const uint32_t cnt = (uint32_t)__popcll(act);
-  uint32_t base = 0;
-  if (lid == leader) base = atomicAdd(&P->cand_count, cnt);
-  base = __shfl(base, leader);
-  const uint64_t below = act & ((1ull << lid) - 1ull);
-  const uint32_t slot = base + (uint32_t)__popcll(below);
-  // beyond cap the mask is dropped; the merge sees cand_count > cap and asks
-  // for another pass over the chunk
-  if (slot < cap) {
-    cand[slot] = mask;
-    ckey[slot] = key;
-  }
-}
-
 // ------------------------------------------------------------------ k_prep
 // One workgroup per instance.  Writes the Q tables (low-spin coupling energy
 // for both block parities), their minimum, the pruning margin, the error
@@ -647,10 +626,30 @@ __global__ __launch_bounds__(kEnumBlock, 8) void k_enum(Batch bt, const void* __
         else g2 = ((i >> (f + 1)) & 1) ? g2 + W[f] : g2 - W[f];
         if (g2 + qv(i) <= thrE) hits[i >> 6] |= (1ull << (i & 63));
       }
+      // one slot reservation for all hits of the wave: an exclusive scan of
+      // the lanes' hit counts, one atomic, then every lane writes its own
+      // hits from its offset (the atomic's latency is paid once per block,
+      // not once per step that hits)
+#pragma unroll
+      for (int w = 0; w < kHitWords; ++w)
+        if (!(valid && pass)) hits[w] = 0ull;
+      uint32_t nh = 0;
+#pragma unroll
+      for (int w = 0; w < kHitWords; ++w) nh += (uint32_t)__popcll(hits[w]);
+      uint32_t incl = nh;
+#pragma unroll
+      for (int o = 1; o < kWaveLanes; o <<= 1) {
+        const uint32_t y = __shfl_up(incl, o);
+        if (__lane_id() >= o) incl += y;
+      }
+      const uint32_t total = __shfl(incl, kWaveLanes - 1);
+      uint32_t base = 0;
+      if (__lane_id() == 0 && total != 0) base = atomicAdd(&P->cand_count, total);
+      uint32_t slot = __shfl(base, 0) + incl - nh;
       const uint64_t pl = ch.prefix_base + (uint64_t)lane;
 #pragma unroll
       for (int w = 0; w < kHitWords; ++w) {
-        uint64_t hw = (valid && pass) ? hits[w] : 0ull;
+        uint64_t hw = hits[w];
         while (hw) {
           const int i = 64 * w + __builtin_ctzll(hw);
           hw &= hw - 1ull;
@@ -667,7 +666,13 @@ __global__ __launch_bounds__(kEnumBlock, 8) void k_enum(Batch bt, const void* __
           if ((gi >> (U - 1)) & 1u) e = e + W[U - 1];
           e = e + qv(i);
           const uint32_t key = kInt ? key_of_i32((int32_t)e) : key_f32((float)e);
-          append_mask(mask, key, P, cand, ckey, cand_cap);
+          // beyond cap the mask is dropped; the merge sees cand_count > cap
+          // and asks for another pass over the chunk
+          if (slot < cand_cap) {
+            cand[slot] = mask;
+            ckey[slot] = key;
+          }
+          ++slot;
         }
       }
     }
