@@ -34,8 +34,8 @@ COPY_BYTES = 512 << 20
 # (KiB per dispatch, averaged over the 447 dispatches of one search), scaled by
 # what the same counters read for the 512 MiB copy (fetch x2.0, write x1.0);
 # valid for the k_enum source with this SHA-256 prefix only
-TRAFFIC = {"kenum_sha256_16": "615e9128bbcfe8e0", "fetch_kib": 2169628.625 / 447,
-           "write_kib": 41254.28125 / 447, "fetch_factor": 524288.0 / 262162.0, "write_factor": 1.0,
+TRAFFIC = {"kenum_sha256_16": "e36ff8d4c6965cf8", "fetch_kib": 2174110.9375 / 447,
+           "write_kib": 41254.125 / 447, "fetch_factor": 524288.0 / 262162.0, "write_factor": 1.0,
            "profile": "profiles/k_enum_f32_dense48_counters.md"}
 
 
@@ -323,9 +323,11 @@ def bench_plain(torch, sg) -> dict:
             _, cnt = np.unique(e[e < e[-1]], return_counts=True)
             ok = bool(np.array_equal(eo, e) and np.all(np.diff(e) >= 0)
                       and len(set(m.tolist())) == S and np.all(cnt % 2 == 0))
+        info = sg.sg_get_run_info(stream)
         out[name] = {"value": float(1 << N) / best, "unit": "spin configs/s", "ms": best * 1e3,
                      "N": N, "S": S, "dtype": "i32", "roofline_frac": frac,
-                     "ground_energy": int(e[0]), "check": "ok" if ok else "FAILED"}
+                     "ground_energy": int(e[0]), "check": "ok" if ok else "FAILED",
+                     "slow_blocks": info["slow_blocks"], "candidates": info["candidates"]}
     out["int24"]["workload"] = ("one fully connected instance, N=24, J_ij, h_i uniform "
                                 "integers in [-7, 7], seed 1; S=100, bit-exact vs the oracle")
     out["chimera48"]["workload"] = ("Chimera-like 2x3 unit cells (48 spins, 124 couplers "
@@ -345,7 +347,7 @@ def main() -> int:
                     help="skip the batched and log Z measurements")
     ap.add_argument("--valu-probe", action="store_true",
                     help="print the measured issue rate of each probed VALU instruction")
-    ap.add_argument("--leg", choices=["batched", "logz", "dos"],
+    ap.add_argument("--leg", choices=["batched", "logz", "dos", "plain"],
                     help="run only this extension's batched calls (warm-up + 1 timed; for "
                          "profiling) and print their times")
     ap.add_argument("--traffic-probe", action="store_true",
@@ -370,6 +372,10 @@ def main() -> int:
     if args.leg:
         if args.leg == "dos":
             print(json.dumps({"dos": bench_dos(torch, sg, 1)}), flush=True)
+            return 0
+        if args.leg == "plain":
+            sg.sg_set_kernel_timing(True)
+            print(json.dumps(bench_plain(torch, sg)), flush=True)
             return 0
         fn = bench_batched if args.leg == "batched" else bench_logz
         print(json.dumps({args.leg: fn(torch, sg, 1, baseline=False)}), flush=True)

@@ -311,6 +311,7 @@ Batch make_batch(Workspace* w, const void* J, const void* h, const int32_t* Ns, 
   bt.tkey = w->tkey;
   bt.tmask = w->tmask;
   bt.sticky = w->sticky;
+  bt.allow_f32_walk = 1;
   return bt;
 }
 
@@ -744,7 +745,8 @@ sg_status sg_density_of_states_i32(int N, const int32_t* J, const int32_t* h, lo
   Workspace* w = nullptr;
   sg_status v = ws_get(st, 1, recs, 1, 1, &w);
   if (v != SG_OK) return v;
-  const Batch bt = make_batch(w, J, h, nullptr, N, N, 1, 1, (int64_t)recs, 1);
+  Batch bt = make_batch(w, J, h, nullptr, N, N, 1, 1, (int64_t)recs, 1);
+  bt.allow_f32_walk = 0;  // the histogram walk reads integer tables
   HIP_TRY(launch_prep(true, bt, st));
   HIP_TRY(launch_dos_prologue(bt, e_min, n_bins, counts_out, st));
   w->ev_used = 0;
@@ -911,7 +913,7 @@ sg_status sg_get_run_info(void* stream, sg_run_info* out) {
 void sg_set_kernel_timing(int enable) { g_timing = enable != 0; }
 
 double sg_probe_valu(int op, int waves_per_simd) {
-  if (op < 0 || op > 16 || waves_per_simd < 1 || waves_per_simd > 8) return -1.0;
+  if (op < 0 || op > 17 || waves_per_simd < 1 || waves_per_simd > 8) return -1.0;
   return probe_valu(op, waves_per_simd);
 }
 

@@ -74,6 +74,7 @@ struct Params {
   // than the buffer holds: the chunk is walked again with the tightened
   // threshold (at most kRetries times)
   uint32_t redo;
+  uint32_t walk_f32;         // integer instance walked in fp32 (exact: |values| < 2^24)
   uint32_t stat_redo;       // repeated passes taken
   double bound;             // sum_{i<j} |J_ij| + sum_i |h_i| (no |E| exceeds it)
 };
@@ -107,6 +108,7 @@ struct Batch {
   uint32_t* tkey;      // [B][S] merge scratch
   uint64_t* tmask;     // [B][S]
   uint32_t* sticky;    // error bits accumulated over searches
+  int allow_f32_walk;  // integer instances may take the fp32 walk (searches: 1)
 };
 
 // Exact log Z walk (forward: partition sums; backward: gradient moments).

@@ -167,6 +167,11 @@ __global__ void k_prep(Batch bt) {
   const int anybad = s_bad[0];
   const int lsb_min = s_lsb[0];
 
+  // An integer instance whose energies stay below 2^24 (2.1 Bv < 2^24: every
+  // value on the walk is an integer of at most 24 bits) is walked in fp32,
+  // where the walk is exact and, on this GPU, faster than in int32; its tables
+  // then hold fp32 values.
+  const bool walk_f32 = kInt && bt.allow_f32_walk && 2.1 * Bv < 16777216.0;
   // Q tables: Q(x) = -sum_{f<f'<U} J_ff' s_f s_f' over the low configuration
   // x = gray(i) ^ (par << (U-1)) of step i in a block of parity par.
   const int U = kU;
@@ -181,7 +186,7 @@ __global__ void k_prep(Batch bt) {
         q -= (double)Jb[a * ld + c] * sa * sc;
       }
     s_q[tid] = q;
-    if (kInt) qtab[tid] = (uint32_t)(int32_t)q;
+    if (kInt && !walk_f32) qtab[tid] = (uint32_t)(int32_t)q;
     else qtab[tid] = __float_as_uint((float)q);
   }
   __syncthreads();
@@ -233,6 +238,7 @@ __global__ void k_prep(Batch bt) {
     P->cand_count = 0;
     P->surv_count = 0;
     P->redo = 0;
+    P->walk_f32 = walk_f32 ? 1u : 0u;
     P->stat_redo = 0;
     P->bound = Bv;
     P->stat_candidates = 0;
@@ -317,7 +323,7 @@ __global__ void k_tables(Batch bt, int ncap, void* out) {
     return;
   }
   uint32_t* rec = bt.table + ((size_t)b * bt.table_recs + (size_t)r) * kRecWords;
-  if (kInt) {
+  if (kInt && !bt.P[b].walk_f32) {
     rec[0] = (uint32_t)(int32_t)cB;
     rec[1] = (uint32_t)(int32_t)R;
     for (int f = 0; f < U; ++f) rec[2 + f] = (uint32_t)(int32_t)wu[f];
@@ -352,15 +358,21 @@ struct Num<int32_t> {
   static __device__ inline int32_t big() { return 1 << 29; }
 };
 
+template <bool kInt, bool kWF>
+__device__ __forceinline__ void enum_walk(const Batch& bt, const void* __restrict__ Jv,
+                                          const void* __restrict__ hv,
+                                          const uint32_t* __restrict__ table,
+                                          const uint32_t* __restrict__ qtab_all, const Chunk& ch,
+                                          int b, int blk, int N, int n, int64_t lanes, Params* P,
+                                          uint32_t* s_yw, void* s_Fw, void* s_Rw, void* s_EHw);
+
 template <bool kInt>
 __global__ __launch_bounds__(kEnumBlock, 8) void k_enum(Batch bt, const void* __restrict__ Jv,
                                                         const void* __restrict__ hv,
                                                         const uint32_t* __restrict__ table,
                                                         const uint32_t* __restrict__ qtab_all,
                                                         Chunk ch, int blocks_per_inst) {
-  using V = typename std::conditional<kInt, int32_t, float>::type;
   using A = typename std::conditional<kInt, int64_t, double>::type;  // exact init
-  constexpr int U = kU;
 
   const int b = blockIdx.x / blocks_per_inst;
   const int blk = blockIdx.x - b * blocks_per_inst;
@@ -375,9 +387,36 @@ __global__ __launch_bounds__(kEnumBlock, 8) void k_enum(Batch bt, const void* __
   if (err0 & (kErrNonFinite | kErrOverflow | kErrInval)) return;
   if (ch.retry && !P->redo) return;
 
-  // The lane's high-spin fields Y_g (index [g - U][thread]) are read once per
-  // block boundary, so they live in LDS rather than in registers.
-  __shared__ V s_y[kMaxHigh * kEnumBlock];
+  // LDS shared by both walk variants: the lane's high-spin fields Y_g (index
+  // [g - U][thread], read once per block boundary), which first hold the
+  // staged couplings, and the workgroup's sums over its upper prefix spins.
+  __shared__ uint32_t s_y[kMaxHigh * kEnumBlock];
+  __shared__ A s_F[2][kMaxFree + 8];
+  __shared__ A s_R[2][kMaxN];
+  __shared__ A s_EH[2];
+  if (kInt && P->walk_f32)
+    enum_walk<true, true>(bt, Jv, hv, table, qtab_all, ch, b, blk, N, n, lanes, P, s_y, s_F, s_R,
+                          s_EH);
+  else
+    enum_walk<kInt, !kInt>(bt, Jv, hv, table, qtab_all, ch, b, blk, N, n, lanes, P, s_y, s_F,
+                           s_R, s_EH);
+}
+
+// The walk of k_enum.  kInt: the instance is int32 (exact set-up in int64,
+// integer keys); kWF: the walk runs in fp32 (fp32 instances, and integer ones
+// whose values fit 24 bits, whose tables then hold fp32 values).
+template <bool kInt, bool kWF>
+__device__ __forceinline__ void enum_walk(const Batch& bt, const void* __restrict__ Jv,
+                                          const void* __restrict__ hv,
+                                          const uint32_t* __restrict__ table,
+                                          const uint32_t* __restrict__ qtab_all, const Chunk& ch,
+                                          int b, int blk, int N, int n, int64_t lanes, Params* P,
+                                          uint32_t* s_yw, void* s_Fw, void* s_Rw, void* s_EHw) {
+  using V = typename std::conditional<kWF, float, int32_t>::type;
+  using A = typename std::conditional<kInt, int64_t, double>::type;  // exact init
+  using Ts = typename std::conditional<kInt, int32_t, float>::type;  // stored values
+  constexpr int U = kU;
+  V* s_y = (V*)s_yw;
   const uint32_t* qtab = qtab_all + (size_t)b * 2 * kBlockSteps;  // uniform: SGPRs
 
   const int tid = threadIdx.x;
@@ -393,8 +432,8 @@ __global__ __launch_bounds__(kEnumBlock, 8) void k_enum(Batch bt, const void* __
   uint32_t* ckey = bt.ckey + (size_t)b * bt.cap;
   const uint32_t cand_cap = bt.cap;
 
-  const V* Jt = (const V*)Jv + (size_t)b * ld * ld;
-  const V* ht = (const V*)hv + (size_t)b * ld;
+  const Ts* Jt = (const Ts*)Jv + (size_t)b * ld * ld;
+  const Ts* ht = (const Ts*)hv + (size_t)b * ld;
 
   // ---- per-lane init (exact in int64 / fp64) --------------------------------
   // y_f = sum_{q >= n} J_fq s_q (field on free spin f from the prefix);
@@ -415,16 +454,16 @@ __global__ __launch_bounds__(kEnumBlock, 8) void k_enum(Batch bt, const void* __
   const int qh = n + kl;      // first H spin
   const int nf = n + kl;      // spins that take a field from H
   const uint64_t h0 = p0 >> kLaneBits;
-  __shared__ A s_F[2][kMaxFree + kLaneBits];
-  __shared__ A s_R[2][kMaxN];
-  __shared__ A s_EH[2];
+  A(*s_F)[kMaxFree + kLaneBits] = (A(*)[kMaxFree + kLaneBits])s_Fw;
+  A(*s_R)[kMaxN] = (A(*)[kMaxN])s_Rw;
+  A* s_EH = (A*)s_EHw;
   const int kp = N - n;
   static_assert(kMaxN * (kMaxN - kU) + (kMaxN - kU) <= kMaxHigh * kEnumBlock,
                 "coupling stage exceeds s_y");
   V* s_stage = s_y;  // s_stage[i kp + q - n] = J_iq (q >= n); then h_q at N kp + q - n
   const V* s_hp = s_stage + N * kp;
   for (int k = tid; k < N * kp + kp; k += kEnumBlock)
-    s_stage[k] = k < N * kp ? Jt[(k / kp) * ld + n + (k % kp)] : ht[n + k - N * kp];
+    s_stage[k] = k < N * kp ? (V)Jt[(k / kp) * ld + n + (k % kp)] : (V)ht[n + k - N * kp];
   __syncthreads();
   for (int t = tid; t < 2 * nf; t += kEnumBlock) {
     const int c = t >= nf, i = t - c * nf;
@@ -498,7 +537,7 @@ __global__ __launch_bounds__(kEnumBlock, 8) void k_enum(Batch bt, const void* __
   V G;
   {
     const uint32_t r0 = tab[1];
-    const A R0 = kInt ? (A)(int32_t)r0 : (A)__uint_as_float(r0);
+    const A R0 = kWF ? (A)__uint_as_float(r0) : (A)(int32_t)r0;
     G = valid ? (V)(EP + ysum + R0) : Num<V>::big();
   }
   // fp32 re-anchor constants: E_P minus the low spins' prefix fields at a
@@ -554,7 +593,7 @@ __global__ __launch_bounds__(kEnumBlock, 8) void k_enum(Batch bt, const void* __
     V rw[2 + U];
 #pragma unroll
     for (int k = 0; k < 2 + U; ++k)
-      rw[k] = kInt ? (V)(int32_t)rec[k] : (V)__uint_as_float(rec[k]);
+      rw[k] = kWF ? (V)__uint_as_float(rec[k]) : (V)(int32_t)rec[k];
     const V ycur = ynext;
     if (T + 1 < nblocks) ynext = s_y[__builtin_ctz(T + 1) * kEnumBlock + tid];
 
@@ -617,7 +656,7 @@ __global__ __launch_bounds__(kEnumBlock, 8) void k_enum(Batch bt, const void* __
       uint64_t hits[kHitWords];
 #pragma unroll
       for (int w = 0; w < kHitWords; ++w) hits[w] = 0ull;
-      auto qv = [&](int i) -> V { return kInt ? (V)(int32_t)q[i] : (V)__uint_as_float(q[i]); };
+      auto qv = [&](int i) -> V { return kWF ? (V)__uint_as_float(q[i]) : (V)(int32_t)q[i]; };
       if (g2 + qv(0) <= thrE) hits[0] |= 1ull;
 #pragma unroll
       for (int i = 1; i < kBlockSteps; ++i) {

@@ -30,7 +30,8 @@ constexpr int kProbeThreads = 256;
   X(13, "v_med3_f32 %0, %0, %1, %2")                    \
   X(14, "v_pk_add_u16 %0, %0, %1")                      \
   X(15, "v_pk_min_i16 %0, %0, %1")                      \
-  X(16, "v_exp_f32 %0, %1")
+  X(16, "v_exp_f32 %0, %1")                             \
+  X(17, "v_sub_u32 %0, %1, %0")
 
 template <int kOp>
 __global__ __launch_bounds__(kProbeThreads) void k_probe(uint32_t seed, uint32_t* out) {

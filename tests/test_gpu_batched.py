@@ -69,6 +69,23 @@ def test_small_batch_vs_oracle_and_single(orc, torch_dev, isint):
         assert np.array_equal(sm, bm[b, :S_b]) and np.array_equal(se, be[b, :S_b])
 
 
+def test_int_batch_mixes_both_walks(orc, torch_dev):
+    """A batch of integer instances where every other one is scaled beyond the
+    fp32-walk limit: both walks in the same launches, bit-exact per instance."""
+    B, S = 24, 40
+    Ns, J, h = make_batch(B, 8, 18, 11, True)
+    J = J.astype(np.int64)
+    h = h.astype(np.int64)
+    J[1::2] *= 1 << 17
+    h[1::2] *= 1 << 17
+    J, h = J.astype(np.int32), h.astype(np.int32)
+    bm, be = run_batched(torch_dev, Ns, J, h, S)
+    for b in range(B):
+        n = int(Ns[b])
+        om, oe = orc.low_spectrum(J[b, :n, :n], h[b, :n], S)
+        check_int(bm[b], be[b], om, oe, "batch %d (N=%d)" % (b, n))
+
+
 def test_workload_shape_matches_single(orc, torch_dev):
     """N uniform in [16, 26] (the 4096-instance workload's distribution, cut at
     26 to keep the per-instance loop short), fp32, unscaled couplings, S = 64."""

@@ -207,6 +207,28 @@ def test_maximum_N_range(orc, torch_dev, N, lo, hi):
     compare(orc, torch_dev, Jf, hf, 64, lo, hi, what="N=%d f32 slice" % N)
 
 
+@pytest.mark.parametrize("N,S", [(8, 256), (12, 4096), (20, 500), (24, 300)])
+def test_int32_walk_large_couplings(orc, torch_dev, N, S):
+    """Integer couplings too large for the exact fp32 walk (2.1 sum|J| >= 2^24,
+    below the 2^28 overflow bound): the int32 walk, bit-exact."""
+    J, h = I.random_int_dense(N, 500 + N, lo=-(1 << 20), hi=1 << 20)
+    bound = int(np.abs(np.triu(J.astype(np.int64), 1)).sum() + np.abs(h.astype(np.int64)).sum())
+    assert 2.1 * bound >= (1 << 24) and bound < (1 << 28), bound
+    compare(orc, torch_dev, J, h, S, what="int32 walk N=%d" % N)
+
+
+def test_int_walk_boundary(orc, torch_dev):
+    """Integer instances just below and just above the fp32-walk limit
+    (2.1 sum|J| < 2^24 takes the fp32 walk): both bit-exact."""
+    N = 16
+    J0, h0 = I.random_int_dense(N, 77)
+    b0 = int(np.abs(np.triu(J0.astype(np.int64), 1)).sum() + np.abs(h0.astype(np.int64)).sum())
+    for target in ((1 << 24) / 2.1 - 64, (1 << 24) / 2.1 + 64):
+        k = int(target // b0)
+        J, h = (J0.astype(np.int64) * k).astype(np.int32), (h0.astype(np.int64) * k).astype(np.int32)
+        compare(orc, torch_dev, J, h, 1000, what="int walk limit x%d" % k)
+
+
 def test_every_state_at_block_boundaries(orc, torch_dev):
     """N = 7 and 8 (one and two 128-state blocks): every state, both paths."""
     for N in (7, 8):
