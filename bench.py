@@ -34,19 +34,20 @@ COPY_BYTES = 512 << 20
 # (KiB per dispatch, averaged over the 447 dispatches of one search), scaled by
 # what the same counters read for the 512 MiB copy (fetch x2.0, write x1.0);
 # valid for the k_enum source with this SHA-256 prefix only
-TRAFFIC = {"kenum_sha256_16": "e36ff8d4c6965cf8", "fetch_kib": 2174110.9375 / 447,
-           "write_kib": 41254.125 / 447, "fetch_factor": 524288.0 / 262162.0, "write_factor": 1.0,
+TRAFFIC = {"kenum_sha256_16": "fd0194a45ece98c7", "fetch_kib": 2174179.4375 / 447,
+           "write_kib": 41268.8125 / 447, "fetch_factor": 524288.0 / 262162.0, "write_factor": 1.0,
            "profile": "profiles/k_enum_f32_dense48_counters.md"}
 
 
 def kenum_source_hash() -> str:
-    """SHA-256 prefix of the k_enum function's source with comments and
-    whitespace removed (layout and comment edits do not change the kernel)."""
+    """SHA-256 prefix of the enumeration kernel's source (the k_enum kernel and
+    its walk, from the k_enum section marker to the next kernel) with comments
+    and whitespace removed (layout and comment edits do not change it)."""
     import hashlib
     import re
     src = open(os.path.join(ROOT, "paper_1904_03621_amd", "csrc", "sg_kernels.hip")).read()
-    i = src.index("void k_enum(Batch bt")
-    j = src.index("\n}\n", i)
+    i = src.index("// ------------------------------------------------------------------ k_enum")
+    j = src.index("// Tiny instances (N < U)", i)
     body = re.sub(r"//[^\n]*", "", src[i:j])
     body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
     body = re.sub(r"\s+", "", body)

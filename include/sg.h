@@ -262,7 +262,7 @@ sg_status sg_reserve(int B_max, int N_max, int S_max, void *stream);
 /*
  * Tuner of the batched search: times sg_low_spectrum_batched_f32 on this
  * batch for the level geometries around the default (free spins per lane n =
- * log2(level size) - shift; by default shift = max(12, ceil(log2(2 L / B))),
+ * log2(level size) - shift; by default shift = max(12, ceil(log2(4 L / B))),
  * L the device's resident lanes; the tuner tries that shift -3 .. +3) and keeps the
  * fastest for later batched calls on this device with the same B, N_max and
  * S; *shift_out is the choice.  Results do not depend on the geometry (the

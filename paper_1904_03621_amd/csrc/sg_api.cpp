@@ -416,8 +416,9 @@ sg_status run_search(bool isint, int N, const void* J, const void* h, int S, uin
 // 2^12 lanes per instance, the fastest geometry measured on 4096 instances of
 // 16..32 spins (fewer free spins per lane spend more of each lane on its
 // set-up; more leave too few lanes once the smaller instances have finished),
-// and more when B is too small for B 2^shift to reach twice the device's
-// resident lanes.  The tuner (sg_tune_batched_f32) may pick another shift per
+// and more when B is too small for B 2^shift to reach four times the
+// device's resident lanes (256 instances of 28 spins: 2^13 lanes each, 5%
+// faster than 2^12).  The tuner (sg_tune_batched_f32) may pick another shift per
 // (device, B, N_max, S).
 constexpr int kShiftFloor = 12;
 constexpr int kShiftSpan = 3;  // the tuner tries default - 3 .. default + 3
@@ -425,7 +426,7 @@ std::map<std::tuple<int, int, int, int>, int> g_shift;  // (device, B, N_max, S)
 
 int default_shift(int B, int64_t fill) {
   int shift = 0;
-  while (shift < 40 && ((int64_t)B << shift) < 2 * fill) ++shift;
+  while (shift < 40 && ((int64_t)B << shift) < 4 * fill) ++shift;
   return std::max(shift, kShiftFloor);
 }
 

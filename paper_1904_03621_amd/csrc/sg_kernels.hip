@@ -679,7 +679,7 @@ __device__ __forceinline__ void enum_walk(const Batch& bt, const void* __restric
 #pragma unroll
       for (int o = 1; o < kWaveLanes; o <<= 1) {
         const uint32_t y = __shfl_up(incl, o);
-        if (__lane_id() >= o) incl += y;
+        if ((int)__lane_id() >= o) incl += y;
       }
       const uint32_t total = __shfl(incl, kWaveLanes - 1);
       uint32_t base = 0;
