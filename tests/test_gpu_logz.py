@@ -124,6 +124,49 @@ def test_free_spins_closed_form(torch_dev):
         check_grad(gJ[b], gh[b], np.triu(np.outer(t, t), 1), t, "free b=%d" % b)
 
 
+def test_free_spins_closed_form_n36(torch_dev):
+    """J = 0 at N = 36 (2^36 states, beyond the oracle): log Z, <s_i> and
+    <s_i s_j> in closed form."""
+    N = 36
+    rng = np.random.default_rng(31)
+    J = np.zeros((1, N, N), dtype=np.float32)
+    h = (rng.standard_normal((1, N)) * 0.5).astype(np.float32)
+    lz, _, _, _ = gpu_forward(torch_dev, J, h, BETAS, 8)
+    g = np.array([[0.0, 1.0, 0.0]])
+    gJ, gh = gpu_backward(torch_dev, J, h, BETAS, g)
+    hd = h[0].astype(np.float64)
+    check_logz(lz[0], np.array([np.sum(np.log(2.0 * np.cosh(bt * hd))) for bt in BETAS]),
+               "free N=36")
+    t = np.tanh(hd)
+    check_grad(gJ[0], gh[0], np.triu(np.outer(t, t), 1), t, "free N=36")
+
+
+def test_open_chain_n40_closed_form(torch_dev):
+    """Open chain of 40 spins, h = 0: Z = 2 prod_i 2 cosh(beta K_i) and
+    <s_i s_j> = prod_{i <= l < j} tanh(beta K_l) (2^40 states)."""
+    N = 40
+    rng = np.random.default_rng(41)
+    K = (rng.standard_normal(N - 1) * 0.8).astype(np.float32)
+    J = np.zeros((1, N, N), dtype=np.float32)
+    for i in range(N - 1):
+        J[0, i, i + 1] = K[i]
+    h = np.zeros((1, N), dtype=np.float32)
+    lz, _, _, _ = gpu_forward(torch_dev, J, h, BETAS, 4)
+    Kd = K.astype(np.float64)
+    want = [np.log(2.0) + np.sum(np.log(2.0 * np.cosh(bt * Kd))) for bt in BETAS]
+    check_logz(lz[0], np.array(want), "chain N=40")
+    g = np.array([[0.0, 1.0, 0.0]])  # beta = 1
+    gJ, gh = gpu_backward(torch_dev, J, h, BETAS, g)
+    t = np.tanh(Kd)
+    ref = np.zeros((N, N))
+    for i in range(N):
+        prod = 1.0
+        for j in range(i + 1, N):
+            prod *= t[j - 1]
+            ref[i, j] = prod
+    check_grad(gJ[0], gh[0], ref, np.zeros(N), "chain N=40")
+
+
 def test_open_chain_transfer_matrix(torch_dev):
     """Open chain (J_{i,i+1} only): log Z from 2 x 2 transfer matrices."""
     N = 20
