@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -190,7 +191,7 @@ struct Workspace {
   int ev_used = 0;
 };
 
-bool g_timing = false;
+std::atomic<bool> g_timing{false};  // process-wide switch, read by every thread's calls
 
 hipError_t ws_event_pair(Workspace* w, hipEvent_t* a, hipEvent_t* b) {
   while ((int)w->ev.size() < 2 * (w->ev_used + 1)) {
