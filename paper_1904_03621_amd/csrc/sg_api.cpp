@@ -442,12 +442,16 @@ int batch_shift(int B, int Nmax, int S, int64_t fill) {
 }
 
 // Chunk levels of a batched search.  Level 0 is [0, first) with
-// first = max(S, 128) rounded up to a power of two (every state of it is a
-// candidate, so it is kept small); level j >= 1 is [first 2^(j-1), first 2^j),
+// first = max(S, 4096) rounded up to a power of two: every state of it is a
+// candidate (at most half the 8192 or more slots an instance has), and one
+// such level replaces the five smallest doubling levels, whose launches and
+// merges cost far more than their states; level j >= 1 is
+// [first 2^(j-1), first 2^j),
 // so every level is as large as everything before it and brings about S
 // candidates.  All instances with states in a level run it in the same launch,
 // with the same geometry: n = clamp(log2(size) - shift, U, 17) free spins per
 // lane.
+constexpr uint64_t kBatchLevel0 = 4096;  // smallest level 0 (<= half of any instance's slots)
 struct Level {
   uint64_t first;
   int n;
@@ -456,7 +460,7 @@ struct Level {
 
 std::vector<Level> batch_levels(int Nmax, int S, int shift) {
   std::vector<Level> out;
-  uint64_t size0 = kBlockSteps;
+  uint64_t size0 = kBatchLevel0;
   while (size0 < (uint64_t)S) size0 <<= 1;
   const uint64_t full = (uint64_t)1 << Nmax;
   uint64_t first = 0, size = size0;
