@@ -30,7 +30,7 @@ hipError_t launch_finalize(bool isint, const Batch& bt, uint64_t* states_out, vo
                            hipStream_t st);
 int enum_occupancy(bool isint);
 double probe_valu(int op, int waves_per_simd);
-hipError_t launch_tables64(const Batch& bt, int ncap, double* out, hipStream_t st);
+hipError_t launch_tables64(const Batch& bt, int ncap, int U, double* out, hipStream_t st);
 hipError_t launch_lz_prep(int mode, const LzArgs& a, const float* J, float* lzq, double* lzqmin,
                           const float* energies, float* e0_out, const double* logz,
                           const double* grad, hipStream_t st);
@@ -318,7 +318,7 @@ Batch make_batch(Workspace* w, const void* J, const void* h, const int32_t* Ns, 
 
 // Records of the concatenated per-block tables for n = U .. ncap.
 size_t table_records(int ncap) { return ((size_t)1 << (ncap - kU + 1)) - 1; }
-size_t lz_table_records(int ncap) { return ((size_t)1 << (ncap - kLzU + 1)) - 1; }
+size_t lz_table_records(int ncap, int U) { return ((size_t)1 << (ncap - U + 1)) - 1; }
 
 // ------------------------------------------------------------------ search
 
@@ -554,8 +554,10 @@ sg_status lz_validate(int B, int N, const void* J, const void* h, int nb, const 
 sg_status lz_buffers(Workspace* w, int B, int N) {
   const size_t Bz = (size_t)B;
   const size_t stride = std::max<size_t>(kMaxBeta, (size_t)N * N + N);
-  HIP_TRY(grow(&w->table64, &w->ntable64, Bz * lz_table_records(std::min(kLzFree, N)) * 8));
-  HIP_TRY(grow(&w->lzq, &w->nlzq, Bz * kMaxBeta * 3 * kLzSteps));
+  // records of U = kLzU outnumber (and outsize) those of U = kLzUF
+  HIP_TRY(grow(&w->table64, &w->ntable64,
+               Bz * lz_table_records(std::min(kLzFree, N), kLzU) * (2 + kLzUF)));
+  HIP_TRY(grow(&w->lzq, &w->nlzq, Bz * kMaxBeta * kLzQStride));
   HIP_TRY(grow(&w->lzqmin, &w->nlzqmin, Bz));
   HIP_TRY(grow(&w->lz_acc, &w->nlz_acc, Bz * stride));
   HIP_TRY(grow(&w->lz_coef, &w->nlz_coef, Bz * kMaxBeta));
@@ -567,15 +569,18 @@ LzArgs lz_args(Workspace* w, int B, int N, int nb, int S, const float* h, const 
   LzArgs a{};
   a.B = B;
   a.N = N;
+  // low spins per block: the partition sums take the larger blocks whenever
+  // the instance has that many spins
+  a.U = (mode == 0 && N >= kLzUF) ? kLzUF : kLzU;
   // free spins per lane: at most kLzFree, fewer when the batch alone would
   // not give every resident lane of the device a prefix
   a.n = std::min(kLzFree, N);
-  while (a.n > kLzU && (int64_t)B * ((int64_t)1 << (N - a.n)) < w->fill[0]) --a.n;
+  while (a.n > a.U && (int64_t)B * ((int64_t)1 << (N - a.n)) < w->fill[0]) --a.n;
   a.nb = nb;
   a.S = S;
   a.lanes = (int64_t)1 << (N - a.n);
-  a.table_recs = (int64_t)lz_table_records(a.n);
-  a.table_offset = (1 << (a.n - kLzU)) - 1;
+  a.table_recs = (int64_t)lz_table_records(a.n, a.U);
+  a.table_offset = (1 << (a.n - a.U)) - 1;
   a.h_in = h;
   a.beta = beta;
   a.e0 = e0;
@@ -673,7 +678,7 @@ sg_status sg_logz_forward_f32(int B, int N, const float* J, const float* h, int 
   const LzArgs a = lz_args(w, B, N, n_beta, S, h, beta, e0_out, 0);
   Batch b64 = bt;
   b64.table_recs = a.table_recs;
-  HIP_TRY(launch_tables64(b64, a.n, w->table64, st));
+  HIP_TRY(launch_tables64(b64, a.n, a.U, w->table64, st));
   HIP_TRY(launch_lz_prep(0, a, J, w->lzq, w->lzqmin, energies_out, e0_out, nullptr, nullptr, st));
   HIP_TRY(launch_logz(0, a, J, h, w->table64, w->lzq, w->lzqmin, st));
   HIP_TRY(launch_lz_final(0, a, logz_out, nullptr, nullptr, st));
@@ -697,7 +702,7 @@ sg_status sg_logz_backward_f32(int B, int N, const float* J, const float* h, int
   if (v != SG_OK) return v;
   const LzArgs a = lz_args(w, B, N, n_beta, 1, h, beta, e0, 1);
   Batch b64 = make_batch(w, J, h, nullptr, N, N, B, 1, a.table_recs, 1);
-  HIP_TRY(launch_tables64(b64, a.n, w->table64, st));
+  HIP_TRY(launch_tables64(b64, a.n, a.U, w->table64, st));
   HIP_TRY(launch_lz_prep(1, a, J, w->lzq, w->lzqmin, nullptr, nullptr, logz, grad_logz, st));
   HIP_TRY(launch_logz(1, a, J, h, w->table64, w->lzq, w->lzqmin, st));
   HIP_TRY(launch_lz_final(1, a, nullptr, grad_J, grad_h, st));

@@ -25,10 +25,13 @@ constexpr int kMaxHigh = kMaxFree - kU;
 constexpr int kRecWords = 16;         // per-block table record (64 B: cB, R, Wu_0..U-1)
 constexpr int kReanchorLog2 = 10;     // fp32: fresh G every 2^10 flips
 constexpr int kReanchorBlocks = 1 << (kReanchorLog2 - kU);
-// The log Z walk uses blocks of its own: 6 low spins (64 configurations),
-// fp64 records of 8 doubles (cB, R, Wu_0..5).
+// The log Z walk uses blocks of its own, U low spins with fp64 records of
+// 2 + U doubles (cB, R, Wu_0..U-1): U = 6 (64 configurations) for the
+// gradient walk, U = 8 (256) for the partition sums when N >= 8.
 constexpr int kLzU = 6;
+constexpr int kLzUF = 8;
 constexpr int kLzSteps = 1 << kLzU;
+constexpr int kLzQStride = 256;  // floats per (instance, beta) of the bq tables
 constexpr int kWaveLanes = 64;
 constexpr int kEnumBlock = 256;       // threads per enumeration workgroup
 constexpr int kMergeThreads = 1024;   // threads of the single-workgroup merge
@@ -117,6 +120,7 @@ constexpr int kLzFree = 14;  // free spins per lane: n = min(N, 14)
 
 struct LzArgs {
   int B, N, n, nb, S;
+  int U;                // low spins per block (kLzU or kLzUF)
   int64_t lanes;        // lanes per instance: 2^(N - n)
   int64_t table_recs;   // fp64 records per instance
   int table_offset;     // first record of the table of n

@@ -262,11 +262,11 @@ __global__ void k_prep(Batch bt) {
 //                 step 2^(U-1) flips it).
 // Tables for n = U .. nmax are concatenated; the table of n starts at record
 // 2^(n-U) - 1.  grid.y indexes the instance.  The search uses U = kU (words
-// of kRecWords); the log Z walk (kF64) U = kLzU and records of 8 doubles.
+// of kRecWords); the log Z walk (kF64) U = kUF and records of 2 + U doubles.
 
-template <bool kInt, bool kF64>
+template <bool kInt, bool kF64, int kUF = kLzU>
 __global__ void k_tables(Batch bt, int ncap, void* out) {
-  constexpr int U = kF64 ? kLzU : kU;
+  constexpr int U = kF64 ? kUF : kU;
   const int b = blockIdx.y;
   const int N = inst_N(bt, b);
   if (N < U || N > bt.ld) return;
@@ -315,8 +315,8 @@ __global__ void k_tables(Batch bt, int ncap, void* out) {
   }
   wu[U - 1] *= (T & 1u) ? 1.0 : -1.0;
 
-  if (kF64) {  // records of 8 doubles (the log Z walk keeps its energies in fp64)
-    double* rec = (double*)out + ((size_t)b * bt.table_recs + (size_t)r) * 8;
+  if (kF64) {  // records of 2 + U doubles (the log Z walk keeps its energies in fp64)
+    double* rec = (double*)out + ((size_t)b * bt.table_recs + (size_t)r) * (2 + U);
     rec[0] = cB;
     rec[1] = R;
     for (int f = 0; f < U; ++f) rec[2 + f] = wu[f];
@@ -1135,11 +1135,15 @@ hipError_t launch_tables(bool isint, const Batch& bt, int ncap, hipStream_t st) 
   return hipGetLastError();
 }
 
-// fp64 records (8 doubles each) of an fp32 batch, for the log Z walk.
-hipError_t launch_tables64(const Batch& bt, int ncap, double* out, hipStream_t st) {
-  const int64_t total = ((int64_t)1 << (ncap - kLzU + 1)) - 1;
+// fp64 records (2 + U doubles each) of an fp32 batch, for the log Z walk.
+hipError_t launch_tables64(const Batch& bt, int ncap, int U, double* out, hipStream_t st) {
+  if (U != kLzU && U != kLzUF) return hipErrorInvalidValue;
+  const int64_t total = ((int64_t)1 << (ncap - U + 1)) - 1;
   const dim3 grid((unsigned)((total + 255) / 256), (unsigned)bt.B);
-  hipLaunchKernelGGL((k_tables<false, true>), grid, dim3(256), 0, st, bt, ncap, (void*)out);
+  if (U == kLzU)
+    hipLaunchKernelGGL((k_tables<false, true, kLzU>), grid, dim3(256), 0, st, bt, ncap, (void*)out);
+  else
+    hipLaunchKernelGGL((k_tables<false, true, kLzUF>), grid, dim3(256), 0, st, bt, ncap, (void*)out);
   return hipGetLastError();
 }
 

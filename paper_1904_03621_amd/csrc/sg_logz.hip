@@ -16,8 +16,9 @@
 // that lowers phi_f s_f and exp(-2 beta |phi_f|) for the other, and
 // bq(x) = exp(-beta (Q(x) - min Q)) a per-instance table.  Every factor except
 // P_T lies in (0, 1], so nothing overflows; P_T is formed in fp64 range.
-// K_T and phi_f are recomputed per block in fp64 from the lane's prefix fields
-// and the block record (no running sum, no drift).
+// K_T and phi_f are formed per block in fp64 from the lane's prefix fields,
+// the block record and the field energy of the high spins (one fp64 update
+// per block, at most 2^H - 1 terms).
 //
 // Forward (kMode 0): the 64 weights of a block are an 8 x 8 contraction of
 // the factor products of spins 0-2 and 3-5 with bq; block sums are fp32, lane
@@ -46,51 +47,54 @@ namespace sg {
 constexpr int kLzHigh = kLzFree - kLzU;
 constexpr int kNCoef = 22;   // 1 + 6 + 15 order <= 2 Walsh coefficients over U = 6
 constexpr int kCoefStride = 24;  // a row's coefficient sums in LDS (16-byte rows)
-// per beta: bq by configuration x, then by Gray step i for block parity 0 and 1
-constexpr int kLzQ = 3 * kLzSteps;
 
 // ------------------------------------------------------------------ prep
 // One workgroup per instance: the low-low energies Q(x), their minimum, the
 // bq tables of every beta, the accumulators cleared, E0 (forward) or the
 // combined gradient weights g_b beta_b / Z~_b (backward).
 
-template <int kMode>
+// U low spins per block; the forward reads bq by configuration only (2^U
+// entries per beta), the backward also by Gray step for both block parities.
+template <int kMode, int U>
 __global__ void k_lz_prep(LzArgs a, const float* __restrict__ J, float* lzq, double* lzqmin,
                           const float* energies, float* e0_out, const double* logz,
                           const double* grad) {
-  __shared__ double s_q[kLzSteps];
+  constexpr int kSteps = 1 << U;
+  constexpr int kQ = kMode == 0 ? kSteps : 3 * kSteps;
+  static_assert(kQ <= kLzQStride, "bq tables exceed their stride");
+  __shared__ double s_q[kSteps];
   __shared__ double s_qmin;
   const int b = blockIdx.x;
   const int N = a.N;
   const float* Jb = J + (size_t)b * N * N;
   const int tid = threadIdx.x;
-  if (tid < kLzSteps) {
+  for (int x = tid; x < kSteps; x += blockDim.x) {
     double q = 0.0;
-    for (int f = 0; f < kLzU; ++f)
-      for (int g = f + 1; g < kLzU; ++g) {
-        const double sf = ((tid >> f) & 1) ? 1.0 : -1.0, sg = ((tid >> g) & 1) ? 1.0 : -1.0;
+    for (int f = 0; f < U; ++f)
+      for (int g = f + 1; g < U; ++g) {
+        const double sf = ((x >> f) & 1) ? 1.0 : -1.0, sg = ((x >> g) & 1) ? 1.0 : -1.0;
         q -= (double)Jb[f * N + g] * sf * sg;
       }
-    s_q[tid] = q;
+    s_q[x] = q;
   }
   __syncthreads();
   if (tid == 0) {
     double m = s_q[0];
-    for (int x = 1; x < kLzSteps; ++x) m = fmin(m, s_q[x]);
+    for (int x = 1; x < kSteps; ++x) m = fmin(m, s_q[x]);
     s_qmin = m;
     lzqmin[b] = m;
   }
   __syncthreads();
   const double qmin = s_qmin;
-  for (int e = tid; e < a.nb * kLzQ; e += blockDim.x) {
-    const int k = e / kLzQ, r = e - k * kLzQ;
+  for (int e = tid; e < a.nb * kQ; e += blockDim.x) {
+    const int k = e / kQ, r = e - k * kQ;
     int x = r;
-    if (r >= kLzSteps) {
-      const int i = r & (kLzSteps - 1);
-      x = (i ^ (i >> 1)) ^ ((r >= 2 * kLzSteps) ? (1 << (kLzU - 1)) : 0);
+    if (r >= kSteps) {
+      const int i = r & (kSteps - 1);
+      x = (i ^ (i >> 1)) ^ ((r >= 2 * kSteps) ? (1 << (U - 1)) : 0);
     }
     const double bk = (double)a.beta[k];
-    lzq[((size_t)b * kMaxBeta + k) * kLzQ + r] = (float)exp(-bk * (s_q[x] - qmin));
+    lzq[((size_t)b * kMaxBeta + k) * kLzQStride + r] = (float)exp(-bk * (s_q[x] - qmin));
   }
   double* acc = a.acc + (size_t)b * a.acc_stride;
   for (int k = tid; k < a.acc_stride; k += blockDim.x) acc[k] = 0.0;
@@ -236,11 +240,20 @@ __device__ inline void lz_slot(int s, int H, int N, int* coef, uint32_t* mask, i
 
 // ------------------------------------------------------------------ walk
 
-// Factor products of three spins: out[x] = prod_{j<3} (bit j of x ? cp[j] : cm[j]).
-__device__ inline void triple_products(const float* cp, const float* cm, float* out) {
-  const float t00 = cm[0] * cm[1], t10 = cp[0] * cm[1], t01 = cm[0] * cp[1], t11 = cp[0] * cp[1];
-  out[0] = t00 * cm[2]; out[1] = t10 * cm[2]; out[2] = t01 * cm[2]; out[3] = t11 * cm[2];
-  out[4] = t00 * cp[2]; out[5] = t10 * cp[2]; out[6] = t01 * cp[2]; out[7] = t11 * cp[2];
+// Factor products of M spins: out[x] = prod_{j<M} (bit j of x ? cp[j] : cm[j]),
+// x < 2^M, built one spin at a time (2^(j+1) products for spin j).
+template <int M>
+__device__ inline void factor_products(const float* cp, const float* cm, float* out) {
+  out[0] = cm[0];
+  out[1] = cp[0];
+#pragma unroll
+  for (int j = 1; j < M; ++j) {
+#pragma unroll
+    for (int x = 0; x < (1 << j); ++x) {
+      out[x + (1 << j)] = out[x] * cp[j];
+      out[x] = out[x] * cm[j];
+    }
+  }
 }
 
 // 2^x for any finite x in fp64 range: 2^n (n integer) times 2^f, f in [0, 1).
@@ -260,29 +273,40 @@ constexpr int lz_min_blocks() {
   return kMode == 1 && NB == 4 ? 2 : 3;
 }
 
-template <int kMode, int NB>
+// U low spins per block: kLzU for the gradient walk, kLzU or kLzUF for the
+// partition sums (a block's 2^U weights are then a 2^(U/2) x 2^(U/2)
+// contraction).
+template <int kMode, int NB, int U>
 __global__ __launch_bounds__(256, (lz_min_blocks<kMode, NB>())) void k_logz(LzArgs a, const float* __restrict__ J,
                                               const float* __restrict__ h,
                                               const double* __restrict__ table64,
                                               const float* __restrict__ lzq,
                                               const double* __restrict__ lzqmin, int bpi) {
-  constexpr int U = kLzU;
-  __shared__ double s_y[kLzHigh * 256];
+  static_assert(kMode == 0 || U == kLzU, "the gradient walk takes blocks of kLzU spins");
+  static_assert(U % 2 == 0 && U <= kLzFree, "blocks split into two equal halves");
+  constexpr int kSteps = 1 << U;
+  constexpr int kQ = kMode == 0 ? kSteps : 3 * kSteps;  // bq floats per beta
+  constexpr int kHigh = kLzFree - U;
+  constexpr int kM = 1 << (U / 2);
+  __shared__ double s_y[kHigh * 256];
   __shared__ __align__(16) float s_c[kMode ? 4 * 4 * kCoefStride : 1];
   __shared__ float s_t[kMode ? 4 * kNCoef : 1];
-  __shared__ float s_bq[NB * kLzQ];  // this instance's bq tables (uniform reads)
+  __shared__ float s_bq[NB * kQ];  // this instance's bq tables (uniform reads)
 
   const int b = blockIdx.x / bpi;
   const int blk = blockIdx.x - b * bpi;
   const int tid = threadIdx.x;
   const int N = a.N, n = a.n, H = n - U;
-  for (int e = tid; e < NB * kLzQ; e += 256) s_bq[e] = lzq[(size_t)b * kMaxBeta * kLzQ + e];
+  for (int e = tid; e < NB * kQ; e += 256) {
+    const int k = e / kQ;
+    s_bq[e] = lzq[((size_t)b * kMaxBeta + k) * kLzQStride + (e - k * kQ)];
+  }
   const int64_t lane = (int64_t)blk * 256 + tid;
   const bool valid = lane < a.lanes;
   const uint64_t p = valid ? (uint64_t)lane : 0ull;
   const float* Jt = J + (size_t)b * N * N;
   const float* ht = h + (size_t)b * N;
-  const double* tab = table64 + ((size_t)b * a.table_recs + (size_t)a.table_offset) * 8;
+  const double* tab = table64 + ((size_t)b * a.table_recs + (size_t)a.table_offset) * (2 + U);
 
   // ---- per-lane init (fp64): y_f = sum_q J_fq s_q, the field on free spin f
   // from the prefix spins q >= n; E_P the energy of the prefix spins alone
@@ -323,8 +347,12 @@ __global__ __launch_bounds__(256, (lz_min_blocks<kMode, NB>())) void k_logz(LzAr
   const double base = lzqmin[b] - (double)a.e0[b];
 
   double c2[NB];   // -beta / ln 2
+  float c2f2[NB];  // 2 c2, for the factor exponents
 #pragma unroll
-  for (int k = 0; k < NB; ++k) c2[k] = -(double)a.beta[k] * 1.4426950408889634;
+  for (int k = 0; k < NB; ++k) {
+    c2[k] = -(double)a.beta[k] * 1.4426950408889634;
+    c2f2[k] = (float)(2.0 * c2[k]);
+  }
 
   // per-lane totals
   double L[NB];                                 // forward
@@ -348,20 +376,26 @@ __global__ __launch_bounds__(256, (lz_min_blocks<kMode, NB>())) void k_logz(LzAr
   }
   __syncthreads();  // s_y, s_bq
 
+  // field energy of the high spins, -sum_k s_k y_(U+k), all down at T = 0;
+  // updated by one flip per block (fp64, at most 2^H - 1 terms)
+  double gh = 0.0;
+  for (int k = 0; k < H; ++k) gh += s_y[k * 256 + tid];
+
   const uint32_t nblocks = 1u << (n - U);
   for (uint32_t T = 0; T < nblocks; ++T) {
     // the bq tables are re-read from LDS every block instead of being held in
     // registers for the whole lane
     asm volatile("" ::: "memory");
-    const double* rec = tab + (size_t)T * 8;
+    const double* rec = tab + (size_t)T * (2 + U);
     const bool odd = T & 1u;
     const uint32_t xh = T ^ (T >> 1);  // high spins of this block (bit k: spin U + k)
-    // energy at the block start without the low-low part, from scratch
-    double G0 = (odd ? epa1 : epa0) + rec[1];
-    for (int k = 0; k < H; ++k) {
-      const double yg = s_y[k * 256 + tid];
-      G0 = ((xh >> k) & 1u) ? G0 - yg : G0 + yg;
+    if (T) {
+      const int kb = __builtin_ctz(T);  // the high spin that flipped
+      const double yb = 2.0 * s_y[kb * 256 + tid];
+      gh = ((xh >> kb) & 1u) ? gh - yb : gh + yb;
     }
+    // energy at the block start without the low-low part
+    const double G0 = (odd ? epa1 : epa0) + rec[1] + gh;
     // phi_f: coefficient of s_f (f < U) in the block's energy
     double phi[U];
 #pragma unroll
@@ -376,37 +410,66 @@ __global__ __launch_bounds__(256, (lz_min_blocks<kMode, NB>())) void k_logz(LzAr
     }
     const double Lb = K - sabs + base;  // lower bound of E - E0 over the block
 
-    float Af[NB][8], Bf[NB][8];
-    double P[NB];
+    float pa[U];
 #pragma unroll
-    for (int k = 0; k < NB; ++k) {
-      P[k] = valid ? exp2_wide(c2[k] * Lb) : 0.0;
-      float cp[U], cm[U];
+    for (int f = 0; f < U; ++f) pa[f] = (float)fabs(phi[f]);
+    // c_f(s_f) at beta k: 1 for the sign that lowers phi_f s_f, 2^(2 c2 |phi_f|)
+    // for the other (cp: s_f = +1, cm: s_f = -1)
+    auto factors = [&](int k, float* cp, float* cm) {
 #pragma unroll
       for (int f = 0; f < U; ++f) {
-        const float af = __builtin_amdgcn_exp2f((float)(c2[k] * 2.0 * fabs(phi[f])));
+        const float af = __builtin_amdgcn_exp2f(c2f2[k] * pa[f]);
         cp[f] = phi[f] > 0.0 ? af : 1.0f;
         cm[f] = phi[f] > 0.0 ? 1.0f : af;
       }
-      triple_products(cp, cm, Af[k]);
-      triple_products(cp + 3, cm + 3, Bf[k]);
-    }
+    };
 
-    if (kMode == 0) {
+    if constexpr (kMode == 0) {
+      // one beta at a time: sum_x A(x_lo) B(x_hi) bq(x) over the 2^U
+      // configurations, x_lo the spins below U/2
 #pragma unroll
       for (int k = 0; k < NB; ++k) {
-        const float* q = s_bq + k * kLzQ;  // bq by configuration
+        const double P = valid ? exp2_wide(c2[k] * Lb) : 0.0;
+        float cp[U], cm[U], Af[kM], Bf[kM];
+        factors(k, cp, cm);
+        factor_products<U / 2>(cp, cm, Af);
+        factor_products<U / 2>(cp + U / 2, cm + U / 2, Bf);
+        // bq by configuration (uniform LDS reads), one row of 2^(U/2) read
+        // ahead of its products.  The empty asm after each row ties the
+        // row's products (through S) to the reads (memory clobber), so later
+        // rows are not fetched early into registers.
+        const float* q = s_bq + k * kQ;
+        float qc[kM], qn[kM];
+#pragma unroll
+        for (int x1 = 0; x1 < kM; ++x1) qc[x1] = q[x1];
         float S = 0.0f;
 #pragma unroll
-        for (int x2 = 0; x2 < 8; ++x2) {
+        for (int x2 = 0; x2 < kM; ++x2) {
+          if (x2 + 1 < kM) {
+#pragma unroll
+            for (int x1 = 0; x1 < kM; ++x1) qn[x1] = q[x1 + kM * (x2 + 1)];
+          }
           float u = 0.0f;
 #pragma unroll
-          for (int x1 = 0; x1 < 8; ++x1) u = fmaf(Af[k][x1], q[x1 + 8 * x2], u);
-          S = fmaf(Bf[k][x2], u, S);
+          for (int x1 = 0; x1 < kM; ++x1) u = fmaf(Af[x1], qc[x1], u);
+          S = fmaf(Bf[x2], u, S);
+          asm volatile("" : "+v"(S) : : "memory");
+#pragma unroll
+          for (int x1 = 0; x1 < kM; ++x1) qc[x1] = qn[x1];
         }
-        L[k] += P[k] * (double)S;
+        L[k] += P * (double)S;
       }
     } else {
+      float Af[NB][8], Bf[NB][8];
+      double P[NB];
+#pragma unroll
+      for (int k = 0; k < NB; ++k) {
+        P[k] = valid ? exp2_wide(c2[k] * Lb) : 0.0;
+        float cp[U], cm[U];
+        factors(k, cp, cm);
+        factor_products<3>(cp, cm, Af[k]);
+        factor_products<3>(cp + 3, cm + 3, Bf[k]);
+      }
       // fold the beta's weight into A and the block parity into B: Gray step
       // i has spins 3-5 at bits 3-5 of gray(i), with spin 5 flipped in odd
       // blocks
@@ -424,7 +487,7 @@ __global__ __launch_bounds__(256, (lz_min_blocks<kMode, NB>())) void k_logz(LzAr
             Bf[k][x2 + 4] = t;
           }
         }
-        bqs[k] = s_bq + k * kLzQ + kLzSteps * (odd ? 2 : 1);
+        bqs[k] = s_bq + k * kQ + kSteps * (odd ? 2 : 1);
       }
       BlockWalk<NB> bw{Af, Bf, bqs, odd ? 1.0f : -1.0f};
       const Coefs C = bw.template walk<U, 0>();
@@ -561,12 +624,17 @@ __global__ void k_lz_final_bwd(LzArgs a, float* grad_J, float* grad_h) {
 hipError_t launch_lz_prep(int mode, const LzArgs& a, const float* J, float* lzq, double* lzqmin,
                           const float* energies, float* e0_out, const double* logz,
                           const double* grad, hipStream_t st) {
-  if (mode == 0)
-    hipLaunchKernelGGL(k_lz_prep<0>, dim3(a.B), dim3(256), 0, st, a, J, lzq, lzqmin, energies,
-                       e0_out, logz, grad);
+  if (mode == 0 && a.U == kLzUF)
+    hipLaunchKernelGGL((k_lz_prep<0, kLzUF>), dim3(a.B), dim3(256), 0, st, a, J, lzq, lzqmin,
+                       energies, e0_out, logz, grad);
+  else if (mode == 0 && a.U == kLzU)
+    hipLaunchKernelGGL((k_lz_prep<0, kLzU>), dim3(a.B), dim3(256), 0, st, a, J, lzq, lzqmin,
+                       energies, e0_out, logz, grad);
+  else if (mode == 1 && a.U == kLzU)
+    hipLaunchKernelGGL((k_lz_prep<1, kLzU>), dim3(a.B), dim3(256), 0, st, a, J, lzq, lzqmin,
+                       energies, e0_out, logz, grad);
   else
-    hipLaunchKernelGGL(k_lz_prep<1>, dim3(a.B), dim3(256), 0, st, a, J, lzq, lzqmin, energies,
-                       e0_out, logz, grad);
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
@@ -575,18 +643,31 @@ hipError_t launch_logz(int mode, const LzArgs& a, const float* J, const float* h
                        hipStream_t st) {
   const int bpi = (int)((a.lanes + 255) / 256);
   const dim3 grid((unsigned)((int64_t)bpi * a.B));
-#define SG_LZ_LAUNCH(M, NBV)                                                                   \
-  hipLaunchKernelGGL((k_logz<M, NBV>), grid, dim3(256), 0, st, a, J, h, table64, lzq, lzqmin, bpi)
-  switch (mode * 8 + a.nb) {
-    case 1: SG_LZ_LAUNCH(0, 1); break;
-    case 2: SG_LZ_LAUNCH(0, 2); break;
-    case 3: SG_LZ_LAUNCH(0, 3); break;
-    case 4: SG_LZ_LAUNCH(0, 4); break;
-    case 9: SG_LZ_LAUNCH(1, 1); break;
-    case 10: SG_LZ_LAUNCH(1, 2); break;
-    case 11: SG_LZ_LAUNCH(1, 3); break;
-    case 12: SG_LZ_LAUNCH(1, 4); break;
-    default: return hipErrorInvalidValue;
+#define SG_LZ_LAUNCH(M, NBV, UV)                                                          \
+  hipLaunchKernelGGL((k_logz<M, NBV, UV>), grid, dim3(256), 0, st, a, J, h, table64, lzq, lzqmin, \
+                     bpi)
+  if (mode == 0 && a.U == kLzUF) {
+    switch (a.nb) {
+      case 1: SG_LZ_LAUNCH(0, 1, kLzUF); break;
+      case 2: SG_LZ_LAUNCH(0, 2, kLzUF); break;
+      case 3: SG_LZ_LAUNCH(0, 3, kLzUF); break;
+      case 4: SG_LZ_LAUNCH(0, 4, kLzUF); break;
+      default: return hipErrorInvalidValue;
+    }
+  } else if (a.U == kLzU) {
+    switch (mode * 8 + a.nb) {
+      case 1: SG_LZ_LAUNCH(0, 1, kLzU); break;
+      case 2: SG_LZ_LAUNCH(0, 2, kLzU); break;
+      case 3: SG_LZ_LAUNCH(0, 3, kLzU); break;
+      case 4: SG_LZ_LAUNCH(0, 4, kLzU); break;
+      case 9: SG_LZ_LAUNCH(1, 1, kLzU); break;
+      case 10: SG_LZ_LAUNCH(1, 2, kLzU); break;
+      case 11: SG_LZ_LAUNCH(1, 3, kLzU); break;
+      case 12: SG_LZ_LAUNCH(1, 4, kLzU); break;
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    return hipErrorInvalidValue;
   }
 #undef SG_LZ_LAUNCH
   return hipGetLastError();
