@@ -411,16 +411,23 @@ __global__ __launch_bounds__(256, (lz_min_blocks<kMode, NB>())) void k_logz(LzAr
     const double Lb = K - sabs + base;  // lower bound of E - E0 over the block
 
     float pa[U];
+    bool up[U];  // the exponential factor goes with s_f = +1 (cp) rather than -1
 #pragma unroll
-    for (int f = 0; f < U; ++f) pa[f] = (float)fabs(phi[f]);
+    for (int f = 0; f < U; ++f) {
+      pa[f] = (float)fabs(phi[f]);
+      up[f] = phi[f] > 0.0;
+    }
+    // the gradient walk indexes spin U-1 by the bits of its Gray steps, which
+    // flip that spin in odd blocks: exchange its two factors there
+    if (kMode == 1 && odd) up[U - 1] = !up[U - 1];
     // c_f(s_f) at beta k: 1 for the sign that lowers phi_f s_f, 2^(2 c2 |phi_f|)
     // for the other (cp: s_f = +1, cm: s_f = -1)
     auto factors = [&](int k, float* cp, float* cm) {
 #pragma unroll
       for (int f = 0; f < U; ++f) {
         const float af = __builtin_amdgcn_exp2f(c2f2[k] * pa[f]);
-        cp[f] = phi[f] > 0.0 ? af : 1.0f;
-        cm[f] = phi[f] > 0.0 ? 1.0f : af;
+        cp[f] = up[f] ? af : 1.0f;
+        cm[f] = up[f] ? 1.0f : af;
       }
     };
 
@@ -460,33 +467,21 @@ __global__ __launch_bounds__(256, (lz_min_blocks<kMode, NB>())) void k_logz(LzAr
         L[k] += P * (double)S;
       }
     } else {
+      // A: factor products of spins 0-2 times the beta's weight (folded into
+      // spin 0's two factors); B: spins 3-5, indexed by the Gray step's bits
+      // (block parity folded in through up[])
       float Af[NB][8], Bf[NB][8];
-      double P[NB];
-#pragma unroll
-      for (int k = 0; k < NB; ++k) {
-        P[k] = valid ? exp2_wide(c2[k] * Lb) : 0.0;
-        float cp[U], cm[U];
-        factors(k, cp, cm);
-        factor_products<3>(cp, cm, Af[k]);
-        factor_products<3>(cp + 3, cm + 3, Bf[k]);
-      }
-      // fold the beta's weight into A and the block parity into B: Gray step
-      // i has spins 3-5 at bits 3-5 of gray(i), with spin 5 flipped in odd
-      // blocks
       const float* bqs[NB];
 #pragma unroll
       for (int k = 0; k < NB; ++k) {
-        const float sk = (float)(a.coef[(size_t)b * kMaxBeta + k] * P[k]);
-#pragma unroll
-        for (int x1 = 0; x1 < 8; ++x1) Af[k][x1] *= sk;
-        if (odd) {
-#pragma unroll
-          for (int x2 = 0; x2 < 4; ++x2) {
-            const float t = Bf[k][x2];
-            Bf[k][x2] = Bf[k][x2 + 4];
-            Bf[k][x2 + 4] = t;
-          }
-        }
+        const double P = valid ? exp2_wide(c2[k] * Lb) : 0.0;
+        const float sk = (float)(a.coef[(size_t)b * kMaxBeta + k] * P);
+        float cp[U], cm[U];
+        factors(k, cp, cm);
+        cp[0] *= sk;
+        cm[0] *= sk;
+        factor_products<3>(cp, cm, Af[k]);
+        factor_products<3>(cp + 3, cm + 3, Bf[k]);
         bqs[k] = s_bq + k * kQ + kSteps * (odd ? 2 : 1);
       }
       BlockWalk<NB> bw{Af, Bf, bqs, odd ? 1.0f : -1.0f};

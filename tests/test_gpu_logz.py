@@ -80,6 +80,24 @@ def test_forward_backward_vs_oracle(orc, torch_dev, N):
         check_grad(gJ[b], gh[b], gJ_ref, gh_ref, "N=%d b=%d" % (N, b))
 
 
+@pytest.mark.parametrize("betas", [[1.3], [0.25, 3.0], [0.2, 0.7, 1.5, 2.5]])
+@pytest.mark.parametrize("N", [7, 12])
+def test_beta_counts_vs_oracle(orc, torch_dev, N, betas):
+    """One, two and four inverse temperatures (each count is its own kernel),
+    with blocks of 6 low spins (N = 7) and of 8 (N = 12)."""
+    B = 2
+    J, h = I.logz_batch(B, N, 60 + N + len(betas))
+    lz, _, _, _ = gpu_forward(torch_dev, J, h, betas, 8)
+    rng = np.random.default_rng(100 + N + len(betas))
+    g = rng.standard_normal((B, len(betas)))
+    gJ, gh = gpu_backward(torch_dev, J, h, betas, g)
+    for b in range(B):
+        what = "N=%d nb=%d b=%d" % (N, len(betas), b)
+        check_logz(lz[b], orc.logz(J[b], h[b], betas)[0], what)
+        gJ_ref, gh_ref = orc.logz_grad(J[b], h[b], betas, g[b])
+        check_grad(gJ[b], gh[b], gJ_ref, gh_ref, what)
+
+
 def test_states_match_batched_search(torch_dev):
     import paper_1904_03621_amd as sg
     torch = torch_dev
