@@ -165,8 +165,9 @@ sg_status sg_low_spectrum_batched_i32(int B, const int32_t *N_dev, int N_max, co
  *                result of sg_low_spectrum_batched_f32 on the same batch
  *
  * The walk keeps its energy chain in fp64 and evaluates each weight in fp32
- * (shifted energy rounded to fp32, hardware exp2); block sums of 64 weights are
- * fp32, every longer sum is fp64.  Relative error of log Z: about 1e-7.  All
+ * (shifted energy rounded to fp32, hardware exp2); block sums of 256 weights
+ * (64 when N = 7) are fp32, every longer sum is fp64.  Relative error of
+ * log Z: about 1e-7.  All
  * buffers are caller-owned; work is enqueued on `stream`.
  */
 sg_status sg_logz_forward_f32(int B, int N, const float *J, const float *h, int n_beta,

@@ -17,9 +17,10 @@
 #include "sg_internal.h"
 
 namespace sg {
-hipError_t launch_prep(bool isint, const Batch& bt, hipStream_t st);
-hipError_t launch_tables(bool isint, const Batch& bt, int ncap, hipStream_t st);
-hipError_t launch_enum(bool isint, const Batch& bt, const Chunk& ch, int ninst, hipStream_t st);
+hipError_t launch_prep(bool isint, int U, const Batch& bt, hipStream_t st);
+hipError_t launch_tables(bool isint, int U, const Batch& bt, int ncap, hipStream_t st);
+hipError_t launch_enum(bool isint, int U, const Batch& bt, const Chunk& ch, int ninst,
+                       hipStream_t st);
 hipError_t launch_direct(const Batch& bt, uint64_t lo, uint64_t hi, hipStream_t st);
 hipError_t launch_score(bool isint, const Batch& bt, int b, int grid, int N, int retry,
                         hipStream_t st);
@@ -75,6 +76,11 @@ sg_status fail(sg_status s, const std::string& msg) {
 
 int ilog2_floor(uint64_t x) { return 63 - __builtin_clzll(x); }
 
+// Low spins per block of a single search: the wider block halves the
+// per-block set-up per state once the instance has enough spins for chunks
+// of at least 2^8 states per lane; batches and the density of states keep kU.
+int search_block(int N) { return N >= 16 ? kUWide : kU; }
+
 struct PlanChunk {
   uint64_t first_mask;
   int n;
@@ -90,7 +96,7 @@ struct PlanChunk {
 // multiple of 2^n, and lanes cover consecutive prefixes.  Ends of the range
 // that are not multiples of a block (2^U states) form chunks with n = 0: one
 // thread per state, every state a candidate.
-std::vector<PlanChunk> plan_chunks(int N, int S, uint64_t lo, uint64_t hi, int64_t fill) {
+std::vector<PlanChunk> plan_chunks(int N, int S, uint64_t lo, uint64_t hi, int64_t fill, int U) {
   std::vector<PlanChunk> out;
   const int nmax = std::min(kMaxFree, N);
   if (fill < kWaveLanes) fill = kWaveLanes;
@@ -98,7 +104,7 @@ std::vector<PlanChunk> plan_chunks(int N, int S, uint64_t lo, uint64_t hi, int64
   uint64_t target = 4096;
   while (target < (uint64_t)S) target <<= 1;
   const uint64_t big = (uint64_t)fill << nmax;
-  const uint64_t blk = (uint64_t)kBlockSteps;
+  const uint64_t blk = (uint64_t)1 << U;
   uint64_t lo_b = (lo + blk - 1) & ~(blk - 1), hi_b = hi & ~(blk - 1);
   if (lo_b >= hi_b) lo_b = hi_b = hi;  // no whole block: one direct chunk
   if (lo < lo_b) out.push_back(PlanChunk{lo, 0, (int64_t)(lo_b - lo)});
@@ -112,7 +118,7 @@ std::vector<PlanChunk> plan_chunks(int N, int S, uint64_t lo, uint64_t hi, int64
       // near the end shrink n rather than the lane count, so that the last
       // chunks still fill the device
       int n = nmax;
-      while (n > kU && (rem >> n) < (uint64_t)fill) --n;
+      while (n > U && (rem >> n) < (uint64_t)fill) --n;
       c.n = n;
       c.lanes = (int64_t)std::min<uint64_t>((uint64_t)fill, rem >> n);
     } else {
@@ -121,7 +127,7 @@ std::vector<PlanChunk> plan_chunks(int N, int S, uint64_t lo, uint64_t hi, int64
       while (size > rem) size >>= 1;
       const int slog = ilog2_floor(size);
       int n = slog - fill_log;
-      n = std::max(n, kU);
+      n = std::max(n, U);
       n = std::min(n, nmax);
       n = std::min(n, slog);
       c.n = n;
@@ -268,7 +274,7 @@ sg_status ws_get(hipStream_t st, int B, size_t recs, size_t cap, int S, Workspac
   }
   const size_t Bz = (size_t)B;
   HIP_TRY(grow(&w->P, &w->nP, Bz));
-  HIP_TRY(grow(&w->qtab, &w->nq, Bz * 2 * kBlockSteps));
+  HIP_TRY(grow(&w->qtab, &w->nq, Bz * kQStride));
   HIP_TRY(grow(&w->table, &w->ntable, Bz * recs * kRecWords));
   if (w->ncand < Bz * cap) {
     size_t have_s = w->ncand, have_m = w->ncand, have_c = w->ncand;
@@ -335,8 +341,8 @@ sg_status validate(int N, const void* J, const void* h, int S, uint64_t lo, uint
   return SG_OK;
 }
 
-hipError_t enum_timed(Workspace* w, bool isint, const Batch& bt, const Chunk& ch, int ninst,
-                      hipStream_t st) {
+hipError_t enum_timed(Workspace* w, bool isint, int U, const Batch& bt, const Chunk& ch,
+                      int ninst, hipStream_t st) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (g_timing) {
     hipError_t r = ws_event_pair(w, &e0, &e1);
@@ -344,7 +350,7 @@ hipError_t enum_timed(Workspace* w, bool isint, const Batch& bt, const Chunk& ch
     r = hipEventRecord(e0, st);
     if (r != hipSuccess) return r;
   }
-  hipError_t r = launch_enum(isint, bt, ch, ninst, st);
+  hipError_t r = launch_enum(isint, U, bt, ch, ninst, st);
   if (r != hipSuccess) return r;
   ++w->last_launches;
   if (g_timing) r = hipEventRecord(e1, st);
@@ -359,20 +365,21 @@ sg_status run_search(bool isint, int N, const void* J, const void* h, int S, uin
   hipStream_t st = (hipStream_t)stream;
   uint32_t cap = kCandCapMin;
   while (cap < 8u * (uint32_t)S) cap <<= 1;
-  const int ncap = std::min(kMaxFree, std::max(N, kU));
-  const size_t recs = table_records(kMaxFree);
+  const int U = search_block(N);
+  const int ncap = std::min(kMaxFree, std::max(N, U));
+  const size_t recs = table_records(kMaxFree);  // blocks of kU outnumber those of kUWide
   Workspace* w = nullptr;
   v = ws_get(st, 1, recs, cap, S, &w);
   if (v != SG_OK) return v;
   const Batch bt = make_batch(w, J, h, nullptr, N, N, 1, S, (int64_t)recs, cap);
 
-  HIP_TRY(launch_prep(isint, bt, st));
+  HIP_TRY(launch_prep(isint, U, bt, st));
   const int score_grid = std::max(1, w->cus) * 4;
   int kmax = 0, nmaxu = 0;
   w->ev_used = 0;
   w->last_launches = 0;
-  if (N >= kU) HIP_TRY(launch_tables(isint, bt, ncap, st));
-  const std::vector<PlanChunk> plan = plan_chunks(N, S, lo, hi, w->fill[isint ? 1 : 0]);
+  if (N >= U) HIP_TRY(launch_tables(isint, U, bt, ncap, st));
+  const std::vector<PlanChunk> plan = plan_chunks(N, S, lo, hi, w->fill[isint ? 1 : 0], U);
   double states = 0.0;
   for (const PlanChunk& pc : plan) {
     if (pc.n == 0) {
@@ -388,14 +395,14 @@ sg_status run_search(bool isint, int N, const void* J, const void* h, int S, uin
     ch.prefix_base = pc.first_mask >> pc.n;
     ch.lanes = pc.lanes;
     ch.n = pc.n;
-    ch.table_offset = (1 << (pc.n - kU)) - 1;
+    ch.table_offset = (1 << (pc.n - U)) - 1;
     // a chunk with more states than candidate slots may overflow: it gets
     // up to kRetries repeated passes, each run only if the last overflowed
     const uint64_t cstates = (uint64_t)pc.lanes << pc.n;
     const int passes = cstates > (uint64_t)cap ? 1 + kRetries : 1;
     for (int r = 0; r < passes; ++r) {
       ch.retry = r;
-      HIP_TRY(enum_timed(w, isint, bt, ch, 1, st));
+      HIP_TRY(enum_timed(w, isint, U, bt, ch, 1, st));
       HIP_TRY(launch_score(isint, bt, 0, score_grid, N, r, st));
       HIP_TRY(launch_merge(bt, 0, r, r == passes - 1, st));
     }
@@ -479,8 +486,8 @@ std::vector<Level> batch_levels(int Nmax, int S, int shift) {
 // finalize into states_out / energies_out.
 sg_status batch_search(Workspace* w, bool isint, const Batch& bt, int Nmax, int ncap,
                        uint64_t* states_out, void* energies_out, hipStream_t st) {
-  HIP_TRY(launch_prep(isint, bt, st));
-  HIP_TRY(launch_tables(isint, bt, ncap, st));
+  HIP_TRY(launch_prep(isint, kU, bt, st));
+  HIP_TRY(launch_tables(isint, kU, bt, ncap, st));
   const std::vector<Level> levels =
       batch_levels(Nmax, bt.S, batch_shift(bt.B, Nmax, bt.S, w->fill[isint ? 1 : 0]));
   w->ev_used = 0;
@@ -498,7 +505,7 @@ sg_status batch_search(Workspace* w, bool isint, const Batch& bt, int Nmax, int 
     const int passes = lstates > (uint64_t)bt.cap ? 1 + kRetries : 1;
     for (int r = 0; r < passes; ++r) {
       ch.retry = r;
-      HIP_TRY(enum_timed(w, isint, bt, ch, bt.B, st));
+      HIP_TRY(enum_timed(w, isint, kU, bt, ch, bt.B, st));
       HIP_TRY(launch_merge_batched(isint, bt, L.first, r, r == passes - 1, st));
     }
     states += (double)lstates;
@@ -758,7 +765,7 @@ sg_status sg_density_of_states_i32(int N, const int32_t* J, const int32_t* h, lo
   if (v != SG_OK) return v;
   Batch bt = make_batch(w, J, h, nullptr, N, N, 1, 1, (int64_t)recs, 1);
   bt.allow_f32_walk = 0;  // the histogram walk reads integer tables
-  HIP_TRY(launch_prep(true, bt, st));
+  HIP_TRY(launch_prep(true, kU, bt, st));
   HIP_TRY(launch_dos_prologue(bt, e_min, n_bins, counts_out, st));
   w->ev_used = 0;
   w->last_launches = 0;
@@ -772,7 +779,7 @@ sg_status sg_density_of_states_i32(int N, const int32_t* J, const int32_t* h, lo
     const int64_t fill = w->fill[1];
     int n = std::min(kMaxFree, N);
     while (n > kU && ((int64_t)1 << (N - n)) < fill) --n;
-    HIP_TRY(launch_tables(true, bt, n, st));
+    HIP_TRY(launch_tables(true, kU, bt, n, st));
     const uint64_t prefixes = (uint64_t)1 << (N - n);
     for (uint64_t base = 0; base < prefixes; base += (uint64_t)fill) {
       Chunk ch{};
@@ -933,7 +940,7 @@ int sg_debug_plan(int N, int S, uint64_t lo, uint64_t hi, int64_t lanes_fill,
   if (N < 1 || N > SG_MAX_N || S < 1 || lo >= hi || hi > ((uint64_t)1 << N) || (lo % 64) != 0 ||
       lanes_fill < 1)
     return -1;
-  const std::vector<PlanChunk> plan = plan_chunks(N, S, lo, hi, lanes_fill);
+  const std::vector<PlanChunk> plan = plan_chunks(N, S, lo, hi, lanes_fill, search_block(N));
   for (int i = 0; i < (int)plan.size() && i < cap; ++i) {
     if (first_mask) first_mask[i] = plan[i].first_mask;
     if (free_bits) free_bits[i] = plan[i].n;

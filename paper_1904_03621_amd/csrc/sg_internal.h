@@ -18,11 +18,16 @@
 
 namespace sg {
 
-constexpr int kU = 7;                 // low spins per search block: 2^7 = 128 steps
+// Low spins per search block: U = kU (2^7 = 128 steps) for batches and the
+// density of states, kUWide (2^8 = 256) for single searches of N >= 16,
+// whose per-block set-up is then spread over twice the states.
+constexpr int kU = 7;
+constexpr int kUWide = 8;
 constexpr int kBlockSteps = 1 << kU;
+constexpr int kQStride = 2 << kUWide;  // qtab words per instance (both block parities)
 constexpr int kMaxFree = 22;          // largest n (free spins per lane)
 constexpr int kMaxHigh = kMaxFree - kU;
-constexpr int kRecWords = 16;         // per-block table record (64 B: cB, R, Wu_0..U-1)
+constexpr int kRecWords = 16;         // per-block table record (64 B: cB, R, Wu_0..U-1, U <= 14)
 constexpr int kReanchorLog2 = 10;     // fp32: fresh G every 2^10 flips
 constexpr int kReanchorBlocks = 1 << (kReanchorLog2 - kU);
 // The log Z walk uses blocks of its own, U low spins with fp64 records of
@@ -98,7 +103,7 @@ struct Batch {
   int B;
   int S;
   Params* P;           // [B]
-  uint32_t* qtab;      // [B][2 * kBlockSteps] low-low energies by block parity and step
+  uint32_t* qtab;      // [B][kQStride] low-low energies by block parity and step
   uint32_t* table;     // [B][table_recs][kRecWords]
   int64_t table_recs;
   uint64_t* cand;      // [B][cap] candidate masks

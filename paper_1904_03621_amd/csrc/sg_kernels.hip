@@ -106,13 +106,15 @@ __device__ inline bool key_less(uint32_t ka, uint64_t ma, uint32_t kb, uint64_t 
 // for both block parities), their minimum, the pruning margin, the error
 // flags and the initial (empty) record state.
 
-template <bool kInt>
+template <bool kInt, int U>
 __global__ void k_prep(Batch bt) {
+  static_assert(2 << U <= kQStride, "Q tables exceed their stride");
+  constexpr int kSteps = 1 << U;
   const int b = blockIdx.x;
   const int N = inst_N(bt, b);
   const int ld = bt.ld;
   Params* P = bt.P + b;
-  uint32_t* qtab = bt.qtab + (size_t)b * 2 * kBlockSteps;
+  uint32_t* qtab = bt.qtab + (size_t)b * kQStride;
   // a batch (per-instance sizes) needs N_b >= U; a single search takes any N >= 1
   const bool badN = N < (bt.Ns ? kU : 1) || N > ld || (N < 63 && (uint64_t)bt.S > (1ull << N));
   const int Nc = badN ? 0 : N;
@@ -174,10 +176,9 @@ __global__ void k_prep(Batch bt) {
   const bool walk_f32 = kInt && bt.allow_f32_walk && 2.1 * Bv < 16777216.0;
   // Q tables: Q(x) = -sum_{f<f'<U} J_ff' s_f s_f' over the low configuration
   // x = gray(i) ^ (par << (U-1)) of step i in a block of parity par.
-  const int U = kU;
-  __shared__ double s_q[2 * kBlockSteps];
-  if (tid < 2 * kBlockSteps) {
-    const int par = tid / kBlockSteps, i = tid % kBlockSteps;
+  __shared__ double s_q[2 * kSteps];
+  for (int e = tid; e < 2 * kSteps; e += blockDim.x) {
+    const int par = e / kSteps, i = e % kSteps;
     const uint32_t x = gray32((uint32_t)i) ^ ((uint32_t)par << (U - 1));
     double q = 0.0;
     for (int a = 0; a < U && a < Nc; ++a)
@@ -185,12 +186,13 @@ __global__ void k_prep(Batch bt) {
         const double sa = ((x >> a) & 1u) ? 1.0 : -1.0, sc = ((x >> c) & 1u) ? 1.0 : -1.0;
         q -= (double)Jb[a * ld + c] * sa * sc;
       }
-    s_q[tid] = q;
-    if (kInt && !walk_f32) qtab[tid] = (uint32_t)(int32_t)q;
-    else qtab[tid] = __float_as_uint((float)q);
+    s_q[e] = q;
+    if (kInt && !walk_f32) qtab[e] = (uint32_t)(int32_t)q;
+    else qtab[e] = __float_as_uint((float)q);
   }
   __syncthreads();
-  for (int st = kBlockSteps; st > 0; st >>= 1) {
+  static_assert(kSteps <= 256, "one thread per pair of the minimum's first round");
+  for (int st = kSteps; st > 0; st >>= 1) {
     if (tid < st) s_q[tid] = fmin(s_q[tid], s_q[tid + st]);
     __syncthreads();
   }
@@ -221,9 +223,9 @@ __global__ void k_prep(Batch bt) {
       const bool exact = Bv == 0.0 || (lsb_min < (1 << 19) && 2.1 * Bv < ldexp(1.0, 24 + lsb_min));
       if (!exact) {
         const double uH = H * 5.9604644775390625e-08;  // 2^-24
-        const double R = (double)kReanchorBlocks;
+        const double R = (double)(1 << (kReanchorLog2 - U));
         const double rounds =
-            R * (kBlockSteps - 1.0 + 3.0 * U + 3.0) + (kMaxFree + 3.0) + kMaxFree * 0.5 + 4.0 +
+            R * (kSteps - 1.0 + 3.0 * U + 3.0) + (kMaxFree + 3.0) + kMaxFree * 0.5 + 4.0 +
             4.0;
         margin = rounds * uH;
       }
@@ -261,12 +263,13 @@ __global__ void k_prep(Batch bt) {
 //                 odd T, -1 for even T (old value of spin U-1 when the inner
 //                 step 2^(U-1) flips it).
 // Tables for n = U .. nmax are concatenated; the table of n starts at record
-// 2^(n-U) - 1.  grid.y indexes the instance.  The search uses U = kU (words
-// of kRecWords); the log Z walk (kF64) U = kUF and records of 2 + U doubles.
+// 2^(n-U) - 1.  grid.y indexes the instance.  The search uses U = kU or
+// kUWide (words of kRecWords); the log Z walk (kF64) U = kLzU or kLzUF and
+// records of 2 + U doubles.
 
-template <bool kInt, bool kF64, int kUF = kLzU>
+template <bool kInt, bool kF64, int U>
 __global__ void k_tables(Batch bt, int ncap, void* out) {
-  constexpr int U = kF64 ? kUF : kU;
+  static_assert(kF64 || 2 + U <= kRecWords, "record exceeds kRecWords");
   const int b = blockIdx.y;
   const int N = inst_N(bt, b);
   if (N < U || N > bt.ld) return;
@@ -358,7 +361,7 @@ struct Num<int32_t> {
   static __device__ inline int32_t big() { return 1 << 29; }
 };
 
-template <bool kInt, bool kWF>
+template <bool kInt, bool kWF, int U>
 __device__ __forceinline__ void enum_walk(const Batch& bt, const void* __restrict__ Jv,
                                           const void* __restrict__ hv,
                                           const uint32_t* __restrict__ table,
@@ -366,7 +369,8 @@ __device__ __forceinline__ void enum_walk(const Batch& bt, const void* __restric
                                           int b, int blk, int N, int n, int64_t lanes, Params* P,
                                           uint32_t* s_yw, void* s_Fw, void* s_Rw, void* s_EHw);
 
-template <bool kInt>
+// U: low spins per block (kU or kUWide; n >= U for every chunk)
+template <bool kInt, int U>
 __global__ __launch_bounds__(kEnumBlock, 8) void k_enum(Batch bt, const void* __restrict__ Jv,
                                                         const void* __restrict__ hv,
                                                         const uint32_t* __restrict__ table,
@@ -395,17 +399,17 @@ __global__ __launch_bounds__(kEnumBlock, 8) void k_enum(Batch bt, const void* __
   __shared__ A s_R[2][kMaxN];
   __shared__ A s_EH[2];
   if (kInt && P->walk_f32)
-    enum_walk<true, true>(bt, Jv, hv, table, qtab_all, ch, b, blk, N, n, lanes, P, s_y, s_F, s_R,
-                          s_EH);
+    enum_walk<true, true, U>(bt, Jv, hv, table, qtab_all, ch, b, blk, N, n, lanes, P, s_y, s_F,
+                             s_R, s_EH);
   else
-    enum_walk<kInt, !kInt>(bt, Jv, hv, table, qtab_all, ch, b, blk, N, n, lanes, P, s_y, s_F,
-                           s_R, s_EH);
+    enum_walk<kInt, !kInt, U>(bt, Jv, hv, table, qtab_all, ch, b, blk, N, n, lanes, P, s_y, s_F,
+                              s_R, s_EH);
 }
 
 // The walk of k_enum.  kInt: the instance is int32 (exact set-up in int64,
 // integer keys); kWF: the walk runs in fp32 (fp32 instances, and integer ones
 // whose values fit 24 bits, whose tables then hold fp32 values).
-template <bool kInt, bool kWF>
+template <bool kInt, bool kWF, int U>
 __device__ __forceinline__ void enum_walk(const Batch& bt, const void* __restrict__ Jv,
                                           const void* __restrict__ hv,
                                           const uint32_t* __restrict__ table,
@@ -415,9 +419,11 @@ __device__ __forceinline__ void enum_walk(const Batch& bt, const void* __restric
   using V = typename std::conditional<kWF, float, int32_t>::type;
   using A = typename std::conditional<kInt, int64_t, double>::type;  // exact init
   using Ts = typename std::conditional<kInt, int32_t, float>::type;  // stored values
-  constexpr int U = kU;
+  static_assert(U >= kU, "s_y holds the kMaxFree - kU high fields of the smallest blocks");
+  constexpr int kSteps = 1 << U;                            // steps per block
+  constexpr int kReBlocks = 1 << (kReanchorLog2 - U);       // fp32: blocks per re-anchor
   V* s_y = (V*)s_yw;
-  const uint32_t* qtab = qtab_all + (size_t)b * 2 * kBlockSteps;  // uniform: SGPRs
+  const uint32_t* qtab = qtab_all + (size_t)b * kQStride;  // uniform: SGPRs
 
   const int tid = threadIdx.x;
   const int ld = bt.ld;
@@ -458,7 +464,7 @@ __device__ __forceinline__ void enum_walk(const Batch& bt, const void* __restric
   A(*s_R)[kMaxN] = (A(*)[kMaxN])s_Rw;
   A* s_EH = (A*)s_EHw;
   const int kp = N - n;
-  static_assert(kMaxN * (kMaxN - kU) + (kMaxN - kU) <= kMaxHigh * kEnumBlock,
+  static_assert(kMaxN * (kMaxN - U) + (kMaxN - U) <= kMaxHigh * kEnumBlock,
                 "coupling stage exceeds s_y");
   V* s_stage = s_y;  // s_stage[i kp + q - n] = J_iq (q >= n); then h_q at N kp + q - n
   const V* s_hp = s_stage + N * kp;
@@ -604,7 +610,7 @@ __device__ __forceinline__ void enum_walk(const Batch& bt, const void* __restric
       const bool up = (T >> (c + 1)) & 1u;
       G = up ? G + ycur : G - ycur;
       G = G + rw[0];
-      if (!kInt && (T & (kReanchorBlocks - 1)) == 0) {
+      if (!kInt && (T & (kReBlocks - 1)) == 0) {
         // fresh G = E_P - sum_f s_f y_f + R(T) in fp32 from the lane's
         // fields: the low part is the parity constant, the high part one LDS
         // read and one fma per high spin (signs from the Gray code of T)
@@ -629,11 +635,11 @@ __device__ __forceinline__ void enum_walk(const Batch& bt, const void* __restric
     const V Gs = G;
     V m = G;
 #pragma unroll
-    for (int i = 1; i < kBlockSteps; i += 2) {
+    for (int i = 1; i < kSteps; i += 2) {
       // odd step i flips spin 0; its old value is bit 1 of i
       G = ((i >> 1) & 1) ? G + W[0] : G - W[0];
       const V Ga = G;
-      if (i + 1 < kBlockSteps) {
+      if (i + 1 < kSteps) {
         const int f = __builtin_ctz(i + 1);
         if (f == U - 1) G = G + W[f];
         else G = (((i + 1) >> (f + 1)) & 1) ? G + W[f] : G - W[f];
@@ -649,17 +655,17 @@ __device__ __forceinline__ void enum_walk(const Batch& bt, const void* __restric
       // bound passed; the opaque copy keeps the compiler from holding the
       // values of the fast walk live across the branch
       ++slow;
-      const uint32_t* q = qtab + (T & 1u) * kBlockSteps;
+      const uint32_t* q = qtab + (T & 1u) * kSteps;
       V g2 = Gs;
       asm volatile("" : "+v"(g2));
-      constexpr int kHitWords = kBlockSteps / 64;
+      constexpr int kHitWords = kSteps / 64;
       uint64_t hits[kHitWords];
 #pragma unroll
       for (int w = 0; w < kHitWords; ++w) hits[w] = 0ull;
       auto qv = [&](int i) -> V { return kWF ? (V)__uint_as_float(q[i]) : (V)(int32_t)q[i]; };
       if (g2 + qv(0) <= thrE) hits[0] |= 1ull;
 #pragma unroll
-      for (int i = 1; i < kBlockSteps; ++i) {
+      for (int i = 1; i < kSteps; ++i) {
         const int f = __builtin_ctz(i);
         if (f == U - 1) g2 = g2 + W[f];
         else g2 = ((i >> (f + 1)) & 1) ? g2 + W[f] : g2 - W[f];
@@ -1121,17 +1127,33 @@ __global__ void k_finalize(Batch bt, uint64_t* states_out, void* energies_out) {
 
 // ---------------------------------------------------------------- launchers
 
-hipError_t launch_prep(bool isint, const Batch& bt, hipStream_t st) {
-  if (isint) hipLaunchKernelGGL(k_prep<true>, dim3(bt.B), dim3(256), 0, st, bt);
-  else hipLaunchKernelGGL(k_prep<false>, dim3(bt.B), dim3(256), 0, st, bt);
+// U: low spins per block of the walk that follows (kU or kUWide)
+hipError_t launch_prep(bool isint, int U, const Batch& bt, hipStream_t st) {
+  if (U != kU && U != kUWide) return hipErrorInvalidValue;
+  if (isint) {
+    if (U == kU) hipLaunchKernelGGL((k_prep<true, kU>), dim3(bt.B), dim3(256), 0, st, bt);
+    else hipLaunchKernelGGL((k_prep<true, kUWide>), dim3(bt.B), dim3(256), 0, st, bt);
+  } else {
+    if (U == kU) hipLaunchKernelGGL((k_prep<false, kU>), dim3(bt.B), dim3(256), 0, st, bt);
+    else hipLaunchKernelGGL((k_prep<false, kUWide>), dim3(bt.B), dim3(256), 0, st, bt);
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_tables(bool isint, const Batch& bt, int ncap, hipStream_t st) {
-  const int64_t total = ((int64_t)1 << (ncap - kU + 1)) - 1;  // search records
+hipError_t launch_tables(bool isint, int U, const Batch& bt, int ncap, hipStream_t st) {
+  if (U != kU && U != kUWide) return hipErrorInvalidValue;
+  const int64_t total = ((int64_t)1 << (ncap - U + 1)) - 1;  // search records
   const dim3 grid((unsigned)((total + 255) / 256), (unsigned)bt.B);
-  if (isint) hipLaunchKernelGGL((k_tables<true, false>), grid, dim3(256), 0, st, bt, ncap, nullptr);
-  else hipLaunchKernelGGL((k_tables<false, false>), grid, dim3(256), 0, st, bt, ncap, nullptr);
+#define SG_TABLES(I, UV) \
+  hipLaunchKernelGGL((k_tables<I, false, UV>), grid, dim3(256), 0, st, bt, ncap, nullptr)
+  if (isint) {
+    if (U == kU) SG_TABLES(true, kU);
+    else SG_TABLES(true, kUWide);
+  } else {
+    if (U == kU) SG_TABLES(false, kU);
+    else SG_TABLES(false, kUWide);
+  }
+#undef SG_TABLES
   return hipGetLastError();
 }
 
@@ -1147,15 +1169,22 @@ hipError_t launch_tables64(const Batch& bt, int ncap, int U, double* out, hipStr
   return hipGetLastError();
 }
 
-hipError_t launch_enum(bool isint, const Batch& bt, const Chunk& ch, int ninst, hipStream_t st) {
+hipError_t launch_enum(bool isint, int U, const Batch& bt, const Chunk& ch, int ninst,
+                       hipStream_t st) {
+  if ((U != kU && U != kUWide) || ch.n < U) return hipErrorInvalidValue;
   const int bpi = (int)((ch.lanes + kEnumBlock - 1) / kEnumBlock);
   const dim3 grid((unsigned)((int64_t)bpi * ninst));
-  if (isint)
-    hipLaunchKernelGGL(k_enum<true>, grid, dim3(kEnumBlock), 0, st, bt, bt.J, bt.h,
-                       (const uint32_t*)bt.table, (const uint32_t*)bt.qtab, ch, bpi);
-  else
-    hipLaunchKernelGGL(k_enum<false>, grid, dim3(kEnumBlock), 0, st, bt, bt.J, bt.h,
-                       (const uint32_t*)bt.table, (const uint32_t*)bt.qtab, ch, bpi);
+#define SG_ENUM(I, UV)                                                                     \
+  hipLaunchKernelGGL((k_enum<I, UV>), grid, dim3(kEnumBlock), 0, st, bt, bt.J, bt.h,      \
+                     (const uint32_t*)bt.table, (const uint32_t*)bt.qtab, ch, bpi)
+  if (isint) {
+    if (U == kU) SG_ENUM(true, kU);
+    else SG_ENUM(true, kUWide);
+  } else {
+    if (U == kU) SG_ENUM(false, kU);
+    else SG_ENUM(false, kUWide);
+  }
+#undef SG_ENUM
   return hipGetLastError();
 }
 
@@ -1200,14 +1229,18 @@ hipError_t launch_finalize(bool isint, const Batch& bt, uint64_t* states_out, vo
   return hipGetLastError();
 }
 
+// resident workgroups per CU of the walk (the smaller of the two block sizes)
 int enum_occupancy(bool isint) {
-  int blocks = 0;
-  hipError_t e;
-  if (isint)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_enum<true>, kEnumBlock, 0);
-  else
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_enum<false>, kEnumBlock, 0);
-  return e == hipSuccess ? blocks : 0;
+  int b7 = 0, b8 = 0;
+  hipError_t e7, e8;
+  if (isint) {
+    e7 = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b7, k_enum<true, kU>, kEnumBlock, 0);
+    e8 = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b8, k_enum<true, kUWide>, kEnumBlock, 0);
+  } else {
+    e7 = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b7, k_enum<false, kU>, kEnumBlock, 0);
+    e8 = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b8, k_enum<false, kUWide>, kEnumBlock, 0);
+  }
+  return e7 == hipSuccess && e8 == hipSuccess ? (b7 < b8 ? b7 : b8) : 0;
 }
 
 }  // namespace sg
