@@ -17,7 +17,7 @@
 #include "sg_internal.h"
 
 namespace sg {
-hipError_t launch_prep(bool isint, int U, const Batch& bt, hipStream_t st);
+hipError_t launch_prep(bool isint, const Batch& bt, hipStream_t st);
 hipError_t launch_tables(bool isint, int U, const Batch& bt, int ncap, hipStream_t st);
 hipError_t launch_enum(bool isint, int U, const Batch& bt, const Chunk& ch, int ninst,
                        hipStream_t st);
@@ -373,7 +373,7 @@ sg_status run_search(bool isint, int N, const void* J, const void* h, int S, uin
   if (v != SG_OK) return v;
   const Batch bt = make_batch(w, J, h, nullptr, N, N, 1, S, (int64_t)recs, cap);
 
-  HIP_TRY(launch_prep(isint, U, bt, st));
+  HIP_TRY(launch_prep(isint, bt, st));
   const int score_grid = std::max(1, w->cus) * 4;
   int kmax = 0, nmaxu = 0;
   w->ev_used = 0;
@@ -484,10 +484,16 @@ std::vector<Level> batch_levels(int Nmax, int S, int shift) {
 
 // Enqueue the batched search over bt (levels of batch_levels) and its
 // finalize into states_out / energies_out.
-sg_status batch_search(Workspace* w, bool isint, const Batch& bt, int Nmax, int ncap,
+sg_status batch_search(Workspace* w, bool isint, const Batch& bt0, int Nmax, int ncap,
                        uint64_t* states_out, void* energies_out, hipStream_t st) {
-  HIP_TRY(launch_prep(isint, kU, bt, st));
-  HIP_TRY(launch_tables(isint, kU, bt, ncap, st));
+  // levels whose lanes have n >= kUWide free spins walk blocks of kUWide,
+  // the others (n = kU) blocks of kU: the one record of n = kU comes first,
+  // then the records of kUWide for n = kUWide .. ncap
+  Batch bt = bt0;
+  bt.table_base8 = (int64_t)table_records(kU);
+  HIP_TRY(launch_prep(isint, bt, st));
+  HIP_TRY(launch_tables(isint, kU, bt, kU, st));
+  if (ncap >= kUWide) HIP_TRY(launch_tables(isint, kUWide, bt, ncap, st));
   const std::vector<Level> levels =
       batch_levels(Nmax, bt.S, batch_shift(bt.B, Nmax, bt.S, w->fill[isint ? 1 : 0]));
   w->ev_used = 0;
@@ -500,12 +506,13 @@ sg_status batch_search(Workspace* w, bool isint, const Batch& bt, int Nmax, int 
     ch.prefix_base = L.first >> L.n;
     ch.lanes = L.lanes;
     ch.n = L.n;
-    ch.table_offset = (1 << (L.n - kU)) - 1;
+    const int U = L.n >= kUWide ? kUWide : kU;
+    ch.table_offset = (U == kUWide ? (int)bt.table_base8 : 0) + (1 << (L.n - U)) - 1;
     const uint64_t lstates = (uint64_t)L.lanes << L.n;
     const int passes = lstates > (uint64_t)bt.cap ? 1 + kRetries : 1;
     for (int r = 0; r < passes; ++r) {
       ch.retry = r;
-      HIP_TRY(enum_timed(w, isint, kU, bt, ch, bt.B, st));
+      HIP_TRY(enum_timed(w, isint, U, bt, ch, bt.B, st));
       HIP_TRY(launch_merge_batched(isint, bt, L.first, r, r == passes - 1, st));
     }
     states += (double)lstates;
@@ -765,7 +772,7 @@ sg_status sg_density_of_states_i32(int N, const int32_t* J, const int32_t* h, lo
   if (v != SG_OK) return v;
   Batch bt = make_batch(w, J, h, nullptr, N, N, 1, 1, (int64_t)recs, 1);
   bt.allow_f32_walk = 0;  // the histogram walk reads integer tables
-  HIP_TRY(launch_prep(true, kU, bt, st));
+  HIP_TRY(launch_prep(true, bt, st));
   HIP_TRY(launch_dos_prologue(bt, e_min, n_bins, counts_out, st));
   w->ev_used = 0;
   w->last_launches = 0;

@@ -18,13 +18,18 @@
 
 namespace sg {
 
-// Low spins per search block: U = kU (2^7 = 128 steps) for batches and the
-// density of states, kUWide (2^8 = 256) for single searches of N >= 16,
-// whose per-block set-up is then spread over twice the states.
+// Low spins per search block: U = kUWide (2^8 = 256 steps) wherever a lane
+// has at least 8 free spins (single searches of N >= 16, batch levels of
+// n >= 8), which spreads the per-block set-up over twice the states of
+// U = kU (2^7 = 128 steps), the size taken otherwise and by the density of
+// states.
 constexpr int kU = 7;
 constexpr int kUWide = 8;
 constexpr int kBlockSteps = 1 << kU;
-constexpr int kQStride = 2 << kUWide;  // qtab words per instance (both block parities)
+// qtab words per instance: the tables of U = kU (both block parities), then
+// those of U = kUWide
+constexpr int kQStride = (2 << kU) + (2 << kUWide);
+constexpr int qtab_base(int U) { return U == kUWide ? (2 << kU) : 0; }
 constexpr int kMaxFree = 22;          // largest n (free spins per lane)
 constexpr int kMaxHigh = kMaxFree - kU;
 constexpr int kRecWords = 16;         // per-block table record (64 B: cB, R, Wu_0..U-1, U <= 14)
@@ -67,8 +72,8 @@ struct Params {
   uint64_t thr_mask;
   // instance-derived
   float margin;          // fp32 pruning margin (bound on incremental error)
-  float qmin_f;          // min over low configs of Q (rounded down)
-  int32_t qmin_i;
+  float qmin_f[2];       // min over low configs of Q (rounded down), [U == kUWide]
+  int32_t qmin_i[2];
   uint32_t err;          // sticky error bits
   // per-chunk counters
   uint32_t cand_count;   // candidates appended by the current chunk
@@ -106,6 +111,7 @@ struct Batch {
   uint32_t* qtab;      // [B][kQStride] low-low energies by block parity and step
   uint32_t* table;     // [B][table_recs][kRecWords]
   int64_t table_recs;
+  int64_t table_base8; // first record of the U = kUWide tables (search tables)
   uint64_t* cand;      // [B][cap] candidate masks
   uint32_t* ckey;      // [B][cap] orderable key of each candidate's walk energy
   uint32_t* skey;      // [B][cap]

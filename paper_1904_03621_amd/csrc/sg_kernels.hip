@@ -103,13 +103,43 @@ __device__ inline bool key_less(uint32_t ka, uint64_t ma, uint32_t kb, uint64_t 
 
 // ------------------------------------------------------------------ k_prep
 // One workgroup per instance.  Writes the Q tables (low-spin coupling energy
-// for both block parities), their minimum, the pruning margin, the error
-// flags and the initial (empty) record state.
+// for both block parities) of both block sizes and their minima, the pruning
+// margin, the error flags and the initial (empty) record state.
 
-template <bool kInt, int U>
-__global__ void k_prep(Batch bt) {
-  static_assert(2 << U <= kQStride, "Q tables exceed their stride");
+// Q(x) = -sum_{f<f'<U} J_ff' s_f s_f' over the low configuration
+// x = gray(i) ^ (par << (U-1)) of step i in a block of parity par, written to
+// qtab[par 2^U + i]; returns (to every thread) the minimum over both parities.
+template <bool kInt, int U, typename T>
+__device__ double prep_qtab(const T* Jb, int ld, int Nc, bool walk_f32, uint32_t* qtab,
+                            double* s_q) {
   constexpr int kSteps = 1 << U;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < 2 * kSteps; e += blockDim.x) {
+    const int par = e / kSteps, i = e % kSteps;
+    const uint32_t x = gray32((uint32_t)i) ^ ((uint32_t)par << (U - 1));
+    double q = 0.0;
+    for (int a = 0; a < U && a < Nc; ++a)
+      for (int c = a + 1; c < U && c < Nc; ++c) {
+        const double sa = ((x >> a) & 1u) ? 1.0 : -1.0, sc = ((x >> c) & 1u) ? 1.0 : -1.0;
+        q -= (double)Jb[a * ld + c] * sa * sc;
+      }
+    s_q[e] = q;
+    if (kInt && !walk_f32) qtab[e] = (uint32_t)(int32_t)q;
+    else qtab[e] = __float_as_uint((float)q);
+  }
+  __syncthreads();
+  static_assert(kSteps <= 256, "one thread per pair of the minimum's first round");
+  for (int st = kSteps; st > 0; st >>= 1) {
+    if (tid < st) s_q[tid] = fmin(s_q[tid], s_q[tid + st]);
+    __syncthreads();
+  }
+  const double m = s_q[0];
+  __syncthreads();  // s_q is reused
+  return m;
+}
+
+template <bool kInt>
+__global__ void k_prep(Batch bt) {
   const int b = blockIdx.x;
   const int N = inst_N(bt, b);
   const int ld = bt.ld;
@@ -174,30 +204,12 @@ __global__ void k_prep(Batch bt) {
   // where the walk is exact and, on this GPU, faster than in int32; its tables
   // then hold fp32 values.
   const bool walk_f32 = kInt && bt.allow_f32_walk && 2.1 * Bv < 16777216.0;
-  // Q tables: Q(x) = -sum_{f<f'<U} J_ff' s_f s_f' over the low configuration
-  // x = gray(i) ^ (par << (U-1)) of step i in a block of parity par.
-  __shared__ double s_q[2 * kSteps];
-  for (int e = tid; e < 2 * kSteps; e += blockDim.x) {
-    const int par = e / kSteps, i = e % kSteps;
-    const uint32_t x = gray32((uint32_t)i) ^ ((uint32_t)par << (U - 1));
-    double q = 0.0;
-    for (int a = 0; a < U && a < Nc; ++a)
-      for (int c = a + 1; c < U && c < Nc; ++c) {
-        const double sa = ((x >> a) & 1u) ? 1.0 : -1.0, sc = ((x >> c) & 1u) ? 1.0 : -1.0;
-        q -= (double)Jb[a * ld + c] * sa * sc;
-      }
-    s_q[e] = q;
-    if (kInt && !walk_f32) qtab[e] = (uint32_t)(int32_t)q;
-    else qtab[e] = __float_as_uint((float)q);
-  }
-  __syncthreads();
-  static_assert(kSteps <= 256, "one thread per pair of the minimum's first round");
-  for (int st = kSteps; st > 0; st >>= 1) {
-    if (tid < st) s_q[tid] = fmin(s_q[tid], s_q[tid + st]);
-    __syncthreads();
-  }
+  // Q tables of both block sizes and their minima
+  __shared__ double s_q[2 << kUWide];
+  const double qmin7 = prep_qtab<kInt, kU>(Jb, ld, Nc, walk_f32, qtab + qtab_base(kU), s_q);
+  const double qmin8 =
+      prep_qtab<kInt, kUWide>(Jb, ld, Nc, walk_f32, qtab + qtab_base(kUWide), s_q);
   if (tid == 0) {
-    const double qmin = s_q[0];
     uint32_t err = 0;
     if (badN) err |= kErrInval;
     if (anybad) err |= kErrNonFinite;
@@ -223,10 +235,11 @@ __global__ void k_prep(Batch bt) {
       const bool exact = Bv == 0.0 || (lsb_min < (1 << 19) && 2.1 * Bv < ldexp(1.0, 24 + lsb_min));
       if (!exact) {
         const double uH = H * 5.9604644775390625e-08;  // 2^-24
-        const double R = (double)(1 << (kReanchorLog2 - U));
-        const double rounds =
-            R * (kSteps - 1.0 + 3.0 * U + 3.0) + (kMaxFree + 3.0) + kMaxFree * 0.5 + 4.0 +
-            4.0;
+        // the larger count of the two block sizes (U = 7: 1208, U = 8: 1128)
+        double walk = 0.0;
+        for (int U = kU; U <= kUWide; ++U)
+          walk = fmax(walk, (double)(1 << (kReanchorLog2 - U)) * ((1 << U) - 1.0 + 3.0 * U + 3.0));
+        const double rounds = walk + (kMaxFree + 3.0) + kMaxFree * 0.5 + 4.0 + 4.0;
         margin = rounds * uH;
       }
     }
@@ -234,8 +247,10 @@ __global__ void k_prep(Batch bt) {
     P->rec_count = 0;
     P->thr_mask = ~0ull;
     P->margin = (float)margin;
-    P->qmin_f = f32_down(qmin);
-    P->qmin_i = (int32_t)qmin;
+    P->qmin_f[0] = f32_down(qmin7);
+    P->qmin_i[0] = (int32_t)qmin7;
+    P->qmin_f[1] = f32_down(qmin8);
+    P->qmin_i[1] = (int32_t)qmin8;
     P->err = err;
     P->cand_count = 0;
     P->surv_count = 0;
@@ -325,7 +340,9 @@ __global__ void k_tables(Batch bt, int ncap, void* out) {
     for (int f = 0; f < U; ++f) rec[2 + f] = wu[f];
     return;
   }
-  uint32_t* rec = bt.table + ((size_t)b * bt.table_recs + (size_t)r) * kRecWords;
+  // search tables of U = kUWide follow those of U = kU at record table_base8
+  const int64_t base = U == kUWide ? bt.table_base8 : 0;
+  uint32_t* rec = bt.table + ((size_t)b * bt.table_recs + (size_t)(base + r)) * kRecWords;
   if (kInt && !bt.P[b].walk_f32) {
     rec[0] = (uint32_t)(int32_t)cB;
     rec[1] = (uint32_t)(int32_t)R;
@@ -423,7 +440,8 @@ __device__ __forceinline__ void enum_walk(const Batch& bt, const void* __restric
   constexpr int kSteps = 1 << U;                            // steps per block
   constexpr int kReBlocks = 1 << (kReanchorLog2 - U);       // fp32: blocks per re-anchor
   V* s_y = (V*)s_yw;
-  const uint32_t* qtab = qtab_all + (size_t)b * kQStride;  // uniform: SGPRs
+  const uint32_t* qtab = qtab_all + (size_t)b * kQStride + qtab_base(U);  // uniform: SGPRs
+  constexpr int kQi = U == kUWide;  // this block size's Q minimum
 
   const int tid = threadIdx.x;
   const int ld = bt.ld;
@@ -570,7 +588,7 @@ __device__ __forceinline__ void enum_walk(const Batch& bt, const void* __restric
     // has a larger mask than the S-th entry, so a tie with it cannot enter
     if (full && ch.first_mask > thr_mask) t -= 1;
     thrE = (V)t;
-    fastThr = (V)(t - (int64_t)P->qmin_i);
+    fastThr = (V)(t - (int64_t)P->qmin_i[kQi]);
   } else {
     if (full) {
       const float tk = __uint_as_float(bits_of_f32_key(thr_key));
@@ -582,7 +600,7 @@ __device__ __forceinline__ void enum_walk(const Batch& bt, const void* __restric
         te = (ch.first_mask > thr_mask) ? nextafterf(tk, -__int_as_float(0x7f800000)) : tk;
       }
       thrE = (V)te;
-      fastThr = (V)f32_up((double)te - (double)P->qmin_f);
+      fastThr = (V)f32_up((double)te - (double)P->qmin_f[kQi]);
     } else {
       thrE = Num<V>::big();
       fastThr = Num<V>::big();
@@ -1127,21 +1145,15 @@ __global__ void k_finalize(Batch bt, uint64_t* states_out, void* energies_out) {
 
 // ---------------------------------------------------------------- launchers
 
-// U: low spins per block of the walk that follows (kU or kUWide)
-hipError_t launch_prep(bool isint, int U, const Batch& bt, hipStream_t st) {
-  if (U != kU && U != kUWide) return hipErrorInvalidValue;
-  if (isint) {
-    if (U == kU) hipLaunchKernelGGL((k_prep<true, kU>), dim3(bt.B), dim3(256), 0, st, bt);
-    else hipLaunchKernelGGL((k_prep<true, kUWide>), dim3(bt.B), dim3(256), 0, st, bt);
-  } else {
-    if (U == kU) hipLaunchKernelGGL((k_prep<false, kU>), dim3(bt.B), dim3(256), 0, st, bt);
-    else hipLaunchKernelGGL((k_prep<false, kUWide>), dim3(bt.B), dim3(256), 0, st, bt);
-  }
+hipError_t launch_prep(bool isint, const Batch& bt, hipStream_t st) {
+  if (isint) hipLaunchKernelGGL(k_prep<true>, dim3(bt.B), dim3(256), 0, st, bt);
+  else hipLaunchKernelGGL(k_prep<false>, dim3(bt.B), dim3(256), 0, st, bt);
   return hipGetLastError();
 }
 
+// records of n = U .. ncap (at table_base8 for U = kUWide)
 hipError_t launch_tables(bool isint, int U, const Batch& bt, int ncap, hipStream_t st) {
-  if (U != kU && U != kUWide) return hipErrorInvalidValue;
+  if ((U != kU && U != kUWide) || ncap < U) return hipErrorInvalidValue;
   const int64_t total = ((int64_t)1 << (ncap - U + 1)) - 1;  // search records
   const dim3 grid((unsigned)((total + 255) / 256), (unsigned)bt.B);
 #define SG_TABLES(I, UV) \

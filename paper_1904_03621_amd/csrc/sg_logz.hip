@@ -20,11 +20,12 @@
 // the block record and the field energy of the high spins (one fp64 update
 // per block, at most 2^H - 1 terms).
 //
-// Forward (kMode 0): the 64 weights of a block are an 8 x 8 contraction of
-// the factor products of spins 0-2 and 3-5 with bq; block sums are fp32, lane
-// totals fp64, one fp64 atomic per wave and beta.
+// Forward (kMode 0): the 2^U weights of a block are a 2^(U/2) x 2^(U/2)
+// contraction of the factor products of the lower and upper U/2 low spins
+// with bq (U = 8 when N >= 8: 16 x 16; else U = 6: 8 x 8); block sums are
+// fp32, lane totals fp64, one fp64 atomic per wave and beta.
 //
-// Backward (kMode 1): the gradient of sum_b g_b log Z(beta_b) needs, for every
+// Backward (kMode 1, U = 6): the gradient of sum_b g_b log Z(beta_b) needs, for every
 // pair and every spin, sum_s omega(s) s_i s_j and sum_s omega(s) s_i with the
 // combined weight omega = sum_b (g_b beta_b / Z_b) exp(-beta_b (E - E0)).
 // omega is formed for each of the 64 states of a block from the factors, and
