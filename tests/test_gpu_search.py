@@ -48,14 +48,16 @@ def test_listing1(orc, torch_dev):
     assert np.allclose(e, [-1.2, -0.8, 0.8, 1.2], atol=1e-6)
 
 
-@pytest.mark.parametrize("N", list(range(1, 13)) + [16])
+@pytest.mark.parametrize("N", list(range(1, 13)) + [15, 16, 17])
 def test_every_state_int(orc, torch_dev, N):
     J, h = I.random_int_dense(N, 100 + N)
     compare(orc, torch_dev, J, h, 1 << N, what="int N=%d all" % N)
 
 
-@pytest.mark.parametrize("N", [1, 3, 5, 6, 7, 9, 12, 14])
+@pytest.mark.parametrize("N", [1, 3, 5, 6, 7, 9, 12, 14, 15, 16, 17])
 def test_every_state_f32(orc, torch_dev, N):
+    """Every state returned in order; N = 15 walks blocks of 7 low spins,
+    N >= 16 blocks of 8."""
     J, h = I.random_f32_dense(N, 200 + N, j_scale=1.0, h_scale=0.3)
     compare(orc, torch_dev, J, h, 1 << N, what="f32 N=%d all" % N)
 
