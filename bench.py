@@ -34,8 +34,8 @@ COPY_BYTES = 512 << 20
 # (KiB per dispatch, averaged over the 447 dispatches of one search), scaled by
 # what the same counters read for the 512 MiB copy (fetch x2.0, write x1.0);
 # valid for the k_enum source with this SHA-256 prefix only
-TRAFFIC = {"kenum_sha256_16": "f85b85b4bc121b48", "fetch_kib": 1129982.0 / 447,
-           "write_kib": 41129.78125 / 447, "fetch_factor": 524288.0 / 262162.0, "write_factor": 1.0,
+TRAFFIC = {"kenum_sha256_16": "34361f53900017ab", "fetch_kib": 1131293.9375 / 447,
+           "write_kib": 41122.125 / 447, "fetch_factor": 524288.0 / 262162.0, "write_factor": 1.0,
            "profile": "profiles/k_enum_f32_dense48_counters.md"}
 
 

@@ -19,7 +19,7 @@
 namespace sg {
 hipError_t launch_prep(bool isint, const Batch& bt, hipStream_t st);
 hipError_t launch_tables(bool isint, int U, const Batch& bt, int ncap, hipStream_t st);
-hipError_t launch_enum(bool isint, int U, const Batch& bt, const Chunk& ch, int ninst,
+hipError_t launch_enum(bool isint, int U, bool split, const Batch& bt, const Chunk& ch, int ninst,
                        hipStream_t st);
 hipError_t launch_direct(const Batch& bt, uint64_t lo, uint64_t hi, hipStream_t st);
 hipError_t launch_score(bool isint, const Batch& bt, int b, int grid, int N, int retry,
@@ -341,8 +341,9 @@ sg_status validate(int N, const void* J, const void* h, int S, uint64_t lo, uint
   return SG_OK;
 }
 
-hipError_t enum_timed(Workspace* w, bool isint, int U, const Batch& bt, const Chunk& ch,
-                      int ninst, hipStream_t st) {
+// split: test the walk's bound per 64-step sub-block (batched searches)
+hipError_t enum_timed(Workspace* w, bool isint, int U, bool split, const Batch& bt,
+                      const Chunk& ch, int ninst, hipStream_t st) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (g_timing) {
     hipError_t r = ws_event_pair(w, &e0, &e1);
@@ -350,7 +351,7 @@ hipError_t enum_timed(Workspace* w, bool isint, int U, const Batch& bt, const Ch
     r = hipEventRecord(e0, st);
     if (r != hipSuccess) return r;
   }
-  hipError_t r = launch_enum(isint, U, bt, ch, ninst, st);
+  hipError_t r = launch_enum(isint, U, split, bt, ch, ninst, st);
   if (r != hipSuccess) return r;
   ++w->last_launches;
   if (g_timing) r = hipEventRecord(e1, st);
@@ -402,7 +403,7 @@ sg_status run_search(bool isint, int N, const void* J, const void* h, int S, uin
     const int passes = cstates > (uint64_t)cap ? 1 + kRetries : 1;
     for (int r = 0; r < passes; ++r) {
       ch.retry = r;
-      HIP_TRY(enum_timed(w, isint, U, bt, ch, 1, st));
+      HIP_TRY(enum_timed(w, isint, U, false, bt, ch, 1, st));
       HIP_TRY(launch_score(isint, bt, 0, score_grid, N, r, st));
       HIP_TRY(launch_merge(bt, 0, r, r == passes - 1, st));
     }
@@ -512,7 +513,7 @@ sg_status batch_search(Workspace* w, bool isint, const Batch& bt0, int Nmax, int
     const int passes = lstates > (uint64_t)bt.cap ? 1 + kRetries : 1;
     for (int r = 0; r < passes; ++r) {
       ch.retry = r;
-      HIP_TRY(enum_timed(w, isint, U, bt, ch, bt.B, st));
+      HIP_TRY(enum_timed(w, isint, U, true, bt, ch, bt.B, st));
       HIP_TRY(launch_merge_batched(isint, bt, L.first, r, r == passes - 1, st));
     }
     states += (double)lstates;

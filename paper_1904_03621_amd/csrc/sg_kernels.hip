@@ -378,7 +378,7 @@ struct Num<int32_t> {
   static __device__ inline int32_t big() { return 1 << 29; }
 };
 
-template <bool kInt, bool kWF, int U>
+template <bool kInt, bool kWF, int U, bool kSplit>
 __device__ __forceinline__ void enum_walk(const Batch& bt, const void* __restrict__ Jv,
                                           const void* __restrict__ hv,
                                           const uint32_t* __restrict__ table,
@@ -386,8 +386,10 @@ __device__ __forceinline__ void enum_walk(const Batch& bt, const void* __restric
                                           int b, int blk, int N, int n, int64_t lanes, Params* P,
                                           uint32_t* s_yw, void* s_Fw, void* s_Rw, void* s_EHw);
 
-// U: low spins per block (kU or kUWide; n >= U for every chunk)
-template <bool kInt, int U>
+// U: low spins per block (kU or kUWide; n >= U for every chunk).  kSplit: the
+// bound is tested per sub-block of 64 steps instead of per block (batches,
+// whose short levels bring many candidates per state).
+template <bool kInt, int U, bool kSplit>
 __global__ __launch_bounds__(kEnumBlock, 8) void k_enum(Batch bt, const void* __restrict__ Jv,
                                                         const void* __restrict__ hv,
                                                         const uint32_t* __restrict__ table,
@@ -416,17 +418,17 @@ __global__ __launch_bounds__(kEnumBlock, 8) void k_enum(Batch bt, const void* __
   __shared__ A s_R[2][kMaxN];
   __shared__ A s_EH[2];
   if (kInt && P->walk_f32)
-    enum_walk<true, true, U>(bt, Jv, hv, table, qtab_all, ch, b, blk, N, n, lanes, P, s_y, s_F,
-                             s_R, s_EH);
+    enum_walk<true, true, U, kSplit>(bt, Jv, hv, table, qtab_all, ch, b, blk, N, n, lanes, P,
+                                     s_y, s_F, s_R, s_EH);
   else
-    enum_walk<kInt, !kInt, U>(bt, Jv, hv, table, qtab_all, ch, b, blk, N, n, lanes, P, s_y, s_F,
-                              s_R, s_EH);
+    enum_walk<kInt, !kInt, U, kSplit>(bt, Jv, hv, table, qtab_all, ch, b, blk, N, n, lanes, P,
+                                      s_y, s_F, s_R, s_EH);
 }
 
 // The walk of k_enum.  kInt: the instance is int32 (exact set-up in int64,
 // integer keys); kWF: the walk runs in fp32 (fp32 instances, and integer ones
 // whose values fit 24 bits, whose tables then hold fp32 values).
-template <bool kInt, bool kWF, int U>
+template <bool kInt, bool kWF, int U, bool kSplit>
 __device__ __forceinline__ void enum_walk(const Batch& bt, const void* __restrict__ Jv,
                                           const void* __restrict__ hv,
                                           const uint32_t* __restrict__ table,
@@ -649,8 +651,18 @@ __device__ __forceinline__ void enum_walk(const Batch& bt, const void* __restric
     for (int f = 0; f < U - 1; ++f) W[f] = WL[f] + rw[2 + f];
     W[U - 1] = ((T & 1u) ? WL[U - 1] : -WL[U - 1]) + rw[2 + U - 1];
 
-    // 2^U - 1 inner steps: one add per state, one 3-input min per two states
-    const V Gs = G;
+    // 2^U - 1 inner steps: one add per state, one 3-input min per two states.
+    // With kSplit the minimum is kept per sub-block of 64 steps, and G at
+    // every sub-block start, so that a block whose bound passes re-walks only
+    // the sub-blocks that can hold a state below the threshold (a few more
+    // instructions per block, far fewer re-walked states where candidates
+    // are frequent); without it the block is one sub-block.
+    constexpr int kSub = kSplit ? 64 : kSteps;
+    constexpr int kNSub = kSteps / kSub;
+    constexpr int kHitWords = kSteps / 64;  // hit masks: one bit per state
+    static_assert(kSteps % kSub == 0 && kSub % 64 == 0, "sub-blocks of whole hit words");
+    V msub[kNSub], gsub[kNSub];
+    gsub[0] = G;
     V m = G;
 #pragma unroll
     for (int i = 1; i < kSteps; i += 2) {
@@ -661,41 +673,60 @@ __device__ __forceinline__ void enum_walk(const Batch& bt, const void* __restric
         const int f = __builtin_ctz(i + 1);
         if (f == U - 1) G = G + W[f];
         else G = (((i + 1) >> (f + 1)) & 1) ? G + W[f] : G - W[f];
-        m = Num<V>::mn(Num<V>::mn(m, Ga), G);
+        if ((i + 1) % kSub == 0) {
+          // step i closes sub-block (i + 1) / kSub - 1; step i + 1 opens the next
+          msub[(i + 1) / kSub - 1] = Num<V>::mn(m, Ga);
+          gsub[(i + 1) / kSub] = G;
+          m = G;
+        } else {
+          m = Num<V>::mn(Num<V>::mn(m, Ga), G);
+        }
       } else {
-        m = Num<V>::mn(m, Ga);
+        msub[kNSub - 1] = Num<V>::mn(m, Ga);
       }
     }
 
-    const bool pass = m <= fastThr;
-    if (__ballot(pass) != 0ull) {
-      // re-walk of this block, testing every state, for the lanes whose
-      // bound passed; the opaque copy keeps the compiler from holding the
-      // values of the fast walk live across the branch
+    bool pass[kNSub];
+    bool any = false;
+#pragma unroll
+    for (int w = 0; w < kNSub; ++w) {
+      pass[w] = msub[w] <= fastThr;
+      any = any || pass[w];
+    }
+    if (__ballot(any) != 0ull) {
+      // re-walk, testing every state, of the sub-blocks whose bound passed in
+      // some lane; the opaque copies keep the compiler from holding the values
+      // of the fast walk live across the branch
       ++slow;
       const uint32_t* q = qtab + (T & 1u) * kSteps;
-      V g2 = Gs;
-      asm volatile("" : "+v"(g2));
-      constexpr int kHitWords = kSteps / 64;
+      const V Gs = gsub[0];
       uint64_t hits[kHitWords];
 #pragma unroll
-      for (int w = 0; w < kHitWords; ++w) hits[w] = 0ull;
+      for (int k = 0; k < kHitWords; ++k) hits[k] = 0ull;
       auto qv = [&](int i) -> V { return kWF ? (V)__uint_as_float(q[i]) : (V)(int32_t)q[i]; };
-      if (g2 + qv(0) <= thrE) hits[0] |= 1ull;
 #pragma unroll
-      for (int i = 1; i < kSteps; ++i) {
-        const int f = __builtin_ctz(i);
-        if (f == U - 1) g2 = g2 + W[f];
-        else g2 = ((i >> (f + 1)) & 1) ? g2 + W[f] : g2 - W[f];
-        if (g2 + qv(i) <= thrE) hits[i >> 6] |= (1ull << (i & 63));
+      for (int w = 0; w < kNSub; ++w) {
+        if (kSplit && __ballot(pass[w]) == 0ull) continue;  // wave-uniform
+        V g2 = gsub[w];
+        asm volatile("" : "+v"(g2));
+        if (g2 + qv(kSub * w) <= thrE) hits[(kSub * w) >> 6] |= 1ull;
+#pragma unroll
+        for (int j = 1; j < kSub; ++j) {
+          const int i = kSub * w + j;
+          const int f = __builtin_ctz(i);
+          if (f == U - 1) g2 = g2 + W[f];
+          else g2 = ((i >> (f + 1)) & 1) ? g2 + W[f] : g2 - W[f];
+          if (g2 + qv(i) <= thrE) hits[i >> 6] |= (1ull << (i & 63));
+        }
+        if (!(valid && pass[w])) {
+#pragma unroll
+          for (int k = 0; k < kSub / 64; ++k) hits[(kSub * w) / 64 + k] = 0ull;
+        }
       }
       // one slot reservation for all hits of the wave: an exclusive scan of
       // the lanes' hit counts, one atomic, then every lane writes its own
       // hits from its offset (the atomic's latency is paid once per block,
       // not once per step that hits)
-#pragma unroll
-      for (int w = 0; w < kHitWords; ++w)
-        if (!(valid && pass)) hits[w] = 0ull;
       uint32_t nh = 0;
 #pragma unroll
       for (int w = 0; w < kHitWords; ++w) nh += (uint32_t)__popcll(hits[w]);
@@ -1181,21 +1212,26 @@ hipError_t launch_tables64(const Batch& bt, int ncap, int U, double* out, hipStr
   return hipGetLastError();
 }
 
-hipError_t launch_enum(bool isint, int U, const Batch& bt, const Chunk& ch, int ninst,
+// split: test the bound per 64-step sub-block (batched searches)
+hipError_t launch_enum(bool isint, int U, bool split, const Batch& bt, const Chunk& ch, int ninst,
                        hipStream_t st) {
   if ((U != kU && U != kUWide) || ch.n < U) return hipErrorInvalidValue;
   const int bpi = (int)((ch.lanes + kEnumBlock - 1) / kEnumBlock);
   const dim3 grid((unsigned)((int64_t)bpi * ninst));
-#define SG_ENUM(I, UV)                                                                     \
-  hipLaunchKernelGGL((k_enum<I, UV>), grid, dim3(kEnumBlock), 0, st, bt, bt.J, bt.h,      \
+#define SG_ENUM(I, UV, SP)                                                                 \
+  hipLaunchKernelGGL((k_enum<I, UV, SP>), grid, dim3(kEnumBlock), 0, st, bt, bt.J, bt.h,  \
                      (const uint32_t*)bt.table, (const uint32_t*)bt.qtab, ch, bpi)
+#define SG_ENUM_U(I, SP)          \
+  if (U == kU) SG_ENUM(I, kU, SP); \
+  else SG_ENUM(I, kUWide, SP)
   if (isint) {
-    if (U == kU) SG_ENUM(true, kU);
-    else SG_ENUM(true, kUWide);
+    if (split) SG_ENUM_U(true, true);
+    else SG_ENUM_U(true, false);
   } else {
-    if (U == kU) SG_ENUM(false, kU);
-    else SG_ENUM(false, kUWide);
+    if (split) SG_ENUM_U(false, true);
+    else SG_ENUM_U(false, false);
   }
+#undef SG_ENUM_U
 #undef SG_ENUM
   return hipGetLastError();
 }
@@ -1241,18 +1277,25 @@ hipError_t launch_finalize(bool isint, const Batch& bt, uint64_t* states_out, vo
   return hipGetLastError();
 }
 
-// resident workgroups per CU of the walk (the smaller of the two block sizes)
+// resident workgroups per CU of the walk (the smallest over its variants)
+template <bool I>
+int enum_occupancy_t() {
+  int best = 1 << 30;
+  auto take = [&](const void* f) {
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, f, kEnumBlock, 0) != hipSuccess)
+      blocks = 0;
+    best = blocks < best ? blocks : best;
+  };
+  take((const void*)k_enum<I, kU, false>);
+  take((const void*)k_enum<I, kUWide, false>);
+  take((const void*)k_enum<I, kU, true>);
+  take((const void*)k_enum<I, kUWide, true>);
+  return best;
+}
+
 int enum_occupancy(bool isint) {
-  int b7 = 0, b8 = 0;
-  hipError_t e7, e8;
-  if (isint) {
-    e7 = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b7, k_enum<true, kU>, kEnumBlock, 0);
-    e8 = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b8, k_enum<true, kUWide>, kEnumBlock, 0);
-  } else {
-    e7 = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b7, k_enum<false, kU>, kEnumBlock, 0);
-    e8 = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b8, k_enum<false, kUWide>, kEnumBlock, 0);
-  }
-  return e7 == hipSuccess && e8 == hipSuccess ? (b7 < b8 ? b7 : b8) : 0;
+  return isint ? enum_occupancy_t<true>() : enum_occupancy_t<false>();
 }
 
 }  // namespace sg
