@@ -457,7 +457,7 @@ int batch_shift(int B, int Nmax, int S, int64_t fill) {
 // [first 2^(j-1), first 2^j),
 // so every level is as large as everything before it and brings about S
 // candidates.  All instances with states in a level run it in the same launch,
-// with the same geometry: n = clamp(log2(size) - shift, U, 17) free spins per
+// with the same geometry: n = clamp(log2(size) - shift, kU, kBatchFreeCap) free spins per
 // lane.
 constexpr uint64_t kBatchLevel0 = 4096;  // smallest level 0 (<= half of any instance's slots)
 struct Level {

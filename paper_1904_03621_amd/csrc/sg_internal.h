@@ -46,7 +46,7 @@ constexpr int kWaveLanes = 64;
 constexpr int kEnumBlock = 256;       // threads per enumeration workgroup
 constexpr int kMergeThreads = 1024;   // threads of the single-workgroup merge
 constexpr int kMergeBatchThreads = 256;  // threads per instance in the batched merge
-constexpr int kBatchFreeCap = 17;     // largest n of a batched search
+constexpr int kBatchFreeCap = 16;     // largest n of a batched search
 constexpr int kLdsSortCap = 4096;     // survivors sorted in LDS up to this
 constexpr int kLdsSortCapBatch = 1024;  // the same for the per-instance batched merge
 constexpr int kRankByCount = 512;     // merges of up to this many entries rank by counting
