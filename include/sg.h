@@ -31,6 +31,13 @@
  *     exit.  Calls on one stream are ordered; calls on different streams use
  *     different workspaces and may run concurrently.  Two host threads must
  *     not issue calls on the same stream at the same time.
+ *   - Graph capture: a call enqueued while its stream captures a HIP graph
+ *     allocates nothing; if the workspace is too small for it the call
+ *     returns SG_EINVAL (size it first with sg_reserve or one eager call of
+ *     the same shape).  From the first sg_reserve or captured call on, the
+ *     workspace never frees a buffer: a later, larger eager call allocates
+ *     new ones and keeps the old ones (which captured graphs still use)
+ *     until the process ends.
  *   - SG_ECAPACITY: a chunk whose candidates overflow the buffer is walked
  *     again (up to two more times) with the threshold its partial merge
  *     tightened; the error is reported only if the last pass still
@@ -78,7 +85,7 @@ typedef enum {
  *   energies_out device float[S]   energies of those states
  *
  * The enumeration accumulates energies incrementally in fp32 with a
- * from-scratch re-anchor every 2^16 Gray-code flips, prunes with a margin
+ * from-scratch re-anchor every 2^10 Gray-code flips, prunes with a margin
  * that bounds the accumulated rounding, and rescores every surviving
  * candidate from scratch in fp64; the returned energies are those fp64
  * values rounded to fp32 (-0 is returned as +0).
@@ -256,7 +263,9 @@ sg_status sg_energy_bound_i32(int N, const int32_t *J, const int32_t *h, long lo
  * batched and log Z calls).  Calls within those limits then allocate nothing,
  * so they can be captured into a HIP graph.  Synchronous; returns SG_EINVAL
  * for out-of-range limits and SG_ENOMEM / SG_EHIP if allocation fails.  The
- * workspace is owned by the library and lives until the process ends.
+ * workspace is owned by the library and lives until the process ends; once
+ * reserved it keeps every buffer a captured graph may use (see "Graph
+ * capture" above).
  */
 sg_status sg_reserve(int B_max, int N_max, int S_max, void *stream);
 
@@ -318,6 +327,35 @@ void sg_set_kernel_timing(int enable);
  * rate.
  */
 double sg_probe_valu(int op, int waves_per_simd);
+
+/*
+ * Test hooks (not compute calls).  They change how later calls lay out their
+ * work, never what a correct call computes, so that instances small enough
+ * for the CPU oracle can run the code paths of the large workloads.
+ *
+ * sg_debug_set_fill: the number of resident lanes the work plans of
+ * (current device, stream) assume (lanes >= 1; 0 restores the device's own
+ * value).  The single search, the density of states and log Z give each lane
+ * more free spins when there are fewer lanes to fill: with lanes = 4 a search
+ * of N = 24 walks up to 2^21 states per lane (block boundaries, high-spin
+ * fields, fp32 re-anchors), and a log Z batch of one N = 20 instance runs 14
+ * free spins per lane at lanes = 64.
+ *
+ * sg_debug_set_margin_scale: multiplies the fp32 pruning margin of later
+ * searches on (current device, stream) by scale, 0 < scale <= 1 (1
+ * restores).  Below 1 the margin may no longer bound the walk's rounding:
+ * results may then be wrong, and the drift guard reports SG_EDRIFT through
+ * sg_get_error once a measured drift exceeds the scaled margin.  Every kernel
+ * still runs to its end.
+ *
+ * sg_debug_set_batch_shift: the level shift of batched calls with this (B,
+ * N_max, S) on the current device, as sg_tune_batched_f32 would set it
+ * (0 <= shift <= 40; shift < 0 restores the default).  A small shift gives
+ * the lanes of a small batch up to 16 free spins.
+ */
+sg_status sg_debug_set_fill(void *stream, long long lanes);
+sg_status sg_debug_set_margin_scale(void *stream, double scale);
+sg_status sg_debug_set_batch_shift(int B, int N_max, int S, int shift);
 
 /*
  * Test hook (not a compute call): the chunk plan the library would use for a

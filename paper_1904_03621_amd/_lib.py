@@ -35,6 +35,7 @@ EXPORTS = [
     "sg_low_spectrum_qubo_f32",
     "sg_get_error", "sg_last_error", "sg_get_run_info", "sg_debug_plan",
     "sg_set_kernel_timing", "sg_probe_valu",
+    "sg_debug_set_fill", "sg_debug_set_margin_scale", "sg_debug_set_batch_shift",
 ]
 PROBE_OPS = {"v_add_f32": 0, "v_min3_f32": 1, "v_add_u32": 2, "v_min3_i32": 3, "v_fma_f32": 4,
              "v_min_f32": 5, "v_or_b32": 6, "v_or3_b32": 7, "v_add3_u32": 8, "v_max3_f32": 9,
@@ -117,6 +118,12 @@ def lib() -> ctypes.CDLL:
         L.sg_probe_valu.argtypes = [i32, i32]
         L.sg_set_kernel_timing.restype = None
         L.sg_set_kernel_timing.argtypes = [i32]
+        L.sg_debug_set_fill.restype = i32
+        L.sg_debug_set_fill.argtypes = [vp, ctypes.c_longlong]
+        L.sg_debug_set_margin_scale.restype = i32
+        L.sg_debug_set_margin_scale.argtypes = [vp, ctypes.c_double]
+        L.sg_debug_set_batch_shift.restype = i32
+        L.sg_debug_set_batch_shift.argtypes = [i32, i32, i32, i32]
         L.sg_debug_plan.restype = i32
         L.sg_debug_plan.argtypes = [i32, i32, u64, u64, ctypes.c_int64,
                                     ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_int32),
@@ -238,6 +245,18 @@ def sg_probe_valu(op, waves_per_simd: int = 8) -> float:
     """Measured lane-instructions/s of one VALU instruction kind (name or code)."""
     code = PROBE_OPS[op] if isinstance(op, str) else int(op)
     return float(lib().sg_probe_valu(code, waves_per_simd))
+
+
+def sg_debug_set_fill(lanes: int, stream=None) -> int:
+    return lib().sg_debug_set_fill(_stream(stream), int(lanes))
+
+
+def sg_debug_set_margin_scale(scale: float, stream=None) -> int:
+    return lib().sg_debug_set_margin_scale(_stream(stream), float(scale))
+
+
+def sg_debug_set_batch_shift(B: int, N_max: int, S: int, shift: int) -> int:
+    return lib().sg_debug_set_batch_shift(B, N_max, S, shift)
 
 
 def sg_debug_plan(N, S, lo, hi, lanes_fill, cap=100000):

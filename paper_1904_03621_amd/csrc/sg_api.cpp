@@ -99,7 +99,7 @@ struct PlanChunk {
 std::vector<PlanChunk> plan_chunks(int N, int S, uint64_t lo, uint64_t hi, int64_t fill, int U) {
   std::vector<PlanChunk> out;
   const int nmax = std::min(kMaxFree, N);
-  if (fill < kWaveLanes) fill = kWaveLanes;
+  if (fill < 1) fill = 1;
   const int fill_log = ilog2_floor((uint64_t)fill);
   uint64_t target = 4096;
   while (target < (uint64_t)S) target <<= 1;
@@ -145,9 +145,17 @@ std::vector<PlanChunk> plan_chunks(int N, int S, uint64_t lo, uint64_t hi, int64
 
 // Device buffers of one (device, stream).  Each buffer only grows; growing
 // frees the old allocation (hipFree waits for the device), so it never races
-// work that earlier calls enqueued.
+// work that earlier calls enqueued.  Once the workspace is pinned (by
+// sg_reserve, or by a call made while its stream was capturing a graph), a
+// graph may hold its buffers: growing then keeps the old allocation alive
+// (retired, released at process exit) instead of freeing it, and a call
+// under capture that would need to grow is refused.
 struct Workspace {
   int device = -1;
+  bool fixed = false;              // the no-alloc entry point's view of its static buffer
+  bool pinned = false;
+  bool capturing = false;          // set by ws_get for the call in progress
+  std::vector<void*> retired;
   uint32_t* sticky = nullptr;
   Params* P = nullptr;
   size_t nP = 0;
@@ -185,7 +193,9 @@ struct Workspace {
   size_t nlz_acc = 0;
   double* lz_coef = nullptr;
   size_t nlz_coef = 0;
-  int64_t fill[2] = {0, 0};
+  int64_t fill[2] = {0, 0};      // resident lanes of the walk (fp32, int32)
+  int64_t fill_dev[2] = {0, 0};  // the device's values (fill differs only under a test hook)
+  float margin_scale = 1.0f;     // test hook: factor on the fp32 pruning margin
   int cus = 0;
   // last run
   int64_t last_chunks = 0;
@@ -219,12 +229,21 @@ constexpr uint32_t kCandCapMin = 1u << 22;     // single search
 constexpr uint32_t kBatchCandCapMin = 1u << 13;  // per instance of a batch
 constexpr uint64_t kBatchCandBudget = 1ull << 24;  // slots over the whole batch
 
+// A call under graph capture that needs a larger buffer: no allocation may be
+// enqueued into the graph, and the buffers a replay would use must not move.
+constexpr hipError_t kGrowUnderCapture = hipErrorStreamCaptureUnsupported;
+
 template <typename T>
-hipError_t grow(T** p, size_t* have, size_t need) {
+hipError_t grow(Workspace* w, T** p, size_t* have, size_t need) {
   if (*have >= need) return hipSuccess;
+  if (w->capturing) return kGrowUnderCapture;
   if (*p) {
-    hipError_t e = hipFree(*p);
-    if (e != hipSuccess) return e;
+    if (w->pinned) {
+      w->retired.push_back((void*)*p);  // a captured graph may still use it
+    } else {
+      hipError_t e = hipFree(*p);
+      if (e != hipSuccess) return e;
+    }
     *p = nullptr;
     *have = 0;
   }
@@ -233,7 +252,20 @@ hipError_t grow(T** p, size_t* have, size_t need) {
   return e;
 }
 
-sg_status ws_create(int dev, Workspace* w) {
+// HIP_TRY for workspace growth: a refusal under capture gets its own message.
+#define GROW_TRY(expr)                                                                \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ == kGrowUnderCapture)                                                      \
+      return fail(SG_EINVAL,                                                          \
+                  "the stream is capturing a graph and the workspace is too small for " \
+                  "this call: call sg_reserve (or run one call of this shape) first"); \
+    if (e_ != hipSuccess)                                                             \
+      return fail(SG_ENOMEM, std::string(#expr ": ") + hipGetErrorString(e_));       \
+  } while (0)
+
+// The device's compute units and resident lanes (allocates nothing).
+sg_status ws_describe(int dev, Workspace* w) {
   w->device = dev;
   hipDeviceProp_t prop;
   HIP_TRY(hipGetDeviceProperties(&prop, dev));
@@ -243,8 +275,14 @@ sg_status ws_create(int dev, Workspace* w) {
   w->cus = prop.multiProcessorCount;
   for (int k = 0; k < 2; ++k) {
     const int occ = enum_occupancy(k == 1);
-    w->fill[k] = (int64_t)w->cus * std::max(occ, 1) * kEnumBlock;
+    w->fill[k] = w->fill_dev[k] = (int64_t)w->cus * std::max(occ, 1) * kEnumBlock;
   }
+  return SG_OK;
+}
+
+sg_status ws_create(int dev, Workspace* w) {
+  const sg_status v = ws_describe(dev, w);
+  if (v != SG_OK) return v;
   HIP_TRY(hipMalloc(&w->sticky, sizeof(uint32_t)));
   HIP_TRY(hipMemset(w->sticky, 0, sizeof(uint32_t)));
   return SG_OK;
@@ -272,23 +310,31 @@ sg_status ws_get(hipStream_t st, int B, size_t recs, size_t cap, int S, Workspac
     }
     g_ws[key] = w;
   }
+  // a call enqueued while the stream captures a graph pins the workspace
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) != hipSuccess) {
+    (void)hipGetLastError();  // not a capture query this stream supports
+    cs = hipStreamCaptureStatusNone;
+  }
+  w->capturing = cs == hipStreamCaptureStatusActive;
+  if (w->capturing) w->pinned = true;
   const size_t Bz = (size_t)B;
-  HIP_TRY(grow(&w->P, &w->nP, Bz));
-  HIP_TRY(grow(&w->qtab, &w->nq, Bz * kQStride));
-  HIP_TRY(grow(&w->table, &w->ntable, Bz * recs * kRecWords));
+  GROW_TRY(grow(w, &w->P, &w->nP, Bz));
+  GROW_TRY(grow(w, &w->qtab, &w->nq, Bz * kQStride));
+  GROW_TRY(grow(w, &w->table, &w->ntable, Bz * recs * kRecWords));
   if (w->ncand < Bz * cap) {
     size_t have_s = w->ncand, have_m = w->ncand, have_c = w->ncand;
-    HIP_TRY(grow(&w->cand, &w->ncand, Bz * cap));
-    HIP_TRY(grow(&w->ckey, &have_c, Bz * cap));
-    HIP_TRY(grow(&w->skey, &have_s, Bz * cap));
-    HIP_TRY(grow(&w->smask, &have_m, Bz * cap));
+    GROW_TRY(grow(w, &w->cand, &w->ncand, Bz * cap));
+    GROW_TRY(grow(w, &w->ckey, &have_c, Bz * cap));
+    GROW_TRY(grow(w, &w->skey, &have_s, Bz * cap));
+    GROW_TRY(grow(w, &w->smask, &have_m, Bz * cap));
   }
   if (w->nrec < Bz * (size_t)S) {
     size_t h1 = w->nrec, h2 = w->nrec, h3 = w->nrec;
-    HIP_TRY(grow(&w->rkey, &w->nrec, Bz * S));
-    HIP_TRY(grow(&w->rmask, &h1, Bz * S));
-    HIP_TRY(grow(&w->tkey, &h2, Bz * S));
-    HIP_TRY(grow(&w->tmask, &h3, Bz * S));
+    GROW_TRY(grow(w, &w->rkey, &w->nrec, Bz * S));
+    GROW_TRY(grow(w, &w->rmask, &h1, Bz * S));
+    GROW_TRY(grow(w, &w->tkey, &h2, Bz * S));
+    GROW_TRY(grow(w, &w->tmask, &h3, Bz * S));
   }
   *out = w;
   return SG_OK;
@@ -319,6 +365,7 @@ Batch make_batch(Workspace* w, const void* J, const void* h, const int32_t* Ns, 
   bt.tmask = w->tmask;
   bt.sticky = w->sticky;
   bt.allow_f32_walk = 1;
+  bt.margin_scale = w->margin_scale;
   return bt;
 }
 
@@ -345,7 +392,8 @@ sg_status validate(int N, const void* J, const void* h, int S, uint64_t lo, uint
 hipError_t enum_timed(Workspace* w, bool isint, int U, bool split, const Batch& bt,
                       const Chunk& ch, int ninst, hipStream_t st) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (g_timing) {
+  const bool timed = g_timing && !w->fixed;  // the no-alloc path creates no events
+  if (timed) {
     hipError_t r = ws_event_pair(w, &e0, &e1);
     if (r != hipSuccess) return r;
     r = hipEventRecord(e0, st);
@@ -354,24 +402,17 @@ hipError_t enum_timed(Workspace* w, bool isint, int U, bool split, const Batch& 
   hipError_t r = launch_enum(isint, U, split, bt, ch, ninst, st);
   if (r != hipSuccess) return r;
   ++w->last_launches;
-  if (g_timing) r = hipEventRecord(e1, st);
+  if (timed) r = hipEventRecord(e1, st);
   return r;
 }
 
-sg_status run_search(bool isint, int N, const void* J, const void* h, int S, uint64_t lo,
-                     uint64_t hi, uint64_t* states_out, void* energies_out, void* stream) {
-  g_last_error.clear();
-  sg_status v = validate(N, J, h, S, lo, hi, states_out, energies_out);
-  if (v != SG_OK) return v;
-  hipStream_t st = (hipStream_t)stream;
-  uint32_t cap = kCandCapMin;
-  while (cap < 8u * (uint32_t)S) cap <<= 1;
+// Enqueue the search of [lo, hi) on workspace w, whose buffers hold `recs`
+// table records, `cap` candidate slots and S record entries.
+sg_status search_on(Workspace* w, bool isint, int N, const void* J, const void* h, int S,
+                    uint64_t lo, uint64_t hi, size_t recs, uint32_t cap, uint64_t* states_out,
+                    void* energies_out, hipStream_t st) {
   const int U = search_block(N);
   const int ncap = std::min(kMaxFree, std::max(N, U));
-  const size_t recs = table_records(kMaxFree);  // blocks of kU outnumber those of kUWide
-  Workspace* w = nullptr;
-  v = ws_get(st, 1, recs, cap, S, &w);
-  if (v != SG_OK) return v;
   const Batch bt = make_batch(w, J, h, nullptr, N, N, 1, S, (int64_t)recs, cap);
 
   HIP_TRY(launch_prep(isint, bt, st));
@@ -418,6 +459,21 @@ sg_status run_search(bool isint, int N, const void* J, const void* h, int S, uin
   w->last_kmax = kmax;
   w->last_nmax = nmaxu;
   return SG_OK;
+}
+
+sg_status run_search(bool isint, int N, const void* J, const void* h, int S, uint64_t lo,
+                     uint64_t hi, uint64_t* states_out, void* energies_out, void* stream) {
+  g_last_error.clear();
+  sg_status v = validate(N, J, h, S, lo, hi, states_out, energies_out);
+  if (v != SG_OK) return v;
+  hipStream_t st = (hipStream_t)stream;
+  uint32_t cap = kCandCapMin;
+  while (cap < 8u * (uint32_t)S) cap <<= 1;
+  const size_t recs = table_records(kMaxFree);  // blocks of kU outnumber those of kUWide
+  Workspace* w = nullptr;
+  v = ws_get(st, 1, recs, cap, S, &w);
+  if (v != SG_OK) return v;
+  return search_on(w, isint, N, J, h, S, lo, hi, recs, cap, states_out, energies_out, st);
 }
 
 // Level geometry of the batched search: n = log2(level size) - shift free
@@ -570,12 +626,12 @@ sg_status lz_buffers(Workspace* w, int B, int N) {
   const size_t Bz = (size_t)B;
   const size_t stride = std::max<size_t>(kMaxBeta, (size_t)N * N + N);
   // records of U = kLzU outnumber (and outsize) those of U = kLzUF
-  HIP_TRY(grow(&w->table64, &w->ntable64,
-               Bz * lz_table_records(std::min(kLzFree, N), kLzU) * (2 + kLzUF)));
-  HIP_TRY(grow(&w->lzq, &w->nlzq, Bz * kMaxBeta * kLzQStride));
-  HIP_TRY(grow(&w->lzqmin, &w->nlzqmin, Bz));
-  HIP_TRY(grow(&w->lz_acc, &w->nlz_acc, Bz * stride));
-  HIP_TRY(grow(&w->lz_coef, &w->nlz_coef, Bz * kMaxBeta));
+  GROW_TRY(grow(w, &w->table64, &w->ntable64,
+                Bz * lz_table_records(std::min(kLzFree, N), kLzU) * (2 + kLzUF)));
+  GROW_TRY(grow(w, &w->lzq, &w->nlzq, Bz * kMaxBeta * kLzQStride));
+  GROW_TRY(grow(w, &w->lzqmin, &w->nlzqmin, Bz));
+  GROW_TRY(grow(w, &w->lz_acc, &w->nlz_acc, Bz * stride));
+  GROW_TRY(grow(w, &w->lz_coef, &w->nlz_coef, Bz * kMaxBeta));
   return SG_OK;
 }
 
@@ -736,6 +792,7 @@ sg_status sg_reserve(int B_max, int N_max, int S_max, void* stream) {
   while (cap < 8u * (uint32_t)S_max) cap <<= 1;
   sg_status v = ws_get(st, 1, table_records(kMaxFree), cap, S_max, &w);
   if (v != SG_OK) return v;
+  w->pinned = true;  // a graph captured from here on may hold these buffers
   // batched search and log Z
   if (N_max >= kU && N_max <= kMaxNBatched && S_max <= SG_MAX_S_BATCHED) {
     // the per-instance slots grow as B shrinks: size for the largest B * cap
@@ -880,10 +937,10 @@ sg_status sg_low_spectrum_qubo_f32(int N, const float* A, const float* b, int S,
   Workspace* w = nullptr;
   sg_status v = ws_get(st, 1, 1, 1, 1, &w);
   if (v != SG_OK) return v;
-  HIP_TRY(grow(&w->qJ, &w->nqJ, (size_t)N * N));
-  HIP_TRY(grow(&w->qh, &w->nqh, (size_t)N));
-  HIP_TRY(grow(&w->qfound, &w->nqfound, (size_t)S));
-  HIP_TRY(grow(&w->qenergy, &w->nqenergy, (size_t)S));
+  GROW_TRY(grow(w, &w->qJ, &w->nqJ, (size_t)N * N));
+  GROW_TRY(grow(w, &w->qh, &w->nqh, (size_t)N));
+  GROW_TRY(grow(w, &w->qfound, &w->nqfound, (size_t)S));
+  GROW_TRY(grow(w, &w->qenergy, &w->nqenergy, (size_t)S));
   HIP_TRY(launch_qubo_to_ising(N, A, b, w->qJ, w->qh, st));
   v = run_search(false, N, w->qJ, w->qh, S, 0, (uint64_t)1 << N, w->qfound, w->qenergy, stream);
   if (v != SG_OK) return v;
@@ -941,6 +998,40 @@ void sg_set_kernel_timing(int enable) { g_timing = enable != 0; }
 double sg_probe_valu(int op, int waves_per_simd) {
   if (op < 0 || op > 17 || waves_per_simd < 1 || waves_per_simd > 8) return -1.0;
   return probe_valu(op, waves_per_simd);
+}
+
+sg_status sg_debug_set_fill(void* stream, long long lanes) {
+  g_last_error.clear();
+  if (lanes < 0) return fail(SG_EINVAL, "lanes must be >= 0");
+  Workspace* w = nullptr;
+  const sg_status v = ws_get((hipStream_t)stream, 1, 1, 1, 1, &w);
+  if (v != SG_OK) return v;
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (int k = 0; k < 2; ++k) w->fill[k] = lanes > 0 ? (int64_t)lanes : w->fill_dev[k];
+  return SG_OK;
+}
+
+sg_status sg_debug_set_margin_scale(void* stream, double scale) {
+  g_last_error.clear();
+  if (!(scale > 0.0) || !(scale <= 1.0)) return fail(SG_EINVAL, "scale must be in (0, 1]");
+  Workspace* w = nullptr;
+  const sg_status v = ws_get((hipStream_t)stream, 1, 1, 1, 1, &w);
+  if (v != SG_OK) return v;
+  std::lock_guard<std::mutex> lk(g_mu);
+  w->margin_scale = (float)scale;
+  return SG_OK;
+}
+
+sg_status sg_debug_set_batch_shift(int B, int N_max, int S, int shift) {
+  g_last_error.clear();
+  if (B < 1 || S < 1 || shift > 40) return fail(SG_EINVAL, "need B >= 1, S >= 1, shift <= 40");
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_mu);
+  const auto key = std::make_tuple(dev, B, N_max, S);
+  if (shift < 0) g_shift.erase(key);
+  else g_shift[key] = shift;
+  return SG_OK;
 }
 
 int sg_debug_plan(int N, int S, uint64_t lo, uint64_t hi, int64_t lanes_fill,

@@ -123,6 +123,7 @@ struct Batch {
   uint64_t* tmask;     // [B][S]
   uint32_t* sticky;    // error bits accumulated over searches
   int allow_f32_walk;  // integer instances may take the fp32 walk (searches: 1)
+  float margin_scale;  // factor on the fp32 pruning margin (1; test hook only)
 };
 
 // Exact log Z walk (forward: partition sums; backward: gradient moments).

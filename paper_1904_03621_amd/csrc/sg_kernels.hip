@@ -240,7 +240,7 @@ __global__ void k_prep(Batch bt) {
         for (int U = kU; U <= kUWide; ++U)
           walk = fmax(walk, (double)(1 << (kReanchorLog2 - U)) * ((1 << U) - 1.0 + 3.0 * U + 3.0));
         const double rounds = walk + (kMaxFree + 3.0) + kMaxFree * 0.5 + 4.0 + 4.0;
-        margin = rounds * uH;
+        margin = rounds * uH * (double)bt.margin_scale;
       }
     }
     P->thr_key = 0xFFFFFFFFu;

@@ -168,6 +168,62 @@ def test_reserve_then_capture(torch_dev):
     assert sg.sg_get_error(stream) == 0
 
 
+def test_graph_survives_workspace_growth(torch_dev):
+    """A graph captured after sg_reserve keeps its buffers: a larger eager call
+    on the same stream grows the workspace (new buffers, the old ones kept),
+    and the graph still replays to the eager result; a call under capture
+    that needs more than the workspace holds is refused (SG_EINVAL) instead
+    of allocating."""
+    import paper_1904_03621_amd as sg
+    from paper_1904_03621_amd import _lib
+    torch = torch_dev
+    B, S, Nmax = 32, 16, 18
+    Ns, J, h = make_batch(B, 8, Nmax, 13, False)
+    Nt, Jt, ht = (torch.from_numpy(x).cuda() for x in (Ns, J, h))
+    m0, e0 = sg.low_spectrum_batched(Nt, Jt, ht, S)
+    stream = torch.cuda.Stream()
+    assert sg.sg_reserve(B, Nmax, S, stream) == 0
+    m_out = torch.zeros((B, S), dtype=torch.int64, device="cuda")
+    e_out = torch.zeros((B, S), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        st = sg.sg_low_spectrum_batched_f32(B, Nt, Nmax, Jt, ht, S, m_out, e_out, stream)
+    assert st == 0
+    g.replay()
+    torch.cuda.synchronize()
+    assert torch.equal(m_out, m0) and torch.equal(e_out, e0)
+    # a larger eager call on the graph's stream: more instances and states
+    B2, S2 = 512, 64
+    Ns2, J2, h2 = make_batch(B2, 8, Nmax, 14, False)
+    N2t, J2t, h2t = (torch.from_numpy(x).cuda() for x in (Ns2, J2, h2))
+    with torch.cuda.stream(stream):
+        m2, e2 = sg.low_spectrum_batched(N2t, J2t, h2t, S2, stream=stream)
+    m2d, e2d = sg.low_spectrum_batched(N2t, J2t, h2t, S2)  # default stream
+    torch.cuda.synchronize()
+    assert torch.equal(m2, m2d) and torch.equal(e2, e2d)
+    for rep in range(2):
+        m_out.fill_(-1)
+        e_out.fill_(0)
+        _ = torch.randn(1000, device="cuda").sum()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(m_out, m0) and torch.equal(e_out, e0), "replay %d after growth" % rep
+    assert sg.sg_get_error(stream) == 0
+    # under capture, a call beyond the workspace is refused
+    B3 = 2048
+    Ns3, J3, h3 = make_batch(B3, 8, Nmax, 15, False)
+    N3t, J3t, h3t = (torch.from_numpy(x).cuda() for x in (Ns3, J3, h3))
+    m3 = torch.empty((B3, S), dtype=torch.int64, device="cuda")
+    e3 = torch.empty((B3, S), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    g3 = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g3, stream=stream):
+        st3 = sg.sg_low_spectrum_batched_f32(B3, N3t, Nmax, J3t, h3t, S, m3, e3, stream)
+    assert st3 == _lib.SG_EINVAL, st3
+    assert "capturing" in _lib.last_error()
+
+
 def test_overflowing_level_is_walked_again(orc, torch_dev):
     """A strong field on the top spin puts ~55000 states of the last level
     below the threshold that the first half of the state space leaves; with
