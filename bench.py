@@ -23,11 +23,22 @@ sys.path.insert(0, ROOT)
 N_SPINS = 48
 S_STATES = 1000
 SEED = 2
-# MI355X fp32 vector peak: 157.3 TFLOP/s counts a fused multiply-add as two
-# flops, i.e. 256 CUs x 128 fp32 lanes x 2.4 GHz = 7.86e13 lane operations/s.
+# Peak of the bound (VALU issue): MI355X has 256 CUs x 4 SIMDs; a SIMD issues
+# an instruction of the doubled-rate class (fp32 add/fma, 32-bit integer
+# add/sub, AND/OR) for 32 lanes per clock, i.e. 256 x 128 lanes x 2.4 GHz =
+# 7.86e13 lane-instructions/s -- the rate behind the 157.3 TFLOP/s fp32 vector
+# figure (an FMA counts two flops).  Three-input min/max and other VOP3-only
+# instructions issue at half that rate.
 PEAK_LANE_OPS = 256 * 128 * 2.4e9
-# algorithmic work per state: one accumulate and one order test
-OPS_PER_STATE = 2.0
+# Algorithmic work per configuration of the walk that runs the search (the
+# paired walk): one accumulate and one order test per state, on 16-bit
+# fixed-point fields two to a 32-bit lane -- one integer add and one AND per
+# Gray step and pair of states, i.e. one doubled-rate lane-instruction per
+# configuration.
+OPS_PER_STATE = 1.0
+# The survey's algorithmic figure: two lane-ops per configuration at the base
+# (non-doubled) issue rate, 3.93e13 / 2 configurations/s.
+SURVEY_STATES_PER_S = 256 * 64 * 2.4e9 / 2.0
 # size of the plain device copy that calibrates the HBM byte counters
 COPY_BYTES = 512 << 20
 # HBM bytes per k_enum launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes
@@ -37,6 +48,15 @@ COPY_BYTES = 512 << 20
 TRAFFIC = {"kenum_sha256_16": "34361f53900017ab", "fetch_kib": 1131293.9375 / 447,
            "write_kib": 41122.125 / 447, "fetch_factor": 524288.0 / 262162.0, "write_factor": 1.0,
            "profile": "profiles/k_enum_f32_dense48_counters.md"}
+
+
+# VALU counters of the search's enumeration launches (rocprofv3 --pmc, one
+# search of this instance; see the profile), valid for the k_enum source with
+# this hash only: SQ_INSTS_VALU (wave instructions) x 64 / 2^48 per
+# configuration, SQ_ACTIVE_INST_VALU x 4 / (1024 SIMDs x cycles) as the
+# VALU-active fraction, and GRBM_GUI_ACTIVE / 8 XCDs / kernel time as sclk.
+COUNTERS = {"kenum_sha256_16": None, "valu_insts_per_state": None, "valu_active": None,
+            "sclk_ghz": None, "profile": "profiles/k_enum_f32_dense48_counters.md"}
 
 
 def kenum_source_hash() -> str:
@@ -52,6 +72,14 @@ def kenum_source_hash() -> str:
     body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
     body = re.sub(r"\s+", "", body)
     return hashlib.sha256(body.encode()).hexdigest()[:16]
+
+
+def valu_counters():
+    """The committed VALU counter figures, or None once the enumeration
+    source differs from the one they were taken on."""
+    if COUNTERS["kenum_sha256_16"] != kenum_source_hash():
+        return None
+    return {k: COUNTERS[k] for k in ("valu_insts_per_state", "valu_active", "sclk_ghz")}
 
 
 def traffic_per_launch():
@@ -78,9 +106,21 @@ def cpu_baseline(J, h, seconds_hint: float = 20.0) -> dict:
     t = time.perf_counter()
     oracle.low_spectrum(J, h, S_STATES, 0, M)
     dt = time.perf_counter() - t
+    # one thread, on a slice a sixteenth as large (a few seconds)
+    M1 = max(1 << 20, M >> 4)
+    t = time.perf_counter()
+    oracle.low_spectrum(J, h, S_STATES, 0, M1, nthreads=1)
+    dt1 = time.perf_counter() - t
     return {"value": M / dt, "unit": "spin configs/s", "cores": oracle.max_threads(),
             "kind": "oracle", "sample": "masks [0, 2^%d) of the same N=48 instance, "
-            "S=%d, %.1f s" % (int(np.log2(M)), S_STATES, dt)}
+            "S=%d, %.1f s" % (int(np.log2(M)), S_STATES, dt),
+            "single_core": {"value": M1 / dt1, "cores": 1,
+                            "sample": "masks [0, 2^%d), %.1f s" % (int(np.log2(M1)), dt1)}}
+
+
+def _median_time(torch, fn, reps: int) -> float:
+    """Median wall time of `reps` synchronised calls."""
+    return float(np.median([_sync_time(torch, fn) for _ in range(max(reps, 1))]))
 
 
 def _sync_time(torch, fn):
@@ -124,10 +164,10 @@ def bench_batched(torch, sg, reps: int, baseline: bool = True) -> dict:
 
     batched()
     if not baseline:
-        t_b = min(_sync_time(torch, batched) for _ in range(reps))
+        t_b = _median_time(torch, batched, reps)
         return {"ms": t_b * 1e3}
     per_instance()  # warm-up: workspaces sized
-    t_b = min(_sync_time(torch, batched) for _ in range(reps))
+    t_b = _median_time(torch, batched, reps)
     t_p = _sync_time(torch, per_instance)
     err = sg.sg_get_error(stream)
     if err != 0:
@@ -159,7 +199,7 @@ def bench_batched(torch, sg, reps: int, baseline: bool = True) -> dict:
                     raise sg.SgError(st, "sg_low_spectrum_f32", sg._lib.last_error())
 
         batched_bin()
-        tb = min(_sync_time(torch, batched_bin) for _ in range(reps))
+        tb = _median_time(torch, batched_bin, reps)
         tp = _sync_time(torch, per_instance_bin)
         same = bool(torch.equal(bm_b, sm[:nb]) and torch.equal(be_b, se[:nb]))
         bins.append({"N": "%d-%d" % (lo_n, hi_n), "instances": nb, "batched_ms": tb * 1e3,
@@ -221,12 +261,12 @@ def bench_logz(torch, sg, reps: int, baseline: bool = True) -> dict:
 
     fwd(); bwd()
     if not baseline:
-        t_f = min(_sync_time(torch, fwd) for _ in range(reps))
-        t_bw = min(_sync_time(torch, bwd) for _ in range(reps))
+        t_f = _median_time(torch, fwd, reps)
+        t_bw = _median_time(torch, bwd, reps)
         return {"forward_ms": t_f * 1e3, "backward_ms": t_bw * 1e3}
     per_instance()  # warm-up
-    t_f = min(_sync_time(torch, fwd) for _ in range(reps))
-    t_bw = min(_sync_time(torch, bwd) for _ in range(reps))
+    t_f = _median_time(torch, fwd, reps)
+    t_bw = _median_time(torch, bwd, reps)
     t_p = _sync_time(torch, per_instance)
     err = sg.sg_get_error(stream)
     if err != 0:
@@ -264,7 +304,7 @@ def bench_dos(torch, sg, reps: int) -> dict:
             raise sg.SgError(st, "sg_density_of_states_i32", sg._lib.last_error())
 
     run()
-    t = min(_sync_time(torch, run) for _ in range(reps))
+    t = _median_time(torch, run, reps)
     err = sg.sg_get_error(stream)
     if err != 0:
         raise sg.SgError(err, "device", sg._lib.last_error())
@@ -300,17 +340,16 @@ def bench_plain(torch, sg) -> dict:
             if st != 0:
                 raise sg.SgError(st, "sg_low_spectrum_i32", sg._lib.last_error())
 
-        best, frac = None, None
+        timed = []  # (wall time, roofline fraction of the enumeration launches)
         for _ in range(runs):
             t = _sync_time(torch, run)
             info = sg.sg_get_run_info(stream)
-            if best is None or t < best:
-                best = t
-                launches = max(info["enum_launches"], 1)
-                avg = info["enum_ms"] / launches
-                if avg > 0:
-                    frac = (OPS_PER_STATE * info["enum_states"] / launches) / (avg * 1e-3) \
-                        / PEAK_LANE_OPS
+            launches = max(info["enum_launches"], 1)
+            avg = info["enum_ms"] / launches
+            frac = (OPS_PER_STATE * info["enum_states"] / launches) / (avg * 1e-3) \
+                / PEAK_LANE_OPS if avg > 0 else None
+            timed.append((t, frac))
+        best, frac = sorted(timed, key=lambda x: x[0])[len(timed) // 2]  # the median run
         err = sg.sg_get_error(stream)
         if err != 0:
             raise sg.SgError(err, "device", sg._lib.last_error())
@@ -368,7 +407,11 @@ def main() -> int:
 
     if args.valu_probe:
         rates = {op: sg.sg_probe_valu(code, 8) for op, code in sg._lib.PROBE_OPS.items()}
-        print(json.dumps({"valu_lane_ops_per_s": rates, "waves_per_simd": 8}), flush=True)
+        mixes = {op: {w: sg.sg_probe_valu(op, w) for w in (1, 2, 4, 8)}
+                 for op in ("mix_f32_walk", "mix_packed_walk", "mix_packed_walk_1chain",
+                            "mix_packed_walk_2chains", "mix_f32_walk_1chain")}
+        print(json.dumps({"valu_lane_ops_per_s": rates, "waves_per_simd": 8,
+                          "mix_by_waves_per_simd": mixes}), flush=True)
         return 0
     if args.leg:
         if args.leg == "dos":
@@ -434,17 +477,27 @@ def main() -> int:
     elapsed = t1 - t0
     states_total = float(1 << N_SPINS) * args.steps
     value = states_total / elapsed
-    # dominant kernel: the enumeration; algorithmic lane-ops per launch over its
-    # average launch duration (HIP events on its stream)
+    # dominant kernel: the enumeration; algorithmic lane-instructions per launch
+    # over its average launch duration (HIP events on its stream)
     avg_ms = enum_ms / max(enum_launches, 1)
     ops_per_launch = OPS_PER_STATE * enum_states / max(enum_launches, 1)
     achieved = ops_per_launch / (avg_ms * 1e-3) if avg_ms > 0 else 0.0
+    # the issue rate this machine sustains for the walk's own instruction mix
+    # (independent chains of v_add_u32 / v_and_b32, every SIMD full)
+    mix_peak = sg.sg_probe_valu("mix_packed_walk", 8)
+    counters = valu_counters()
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
                 "unit": "Tlane-op/s", "frac": achieved / PEAK_LANE_OPS,
                 "traffic": traffic_per_launch(), "traffic_unit": "HBM bytes per launch",
-                "kernel": "k_enum<float>", "avg_launch_ms": avg_ms,
+                "kernel": "k_enum<float> (paired walk)", "avg_launch_ms": avg_ms,
                 "launches_per_step": enum_launches / max(args.steps, 1),
-                "ops_per_state": OPS_PER_STATE}
+                "ops_per_state": OPS_PER_STATE,
+                "measured_mix_peak": mix_peak / 1e12 if mix_peak > 0 else None,
+                "frac_of_measured_mix_peak": achieved / mix_peak if mix_peak > 0 else None,
+                "valu_insts_per_state": counters["valu_insts_per_state"] if counters else None,
+                "valu_active": counters["valu_active"] if counters else None,
+                "sclk_ghz": counters["sclk_ghz"] if counters else None,
+                "survey_algorithmic_frac": value / SURVEY_STATES_PER_S}
 
     # sanity of the result: sorted, distinct, energies match the oracle's
     m = states.cpu().numpy().astype(np.uint64)
@@ -479,9 +532,9 @@ def main() -> int:
     }
     if not args.no_extensions:
         out.update(bench_plain(torch, sg))
-        out["batched"] = bench_batched(torch, sg, 3)
-        out["logz"] = bench_logz(torch, sg, 3)
-        out["dos"] = bench_dos(torch, sg, 2)
+        out["batched"] = bench_batched(torch, sg, 5)
+        out["logz"] = bench_logz(torch, sg, 5)
+        out["dos"] = bench_dos(torch, sg, 3)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(J, h)
     print(json.dumps(out), flush=True)

@@ -320,8 +320,13 @@ void sg_set_kernel_timing(int enable);
  * 2 v_add_u32, 3 v_min3_i32, 4 v_fma_f32, 5 v_min_f32, 6 v_or_b32,
  * 7 v_or3_b32, 8 v_add3_u32, 9 v_max3_f32, 10 v_min_i32, 11 v_sub_f32,
  * 12 v_and_or_b32, 13 v_med3_f32, 14 v_pk_add_u16, 15 v_pk_min_i16,
- * 16 v_exp_f32, 17 v_sub_u32), with `waves_per_simd` (1..8) resident waves on
- * every SIMD.
+ * 16 v_exp_f32, 17 v_sub_u32, 18 v_and_b32, 19 v_cvt_i32_f32,
+ * 20 v_lshl_add_u32), or of an instruction mix of the walk's steps, 8
+ * independent chains per lane (21: two v_add_f32 and one v_min3_f32 per two
+ * states, the fp32 walk; 22: v_add_u32, v_and_b32, v_sub_u32, v_and_b32 per two
+ * steps, the walk over two 16-bit fields per word; 23 and 24: 22 with one
+ * and two chains per lane; 25: 21 with one chain per lane), with
+ * `waves_per_simd` (1..8) resident waves on every SIMD.
  * Synchronous (own stream); returns < 0 on error.  Context for the
  * enumeration kernel's roofline: which instructions issue at the doubled
  * rate.

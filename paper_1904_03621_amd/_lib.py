@@ -40,7 +40,11 @@ EXPORTS = [
 PROBE_OPS = {"v_add_f32": 0, "v_min3_f32": 1, "v_add_u32": 2, "v_min3_i32": 3, "v_fma_f32": 4,
              "v_min_f32": 5, "v_or_b32": 6, "v_or3_b32": 7, "v_add3_u32": 8, "v_max3_f32": 9,
              "v_min_i32": 10, "v_sub_f32": 11, "v_and_or_b32": 12, "v_med3_f32": 13,
-             "v_pk_add_u16": 14, "v_pk_min_i16": 15, "v_exp_f32": 16, "v_sub_u32": 17}
+             "v_pk_add_u16": 14, "v_pk_min_i16": 15, "v_exp_f32": 16, "v_sub_u32": 17,
+             "v_and_b32": 18, "v_cvt_i32_f32": 19, "v_lshl_add_u32": 20,
+             # instruction mixes of the walk's steps (lane-instructions/s)
+             "mix_f32_walk": 21, "mix_packed_walk": 22, "mix_packed_walk_1chain": 23,
+             "mix_packed_walk_2chains": 24, "mix_f32_walk_1chain": 25}
 
 
 class SgError(RuntimeError):

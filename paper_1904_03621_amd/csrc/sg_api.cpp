@@ -18,7 +18,8 @@
 
 namespace sg {
 hipError_t launch_prep(bool isint, const Batch& bt, hipStream_t st);
-hipError_t launch_tables(bool isint, int U, const Batch& bt, int ncap, hipStream_t st);
+hipError_t launch_tables(bool isint, int U, const Batch& bt, int ncap, bool paired,
+                         hipStream_t st);
 hipError_t launch_enum(bool isint, int U, bool split, const Batch& bt, const Chunk& ch, int ninst,
                        hipStream_t st);
 hipError_t launch_direct(const Batch& bt, uint64_t lo, uint64_t hi, hipStream_t st);
@@ -152,7 +153,6 @@ std::vector<PlanChunk> plan_chunks(int N, int S, uint64_t lo, uint64_t hi, int64
 // under capture that would need to grow is refused.
 struct Workspace {
   int device = -1;
-  bool fixed = false;              // the no-alloc entry point's view of its static buffer
   bool pinned = false;
   bool capturing = false;          // set by ws_get for the call in progress
   std::vector<void*> retired;
@@ -392,8 +392,7 @@ sg_status validate(int N, const void* J, const void* h, int S, uint64_t lo, uint
 hipError_t enum_timed(Workspace* w, bool isint, int U, bool split, const Batch& bt,
                       const Chunk& ch, int ninst, hipStream_t st) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  const bool timed = g_timing && !w->fixed;  // the no-alloc path creates no events
-  if (timed) {
+  if (g_timing) {
     hipError_t r = ws_event_pair(w, &e0, &e1);
     if (r != hipSuccess) return r;
     r = hipEventRecord(e0, st);
@@ -402,7 +401,7 @@ hipError_t enum_timed(Workspace* w, bool isint, int U, bool split, const Batch& 
   hipError_t r = launch_enum(isint, U, split, bt, ch, ninst, st);
   if (r != hipSuccess) return r;
   ++w->last_launches;
-  if (timed) r = hipEventRecord(e1, st);
+  if (g_timing) r = hipEventRecord(e1, st);
   return r;
 }
 
@@ -420,7 +419,7 @@ sg_status search_on(Workspace* w, bool isint, int N, const void* J, const void* 
   int kmax = 0, nmaxu = 0;
   w->ev_used = 0;
   w->last_launches = 0;
-  if (N >= U) HIP_TRY(launch_tables(isint, U, bt, ncap, st));
+  if (N >= U) HIP_TRY(launch_tables(isint, U, bt, ncap, true, st));
   const std::vector<PlanChunk> plan = plan_chunks(N, S, lo, hi, w->fill[isint ? 1 : 0], U);
   double states = 0.0;
   for (const PlanChunk& pc : plan) {
@@ -549,8 +548,8 @@ sg_status batch_search(Workspace* w, bool isint, const Batch& bt0, int Nmax, int
   Batch bt = bt0;
   bt.table_base8 = (int64_t)table_records(kU);
   HIP_TRY(launch_prep(isint, bt, st));
-  HIP_TRY(launch_tables(isint, kU, bt, kU, st));
-  if (ncap >= kUWide) HIP_TRY(launch_tables(isint, kUWide, bt, ncap, st));
+  HIP_TRY(launch_tables(isint, kU, bt, kU, false, st));
+  if (ncap >= kUWide) HIP_TRY(launch_tables(isint, kUWide, bt, ncap, true, st));
   const std::vector<Level> levels =
       batch_levels(Nmax, bt.S, batch_shift(bt.B, Nmax, bt.S, w->fill[isint ? 1 : 0]));
   w->ev_used = 0;
@@ -844,7 +843,7 @@ sg_status sg_density_of_states_i32(int N, const int32_t* J, const int32_t* h, lo
     const int64_t fill = w->fill[1];
     int n = std::min(kMaxFree, N);
     while (n > kU && ((int64_t)1 << (N - n)) < fill) --n;
-    HIP_TRY(launch_tables(true, kU, bt, n, st));
+    HIP_TRY(launch_tables(true, kU, bt, n, false, st));
     const uint64_t prefixes = (uint64_t)1 << (N - n);
     for (uint64_t base = 0; base < prefixes; base += (uint64_t)fill) {
       Chunk ch{};
@@ -996,7 +995,7 @@ sg_status sg_get_run_info(void* stream, sg_run_info* out) {
 void sg_set_kernel_timing(int enable) { g_timing = enable != 0; }
 
 double sg_probe_valu(int op, int waves_per_simd) {
-  if (op < 0 || op > 17 || waves_per_simd < 1 || waves_per_simd > 8) return -1.0;
+  if (op < 0 || op > 25 || waves_per_simd < 1 || waves_per_simd > 8) return -1.0;
   return probe_valu(op, waves_per_simd);
 }
 

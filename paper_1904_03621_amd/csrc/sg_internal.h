@@ -90,7 +90,20 @@ struct Params {
   uint32_t walk_f32;         // integer instance walked in fp32 (exact: |values| < 2^24)
   uint32_t stat_redo;       // repeated passes taken
   double bound;             // sum_{i<j} |J_ij| + sum_i |h_i| (no |E| exceeds it)
+  // paired walk (two 16-bit fixed-point fields per word): the power-of-two
+  // scale of its values (0: not available), and the slack subtracted from the
+  // field offset 2^15 so that rounding never hides a state below the bound
+  float pk_scale;
+  int32_t pk_slack;
 };
+
+// Paired walk: the record of block T < half of a table (n >= U + 2 free
+// spins, U = kUWide) holds, in words kPkWord .. kRecWords - 1, the packed
+// record steps pk_f = (Wx_f(T + half) << 16) + Wx_f(T) of f = 0 .. 5 (integer
+// sum mod 2^32, Wx the fixed-point value of the record's Wu_f), and the record
+// of block T + half holds f = 6, 7 in its words kPkWord, kPkWord + 1.
+constexpr int kPkWord = 2 + kUWide;
+constexpr int kPkInA = kRecWords - kPkWord;  // packed steps stored in the first record
 
 // Extra passes over a chunk whose candidates overflowed the buffer.
 constexpr int kRetries = 2;

@@ -243,6 +243,30 @@ __global__ void k_prep(Batch bt) {
         margin = rounds * uH * (double)bt.margin_scale;
       }
     }
+    // Paired walk (fp32 walks only): every field value is (G - fastThr) sc
+    // + 2^15 - slack plus at most U + 1 units of rounding (the start value
+    // and up to U low-spin steps of two roundings each), with
+    // |G - fastThr| <= R = 2 Bv + 2 BQ + 2 margin + 1 (G = E - Q with
+    // |E| <= Bv, |Q| <= BQ over the U low spins, walk values within the
+    // margin); sc is the largest power of two with R sc + slack + U + 2
+    // <= 2^15, so no field ever leaves [0, 2^16).  A slack of U + 1 units
+    // keeps every state whose value is at or below fastThr below 2^15.
+    float pk_scale = 0.0f;
+    const int pk_slack = kUWide + 1;
+    if ((!kInt || walk_f32) && !anybad && !badN) {
+      double BQ = 0.0;
+      for (int a = 0; a < kUWide && a < Nc; ++a)
+        for (int c = a + 1; c < kUWide && c < Nc; ++c) BQ += fabs((double)Jb[a * ld + c]);
+      const double R = 2.0 * Bv + 2.0 * BQ + 2.0 * margin + 1.0;
+      const double room = 32768.0 - pk_slack - kUWide - 2.0;
+      if (isfinite(R)) {
+        int e = (int)floor(log2(room / R)) + 1;
+        while (ldexp(R, e) > room) --e;
+        if (e >= -100) pk_scale = (float)ldexp(1.0, e);
+      }
+    }
+    P->pk_scale = pk_scale;
+    P->pk_slack = pk_slack;
     P->thr_key = 0xFFFFFFFFu;
     P->rec_count = 0;
     P->thr_mask = ~0ull;
@@ -283,7 +307,7 @@ __global__ void k_prep(Batch bt) {
 // records of 2 + U doubles.
 
 template <bool kInt, bool kF64, int U>
-__global__ void k_tables(Batch bt, int ncap, void* out) {
+__global__ void k_tables(Batch bt, int ncap, void* out, int paired) {
   static_assert(kF64 || 2 + U <= kRecWords, "record exceeds kRecWords");
   const int b = blockIdx.y;
   const int N = inst_N(bt, b);
@@ -325,13 +349,17 @@ __global__ void k_tables(Batch bt, int ncap, void* out) {
   for (int a = 0; a < U; ++a)
     for (int c = a + 1; c < U; ++c) q -= J(a, c) * S(a) * S(c);
   const double R = eff - q;
+  // Wu_f of the block whose free configuration is xb (parity of T)
+  auto wu_of = [&](uint32_t xb, double* w) {
+    for (int f = 0; f < U; ++f) {
+      double s = H(f);
+      for (int g = U; g < n; ++g) s += J(f, g) * (((xb >> g) & 1u) ? 1.0 : -1.0);
+      w[f] = 2.0 * s;
+    }
+    w[U - 1] *= (T & 1u) ? 1.0 : -1.0;
+  };
   double wu[U];
-  for (int f = 0; f < U; ++f) {
-    double s = H(f);
-    for (int g = U; g < n; ++g) s += J(f, g) * S(g);
-    wu[f] = 2.0 * s;
-  }
-  wu[U - 1] *= (T & 1u) ? 1.0 : -1.0;
+  wu_of(x, wu);
 
   if (kF64) {  // records of 2 + U doubles (the log Z walk keeps its energies in fp64)
     double* rec = (double*)out + ((size_t)b * bt.table_recs + (size_t)r) * (2 + U);
@@ -351,6 +379,21 @@ __global__ void k_tables(Batch bt, int ncap, void* out) {
     rec[0] = __float_as_uint((float)cB);
     rec[1] = __float_as_uint((float)R);
     for (int f = 0; f < U; ++f) rec[2 + f] = __float_as_uint((float)wu[f]);
+    // packed steps of the paired walk: blocks T and T ^ half (same parity)
+    const float sc = bt.P[b].pk_scale;
+    if (paired && U == kUWide && n >= U + 2 && sc > 0.0f) {
+      const uint32_t half = 1u << (n - U - 1);
+      const uint32_t T2 = T ^ half;
+      double wp[U];
+      wu_of(gray32(T2 << U), wp);
+      const bool first = T < half;  // this record is block A of its pair
+      for (int f = first ? 0 : kPkInA; f < (first ? kPkInA : U); ++f) {
+        const int32_t xs = (int32_t)rintf((float)wu[f] * sc);
+        const int32_t xp = (int32_t)rintf((float)wp[f] * sc);
+        const uint32_t xa = (uint32_t)(first ? xs : xp), xb = (uint32_t)(first ? xp : xs);
+        rec[kPkWord + (first ? f : f - kPkInA)] = xa + (xb << 16);
+      }
+    }
   }
 }
 
@@ -358,12 +401,19 @@ __global__ void k_tables(Batch bt, int ncap, void* out) {
 // One lane per prefix p (spins n..N-1 fixed to the bits of p); the lane walks
 // all 2^n configurations of the free spins in reflected Gray-code order,
 // blocks of 2^U steps at a time.  Every state costs one add (its G, the
-// energy minus the low-low part) and enters the block minimum (one 3-input
-// min per two states).  The block minimum plus the smallest low-low energy
-// bounds every energy of the block from below; a block whose bound passes the
-// threshold is walked again with the same arithmetic, each state tested
-// exactly, and every state at or below the threshold is appended as a
-// candidate mask.  blockIdx.x / blocks_per_inst selects the instance.
+// energy minus the low-low part) and one order test against the bound
+// fastThr = threshold - (smallest low-low energy), which no state below the
+// threshold can exceed.  Two walks:
+//   plain  -- G in fp32 (or int32); the block minimum, one 3-input min per
+//             two states, against the bound;
+//   paired -- (blocks of 8, n >= 10, fp32 walks) blocks T
+//             and T + 2^(n-U-1) in the two 16-bit fixed-point fields of one
+//             word: one integer add and one AND per step for both states,
+//             the sign bit of each field the test.
+// A block that may hold a state below the bound is walked again in fp32 (or
+// int32), each state tested exactly, and every state at or below the
+// threshold is appended as a candidate mask.  blockIdx.x / blocks_per_inst
+// selects the instance.
 
 template <typename V>
 struct Num;
@@ -378,7 +428,7 @@ struct Num<int32_t> {
   static __device__ inline int32_t big() { return 1 << 29; }
 };
 
-template <bool kInt, bool kWF, int U, bool kSplit>
+template <bool kInt, bool kWF, int U, bool kSplit, bool kPk>
 __device__ __forceinline__ void enum_walk(const Batch& bt, const void* __restrict__ Jv,
                                           const void* __restrict__ hv,
                                           const uint32_t* __restrict__ table,
@@ -389,7 +439,7 @@ __device__ __forceinline__ void enum_walk(const Batch& bt, const void* __restric
 // U: low spins per block (kU or kUWide; n >= U for every chunk).  kSplit: the
 // bound is tested per sub-block of 64 steps instead of per block (batches,
 // whose short levels bring many candidates per state).
-template <bool kInt, int U, bool kSplit>
+template <bool kInt, int U, bool kSplit, bool kPk>
 __global__ __launch_bounds__(kEnumBlock, 8) void k_enum(Batch bt, const void* __restrict__ Jv,
                                                         const void* __restrict__ hv,
                                                         const uint32_t* __restrict__ table,
@@ -418,17 +468,17 @@ __global__ __launch_bounds__(kEnumBlock, 8) void k_enum(Batch bt, const void* __
   __shared__ A s_R[2][kMaxN];
   __shared__ A s_EH[2];
   if (kInt && P->walk_f32)
-    enum_walk<true, true, U, kSplit>(bt, Jv, hv, table, qtab_all, ch, b, blk, N, n, lanes, P,
-                                     s_y, s_F, s_R, s_EH);
+    enum_walk<true, true, U, kSplit, kPk>(bt, Jv, hv, table, qtab_all, ch, b, blk, N, n, lanes,
+                                          P, s_y, s_F, s_R, s_EH);
   else
-    enum_walk<kInt, !kInt, U, kSplit>(bt, Jv, hv, table, qtab_all, ch, b, blk, N, n, lanes, P,
-                                      s_y, s_F, s_R, s_EH);
+    enum_walk<kInt, !kInt, U, kSplit, kPk && !kInt>(bt, Jv, hv, table, qtab_all, ch, b, blk, N,
+                                                    n, lanes, P, s_y, s_F, s_R, s_EH);
 }
 
 // The walk of k_enum.  kInt: the instance is int32 (exact set-up in int64,
 // integer keys); kWF: the walk runs in fp32 (fp32 instances, and integer ones
 // whose values fit 24 bits, whose tables then hold fp32 values).
-template <bool kInt, bool kWF, int U, bool kSplit>
+template <bool kInt, bool kWF, int U, bool kSplit, bool kPk>
 __device__ __forceinline__ void enum_walk(const Batch& bt, const void* __restrict__ Jv,
                                           const void* __restrict__ hv,
                                           const uint32_t* __restrict__ table,
@@ -570,7 +620,7 @@ __device__ __forceinline__ void enum_walk(const Batch& bt, const void* __restric
   // block start of either parity (low spins all -1, except spin U-1 = +1 in
   // odd blocks), from the rounded fields the walk itself uses.
   float epa0 = 0.0f, epa1 = 0.0f;
-  if (!kInt) {
+  if (kWF) {
     double lo = 0.0;
     for (int f = 0; f < U - 1; ++f) lo += 0.5 * (double)WL[f];
     const double yl = 0.5 * (double)WL[U - 1];
@@ -612,163 +662,347 @@ __device__ __forceinline__ void enum_walk(const Batch& bt, const void* __restric
   const uint32_t nblocks = 1u << (n - U);
   float drift = 0.0f;
   uint32_t slow = 0;  // wave-blocks that took the re-walk (wave-uniform)
-  V ynext = nblocks > 1 ? s_y[tid] : (V)0;  // block 1 flips high spin U
 
-  for (uint32_t T = 0; T < nblocks; ++T) {
-    const uint32_t* rec = tab + (size_t)T * kRecWords;
-    V rw[2 + U];
+  // With kSplit the minimum is kept per sub-block of 64 steps, and G at every
+  // sub-block start, so that a block whose bound passes re-walks only the
+  // sub-blocks that can hold a state below the threshold (a few more
+  // instructions per block, far fewer re-walked states where candidates are
+  // frequent); without it the block is one sub-block.
+  constexpr int kSub = kSplit ? 64 : kSteps;
+  constexpr int kNSub = kSteps / kSub;
+  constexpr int kHitWords = kSteps / 64;  // hit masks: one bit per state
+  static_assert(kSteps % kSub == 0 && kSub % 64 == 0, "sub-blocks of whole hit words");
+
+  // Re-walk of block T (steps W, sub-block start values gsub), testing every
+  // state exactly, of the sub-blocks whose `pass` bit is set in some lane;
+  // the states at or below thrE in lanes that passed become candidates.
+  auto rewalk = [&](uint32_t T, const V (&W)[U], const V (&gsub)[kNSub],
+                    const bool (&pass)[kNSub]) {
+    ++slow;
+    const uint32_t* q = qtab + (T & 1u) * kSteps;
+    const V Gs = gsub[0];
+    uint64_t hits[kHitWords];
 #pragma unroll
-    for (int k = 0; k < 2 + U; ++k)
-      rw[k] = kWF ? (V)__uint_as_float(rec[k]) : (V)(int32_t)rec[k];
-    const V ycur = ynext;
-    if (T + 1 < nblocks) ynext = s_y[__builtin_ctz(T + 1) * kEnumBlock + tid];
-
-    if (T != 0) {
-      // boundary step: flip high spin g = U + c whose old value is +1 iff bit
-      // c+1 of T is set
-      const int c = __builtin_ctz(T);
-      const bool up = (T >> (c + 1)) & 1u;
-      G = up ? G + ycur : G - ycur;
-      G = G + rw[0];
-      if (!kInt && (T & (kReBlocks - 1)) == 0) {
-        // fresh G = E_P - sum_f s_f y_f + R(T) in fp32 from the lane's
-        // fields: the low part is the parity constant, the high part one LDS
-        // read and one fma per high spin (signs from the Gray code of T)
-        const uint32_t xh = gray32(T);  // high spins' bits
-        float a = (float)(T & 1u ? epa1 : epa0) + (float)rw[1];
-        for (int k = 0; k < n - U; ++k) {
-          const float yg = (float)s_y[k * kEnumBlock + tid];
-          a = fmaf(((xh >> k) & 1u) ? -0.5f : 0.5f, yg, a);
-        }
-        const float fresh = valid ? a : (float)G;
-        drift = fmaxf(drift, fabsf((float)G - fresh));
-        G = (V)fresh;
-      }
-    }
-
-    V W[U];
-#pragma unroll
-    for (int f = 0; f < U - 1; ++f) W[f] = WL[f] + rw[2 + f];
-    W[U - 1] = ((T & 1u) ? WL[U - 1] : -WL[U - 1]) + rw[2 + U - 1];
-
-    // 2^U - 1 inner steps: one add per state, one 3-input min per two states.
-    // With kSplit the minimum is kept per sub-block of 64 steps, and G at
-    // every sub-block start, so that a block whose bound passes re-walks only
-    // the sub-blocks that can hold a state below the threshold (a few more
-    // instructions per block, far fewer re-walked states where candidates
-    // are frequent); without it the block is one sub-block.
-    constexpr int kSub = kSplit ? 64 : kSteps;
-    constexpr int kNSub = kSteps / kSub;
-    constexpr int kHitWords = kSteps / 64;  // hit masks: one bit per state
-    static_assert(kSteps % kSub == 0 && kSub % 64 == 0, "sub-blocks of whole hit words");
-    V msub[kNSub], gsub[kNSub];
-    gsub[0] = G;
-    V m = G;
-#pragma unroll
-    for (int i = 1; i < kSteps; i += 2) {
-      // odd step i flips spin 0; its old value is bit 1 of i
-      G = ((i >> 1) & 1) ? G + W[0] : G - W[0];
-      const V Ga = G;
-      if (i + 1 < kSteps) {
-        const int f = __builtin_ctz(i + 1);
-        if (f == U - 1) G = G + W[f];
-        else G = (((i + 1) >> (f + 1)) & 1) ? G + W[f] : G - W[f];
-        if ((i + 1) % kSub == 0) {
-          // step i closes sub-block (i + 1) / kSub - 1; step i + 1 opens the next
-          msub[(i + 1) / kSub - 1] = Num<V>::mn(m, Ga);
-          gsub[(i + 1) / kSub] = G;
-          m = G;
-        } else {
-          m = Num<V>::mn(Num<V>::mn(m, Ga), G);
-        }
-      } else {
-        msub[kNSub - 1] = Num<V>::mn(m, Ga);
-      }
-    }
-
-    bool pass[kNSub];
-    bool any = false;
+    for (int k = 0; k < kHitWords; ++k) hits[k] = 0ull;
+    auto qv = [&](int i) -> V { return kWF ? (V)__uint_as_float(q[i]) : (V)(int32_t)q[i]; };
 #pragma unroll
     for (int w = 0; w < kNSub; ++w) {
-      pass[w] = msub[w] <= fastThr;
-      any = any || pass[w];
-    }
-    if (__ballot(any) != 0ull) {
-      // re-walk, testing every state, of the sub-blocks whose bound passed in
-      // some lane; the opaque copies keep the compiler from holding the values
-      // of the fast walk live across the branch
-      ++slow;
-      const uint32_t* q = qtab + (T & 1u) * kSteps;
-      const V Gs = gsub[0];
-      uint64_t hits[kHitWords];
+      if (kSplit && __ballot(pass[w]) == 0ull) continue;  // wave-uniform
+      // the opaque copy keeps the compiler from holding the values of the
+      // fast walk live across the branch
+      V g2 = gsub[w];
+      asm volatile("" : "+v"(g2));
+      if (g2 + qv(kSub * w) <= thrE) hits[(kSub * w) >> 6] |= 1ull;
 #pragma unroll
-      for (int k = 0; k < kHitWords; ++k) hits[k] = 0ull;
-      auto qv = [&](int i) -> V { return kWF ? (V)__uint_as_float(q[i]) : (V)(int32_t)q[i]; };
+      for (int j = 1; j < kSub; ++j) {
+        const int i = kSub * w + j;
+        const int f = __builtin_ctz(i);
+        if (f == U - 1) g2 = g2 + W[f];
+        else g2 = ((i >> (f + 1)) & 1) ? g2 + W[f] : g2 - W[f];
+        if (g2 + qv(i) <= thrE) hits[i >> 6] |= (1ull << (i & 63));
+      }
+      if (!(valid && pass[w])) {
+#pragma unroll
+        for (int k = 0; k < kSub / 64; ++k) hits[(kSub * w) / 64 + k] = 0ull;
+      }
+    }
+    // one slot reservation for all hits of the wave: an exclusive scan of
+    // the lanes' hit counts, one atomic, then every lane writes its own
+    // hits from its offset (the atomic's latency is paid once per block,
+    // not once per step that hits)
+    uint32_t nh = 0;
+#pragma unroll
+    for (int w = 0; w < kHitWords; ++w) nh += (uint32_t)__popcll(hits[w]);
+    uint32_t incl = nh;
+#pragma unroll
+    for (int o = 1; o < kWaveLanes; o <<= 1) {
+      const uint32_t y = __shfl_up(incl, o);
+      if ((int)__lane_id() >= o) incl += y;
+    }
+    const uint32_t total = __shfl(incl, kWaveLanes - 1);
+    uint32_t base = 0;
+    if (__lane_id() == 0 && total != 0) base = atomicAdd(&P->cand_count, total);
+    uint32_t slot = __shfl(base, 0) + incl - nh;
+    const uint64_t pl = ch.prefix_base + (uint64_t)lane;
+#pragma unroll
+    for (int w = 0; w < kHitWords; ++w) {
+      uint64_t hw = hits[w];
+      while (hw) {
+        const int i = 64 * w + __builtin_ctzll(hw);
+        hw &= hw - 1ull;
+        const uint64_t t = ((uint64_t)T << U) | (uint64_t)i;
+        const uint64_t mask = (pl << n) | (t ^ (t >> 1));
+        // the walk's energy of step i, from the block start: a low spin
+        // f < U-1 that is up at step i flipped an odd number of times from
+        // -1 (net -W_f); spin U-1 flips once, at step 2^(U-1) (net +W_{U-1})
+        const uint32_t gi = (uint32_t)(i ^ (i >> 1));
+        V e = Gs;
+#pragma unroll
+        for (int f = 0; f < U - 1; ++f)
+          if ((gi >> f) & 1u) e = e - W[f];
+        if ((gi >> (U - 1)) & 1u) e = e + W[U - 1];
+        e = e + qv(i);
+        const uint32_t key = kInt ? key_of_i32((int32_t)e) : key_f32((float)e);
+        // beyond cap the mask is dropped; the merge sees cand_count > cap
+        // and asks for another pass over the chunk
+        if (slot < cand_cap) {
+          cand[slot] = mask;
+          ckey[slot] = key;
+        }
+        ++slot;
+      }
+    }
+  };
+
+  // fresh G at the start of block T (fp32 walks): E_P minus the prefix fields
+  // of the low spins (the parity constant), plus the record's R(T), minus the
+  // high spins' prefix fields with their signs from the Gray code of T (one
+  // LDS read and one fma per high spin)
+  auto fresh_g = [&](uint32_t T, V RT) -> float {
+    const uint32_t xh = gray32(T);  // high spins' bits
+    float a = (float)(T & 1u ? epa1 : epa0) + (float)RT;
+    for (int k = 0; k < n - U; ++k) {
+      const float yg = (float)s_y[k * kEnumBlock + tid];
+      a = fmaf(((xh >> k) & 1u) ? -0.5f : 0.5f, yg, a);
+    }
+    return a;
+  };
+
+  if constexpr (kPk) {
+    static_assert(!kPk || (kWF && U == kUWide), "paired walk: fp32 walks, blocks of 8");
+    // ---- paired walk ----------------------------------------------------------
+    // Blocks T and T + half (half = nblocks / 2, n >= U + 2: both of the same
+    // parity) are walked together as the low and high 16-bit fields of one
+    // 32-bit word, in fixed point with the power-of-two scale sc: a field
+    // holds (G - fastThr) sc + 2^15 - slack, so that its bit 15 is clear iff
+    // its state may lie below the bound.  Every Gray step is one integer add
+    // of the packed step (W_f(T + half) sc << 16) + W_f(T) sc, exact as an
+    // integer sum because no field leaves [0, 2^16) (range bounded in
+    // k_prep), and one AND into an accumulator over both fields.  G itself is
+    // carried in fp32 from block to block (boundary steps, the block's net
+    // step +W_{U-1}, re-anchors) and turned into fixed point once per block.
+    const uint32_t half = nblocks >> 1;
+    const float sc = P->pk_scale;
+    const uint32_t off = 32768u - (uint32_t)P->pk_slack;
+    const bool armed = full && sc > 0.0f;  // else every block is re-walked
+    const float ftsc = armed ? fastThr * sc : 0.0f;  // exact: sc is a power of two
+    uint32_t wlpk[U];  // the lane's part of the packed steps: the same in both fields
+#pragma unroll
+    for (int f = 0; f < U; ++f) wlpk[f] = (uint32_t)(int32_t)rintf((float)WL[f] * sc) * 65537u;
+    V GA = G, GB = G;
+    V ynext = s_y[tid];  // pair 1 flips high spin U in both blocks
+    for (uint32_t T = 0; T < half; ++T) {
+      const uint32_t TB = T + half;
+      const uint32_t* recA = tab + (size_t)T * kRecWords;
+      const uint32_t* recB = tab + (size_t)TB * kRecWords;
+      V ra[2 + U], rb[2 + U];
+#pragma unroll
+      for (int k = 0; k < 2 + U; ++k) {
+        ra[k] = (V)__uint_as_float(recA[k]);
+        rb[k] = (V)__uint_as_float(recB[k]);
+      }
+      uint32_t rpk[U];
+#pragma unroll
+      for (int f = 0; f < U; ++f) rpk[f] = f < kPkInA ? recA[kPkWord + f] : recB[kPkWord + f - kPkInA];
+      const V ycur = ynext;
+      if (T + 1 < half) ynext = s_y[__builtin_ctz(T + 1) * kEnumBlock + tid];
+      const bool odd = T & 1u;
+      if (T == 0) {
+        const float fb = fresh_g(TB, rb[1]);
+        GB = valid ? (V)fb : G;
+      } else {
+        // boundary step of both blocks: flip high spin U + c, old value +1
+        // iff bit c+1 of the block index is set
+        const int c = __builtin_ctz(T);
+        GA = ((T >> (c + 1)) & 1u) ? GA + ycur : GA - ycur;
+        GB = ((TB >> (c + 1)) & 1u) ? GB + ycur : GB - ycur;
+        GA = GA + ra[0];
+        GB = GB + rb[0];
+        if (!kInt && (T & (kReBlocks - 1)) == 0) {
+          const float fa = valid ? fresh_g(T, ra[1]) : (float)GA;
+          const float fb = valid ? fresh_g(TB, rb[1]) : (float)GB;
+          drift = fmaxf(drift, fmaxf(fabsf((float)GA - fa), fabsf((float)GB - fb)));
+          GA = (V)fa;
+          GB = (V)fb;
+        }
+      }
+      // fixed-point start values and packed steps
+      // (lanes past the chunk's end hold no state: any finite value will do)
+      const float ga = valid ? fmaf((float)GA, sc, -ftsc) : 0.0f;
+      const float gb = valid ? fmaf((float)GB, sc, -ftsc) : 0.0f;
+      const uint32_t za = (uint32_t)(int32_t)rintf(ga) + off;
+      const uint32_t zb = (uint32_t)(int32_t)rintf(gb) + off;
+      uint32_t pk[U];
+#pragma unroll
+      for (int f = 0; f < U - 1; ++f) pk[f] = wlpk[f] + rpk[f];
+      pk[U - 1] = (odd ? wlpk[U - 1] : 0u - wlpk[U - 1]) + rpk[U - 1];
+      uint32_t g = za + (zb << 16);
+      uint32_t acc = g;
+      uint32_t accs[kNSub];  // one accumulator per sub-block
+#if SG_PK_GROUP4
+      // Groups of four steps: inside group k the states are the group's first
+      // b and b - pk0, b - pk0 + s pk1, b + s pk1 (spins 0 and 1; s = +1 for
+      // odd k, -1 for even k), three adds that depend on b only; the next
+      // group starts from the last state by one step of spin ctz(4(k+1)).
+      // The ANDs pair the states before they meet the accumulator.
+      const uint32_t m0 = 0u - pk[0];
+      const uint32_t qo = pk[1] - pk[0], qe = 0u - pk[1] - pk[0];
+      const uint32_t no = pk[1], ne = 0u - pk[1];
+#pragma unroll
+      for (int k = 0; k < kSteps / 4; ++k) {
+        const bool ko = k & 1;
+        const uint32_t b = g;
+        const uint32_t g1 = b + m0;
+        const uint32_t g2 = b + (ko ? qo : qe);
+        const uint32_t g3 = b + (ko ? no : ne);
+        if (4 * k + 4 < kSteps) {
+          const int i = 4 * k + 4;
+          const int f = __builtin_ctz(i);
+          if (f == U - 1) g = g3 + pk[f];
+          else g = ((i >> (f + 1)) & 1) ? g3 + pk[f] : g3 - pk[f];
+        }
+        uint32_t t, u;
+        asm volatile("v_and_b32 %0, %1, %2" : "=v"(t) : "v"(g1), "v"(g2));
+        asm volatile("v_and_b32 %0, %1, %2" : "=v"(u) : "v"(b), "v"(g3));
+        if (k != 0 && (4 * k) % kSub == 0) {
+          // group k opens sub-block 4k / kSub
+          accs[4 * k / kSub - 1] = acc;
+          acc = 0xFFFFFFFFu;
+        }
+        asm volatile("v_and_b32 %0, %0, %1" : "+v"(acc) : "v"(t));
+        asm volatile("v_and_b32 %0, %0, %1" : "+v"(acc) : "v"(u));
+      }
+#else
+#pragma unroll
+      for (int i = 1; i < kSteps; ++i) {
+        const int f = __builtin_ctz(i);
+        if (f == U - 1) g = g + pk[f];
+        else g = ((i >> (f + 1)) & 1) ? g + pk[f] : g - pk[f];
+        if (i % kSub == 0) {
+          // step i opens sub-block i / kSub
+          accs[i / kSub - 1] = acc;
+          acc = g;
+        } else {
+          // the AND in walk order: left to the compiler, the chain of ANDs is
+          // re-associated into a tree that keeps every step's value live
+          asm volatile("v_and_b32 %0, %0, %1" : "+v"(acc) : "v"(g));
+        }
+      }
+#endif
+      accs[kNSub - 1] = acc;
+      bool pa[kNSub], pb[kNSub];
+      bool anya = false, anyb = false;
 #pragma unroll
       for (int w = 0; w < kNSub; ++w) {
-        if (kSplit && __ballot(pass[w]) == 0ull) continue;  // wave-uniform
-        V g2 = gsub[w];
-        asm volatile("" : "+v"(g2));
-        if (g2 + qv(kSub * w) <= thrE) hits[(kSub * w) >> 6] |= 1ull;
-#pragma unroll
-        for (int j = 1; j < kSub; ++j) {
-          const int i = kSub * w + j;
-          const int f = __builtin_ctz(i);
-          if (f == U - 1) g2 = g2 + W[f];
-          else g2 = ((i >> (f + 1)) & 1) ? g2 + W[f] : g2 - W[f];
-          if (g2 + qv(i) <= thrE) hits[i >> 6] |= (1ull << (i & 63));
-        }
-        if (!(valid && pass[w])) {
-#pragma unroll
-          for (int k = 0; k < kSub / 64; ++k) hits[(kSub * w) / 64 + k] = 0ull;
-        }
+        pa[w] = valid && (!armed || (accs[w] & 0x8000u) == 0u);
+        pb[w] = valid && (!armed || (accs[w] & 0x80000000u) == 0u);
+        anya = anya || pa[w];
+        anyb = anyb || pb[w];
       }
-      // one slot reservation for all hits of the wave: an exclusive scan of
-      // the lanes' hit counts, one atomic, then every lane writes its own
-      // hits from its offset (the atomic's latency is paid once per block,
-      // not once per step that hits)
-      uint32_t nh = 0;
+      const V wl = odd ? WL[U - 1] : -WL[U - 1];
+      // the fp32 steps of a block, formed only on the rare re-walk
+      auto steps = [&](const V (&r)[2 + U], V (&W)[U]) {
 #pragma unroll
-      for (int w = 0; w < kHitWords; ++w) nh += (uint32_t)__popcll(hits[w]);
-      uint32_t incl = nh;
+        for (int f = 0; f < U - 1; ++f) W[f] = WL[f] + r[2 + f];
+        W[U - 1] = wl + r[2 + U - 1];
+      };
+      // G at every sub-block start, from the block start: a low spin f < U-1
+      // that is up at step i flipped an odd number of times from -1 (net
+      // -W_f); spin U-1 flips once, at step 2^(U-1) (net +W_{U-1})
+      auto starts = [&](V G0, const V (&W)[U], V (&gs)[kNSub]) {
 #pragma unroll
-      for (int o = 1; o < kWaveLanes; o <<= 1) {
-        const uint32_t y = __shfl_up(incl, o);
-        if ((int)__lane_id() >= o) incl += y;
-      }
-      const uint32_t total = __shfl(incl, kWaveLanes - 1);
-      uint32_t base = 0;
-      if (__lane_id() == 0 && total != 0) base = atomicAdd(&P->cand_count, total);
-      uint32_t slot = __shfl(base, 0) + incl - nh;
-      const uint64_t pl = ch.prefix_base + (uint64_t)lane;
-#pragma unroll
-      for (int w = 0; w < kHitWords; ++w) {
-        uint64_t hw = hits[w];
-        while (hw) {
-          const int i = 64 * w + __builtin_ctzll(hw);
-          hw &= hw - 1ull;
-          const uint64_t t = ((uint64_t)T << U) | (uint64_t)i;
-          const uint64_t mask = (pl << n) | (t ^ (t >> 1));
-          // the walk's energy of step i, from the block start: a low spin
-          // f < U-1 that is up at step i flipped an odd number of times from
-          // -1 (net -W_f); spin U-1 flips once, at step 2^(U-1) (net +W_{U-1})
-          const uint32_t gi = (uint32_t)(i ^ (i >> 1));
-          V e = Gs;
+        for (int w = 0; w < kNSub; ++w) {
+          const uint32_t gi = gray32((uint32_t)(kSub * w));
+          V e = G0;
 #pragma unroll
           for (int f = 0; f < U - 1; ++f)
             if ((gi >> f) & 1u) e = e - W[f];
           if ((gi >> (U - 1)) & 1u) e = e + W[U - 1];
-          e = e + qv(i);
-          const uint32_t key = kInt ? key_of_i32((int32_t)e) : key_f32((float)e);
-          // beyond cap the mask is dropped; the merge sees cand_count > cap
-          // and asks for another pass over the chunk
-          if (slot < cand_cap) {
-            cand[slot] = mask;
-            ckey[slot] = key;
-          }
-          ++slot;
+          gs[w] = e;
+        }
+      };
+      if (__ballot(anya) != 0ull) {
+        V W[U], gs[kNSub];
+        steps(ra, W);
+        starts(GA, W, gs);
+        rewalk(T, W, gs, pa);
+      }
+      if (__ballot(anyb) != 0ull) {
+        V W[U], gs[kNSub];
+        steps(rb, W);
+        starts(GB, W, gs);
+        rewalk(TB, W, gs, pb);
+      }
+      // the blocks end with spin U-1 up and every other low spin back down
+      GA = GA + (wl + ra[2 + U - 1]);
+      GB = GB + (wl + rb[2 + U - 1]);
+    }
+  } else {
+    V ynext = nblocks > 1 ? s_y[tid] : (V)0;  // block 1 flips high spin U
+
+    for (uint32_t T = 0; T < nblocks; ++T) {
+      const uint32_t* rec = tab + (size_t)T * kRecWords;
+      V rw[2 + U];
+#pragma unroll
+      for (int k = 0; k < 2 + U; ++k)
+        rw[k] = kWF ? (V)__uint_as_float(rec[k]) : (V)(int32_t)rec[k];
+      const V ycur = ynext;
+      if (T + 1 < nblocks) ynext = s_y[__builtin_ctz(T + 1) * kEnumBlock + tid];
+
+      if (T != 0) {
+        // boundary step: flip high spin g = U + c whose old value is +1 iff bit
+        // c+1 of T is set
+        const int c = __builtin_ctz(T);
+        const bool up = (T >> (c + 1)) & 1u;
+        G = up ? G + ycur : G - ycur;
+        G = G + rw[0];
+        if (!kInt && (T & (kReBlocks - 1)) == 0) {
+          // fresh G = E_P - sum_f s_f y_f + R(T) in fp32 from the lane's fields
+          const float fresh = valid ? fresh_g(T, rw[1]) : (float)G;
+          drift = fmaxf(drift, fabsf((float)G - fresh));
+          G = (V)fresh;
         }
       }
+
+      V W[U];
+#pragma unroll
+      for (int f = 0; f < U - 1; ++f) W[f] = WL[f] + rw[2 + f];
+      W[U - 1] = ((T & 1u) ? WL[U - 1] : -WL[U - 1]) + rw[2 + U - 1];
+
+      // 2^U - 1 inner steps: one add per state, one 3-input min per two states
+      V msub[kNSub], gsub[kNSub];
+      gsub[0] = G;
+      V m = G;
+#pragma unroll
+      for (int i = 1; i < kSteps; i += 2) {
+        // odd step i flips spin 0; its old value is bit 1 of i
+        G = ((i >> 1) & 1) ? G + W[0] : G - W[0];
+        const V Ga = G;
+        if (i + 1 < kSteps) {
+          const int f = __builtin_ctz(i + 1);
+          if (f == U - 1) G = G + W[f];
+          else G = (((i + 1) >> (f + 1)) & 1) ? G + W[f] : G - W[f];
+          if ((i + 1) % kSub == 0) {
+            // step i closes sub-block (i + 1) / kSub - 1; step i + 1 opens the next
+            msub[(i + 1) / kSub - 1] = Num<V>::mn(m, Ga);
+            gsub[(i + 1) / kSub] = G;
+            m = G;
+          } else {
+            m = Num<V>::mn(Num<V>::mn(m, Ga), G);
+          }
+        } else {
+          msub[kNSub - 1] = Num<V>::mn(m, Ga);
+        }
+      }
+
+      bool pass[kNSub];
+      bool any = false;
+#pragma unroll
+      for (int w = 0; w < kNSub; ++w) {
+        pass[w] = msub[w] <= fastThr;
+        any = any || pass[w];
+      }
+      if (__ballot(any) != 0ull) rewalk(T, W, gsub, pass);
     }
   }
 
@@ -1183,12 +1417,15 @@ hipError_t launch_prep(bool isint, const Batch& bt, hipStream_t st) {
 }
 
 // records of n = U .. ncap (at table_base8 for U = kUWide)
-hipError_t launch_tables(bool isint, int U, const Batch& bt, int ncap, hipStream_t st) {
+// paired: also write the packed steps of the paired walk
+hipError_t launch_tables(bool isint, int U, const Batch& bt, int ncap, bool paired,
+                         hipStream_t st) {
   if ((U != kU && U != kUWide) || ncap < U) return hipErrorInvalidValue;
   const int64_t total = ((int64_t)1 << (ncap - U + 1)) - 1;  // search records
   const dim3 grid((unsigned)((total + 255) / 256), (unsigned)bt.B);
 #define SG_TABLES(I, UV) \
-  hipLaunchKernelGGL((k_tables<I, false, UV>), grid, dim3(256), 0, st, bt, ncap, nullptr)
+  hipLaunchKernelGGL((k_tables<I, false, UV>), grid, dim3(256), 0, st, bt, ncap, nullptr, \
+                     paired ? 1 : 0)
   if (isint) {
     if (U == kU) SG_TABLES(true, kU);
     else SG_TABLES(true, kUWide);
@@ -1206,11 +1443,18 @@ hipError_t launch_tables64(const Batch& bt, int ncap, int U, double* out, hipStr
   const int64_t total = ((int64_t)1 << (ncap - U + 1)) - 1;
   const dim3 grid((unsigned)((total + 255) / 256), (unsigned)bt.B);
   if (U == kLzU)
-    hipLaunchKernelGGL((k_tables<false, true, kLzU>), grid, dim3(256), 0, st, bt, ncap, (void*)out);
+    hipLaunchKernelGGL((k_tables<false, true, kLzU>), grid, dim3(256), 0, st, bt, ncap, (void*)out,
+                       0);
   else
-    hipLaunchKernelGGL((k_tables<false, true, kLzUF>), grid, dim3(256), 0, st, bt, ncap, (void*)out);
+    hipLaunchKernelGGL((k_tables<false, true, kLzUF>), grid, dim3(256), 0, st, bt, ncap, (void*)out,
+                       0);
   return hipGetLastError();
 }
+
+// The paired walk takes the chunks (single searches) and levels (batches)
+// with blocks of kUWide and at least two high spins (its tables hold the
+// packed steps of those n).
+bool enum_paired(int U, int n) { return U == kUWide && n >= kUWide + 2; }
 
 // split: test the bound per 64-step sub-block (batched searches)
 hipError_t launch_enum(bool isint, int U, bool split, const Batch& bt, const Chunk& ch, int ninst,
@@ -1218,13 +1462,21 @@ hipError_t launch_enum(bool isint, int U, bool split, const Batch& bt, const Chu
   if ((U != kU && U != kUWide) || ch.n < U) return hipErrorInvalidValue;
   const int bpi = (int)((ch.lanes + kEnumBlock - 1) / kEnumBlock);
   const dim3 grid((unsigned)((int64_t)bpi * ninst));
-#define SG_ENUM(I, UV, SP)                                                                 \
-  hipLaunchKernelGGL((k_enum<I, UV, SP>), grid, dim3(kEnumBlock), 0, st, bt, bt.J, bt.h,  \
+#define SG_ENUM(I, UV, SP, PK)                                                                 \
+  hipLaunchKernelGGL((k_enum<I, UV, SP, PK>), grid, dim3(kEnumBlock), 0, st, bt, bt.J, bt.h,  \
                      (const uint32_t*)bt.table, (const uint32_t*)bt.qtab, ch, bpi)
-#define SG_ENUM_U(I, SP)          \
-  if (U == kU) SG_ENUM(I, kU, SP); \
-  else SG_ENUM(I, kUWide, SP)
-  if (isint) {
+#define SG_ENUM_U(I, SP)                 \
+  if (U == kU) SG_ENUM(I, kU, SP, false); \
+  else SG_ENUM(I, kUWide, SP, false)
+  if (enum_paired(U, ch.n)) {
+    if (isint) {
+      if (split) SG_ENUM(true, kUWide, true, true);
+      else SG_ENUM(true, kUWide, false, true);
+    } else {
+      if (split) SG_ENUM(false, kUWide, true, true);
+      else SG_ENUM(false, kUWide, false, true);
+    }
+  } else if (isint) {
     if (split) SG_ENUM_U(true, true);
     else SG_ENUM_U(true, false);
   } else {
@@ -1287,10 +1539,12 @@ int enum_occupancy_t() {
       blocks = 0;
     best = blocks < best ? blocks : best;
   };
-  take((const void*)k_enum<I, kU, false>);
-  take((const void*)k_enum<I, kUWide, false>);
-  take((const void*)k_enum<I, kU, true>);
-  take((const void*)k_enum<I, kUWide, true>);
+  take((const void*)k_enum<I, kU, false, false>);
+  take((const void*)k_enum<I, kUWide, false, false>);
+  take((const void*)k_enum<I, kU, true, false>);
+  take((const void*)k_enum<I, kUWide, true, false>);
+  take((const void*)k_enum<I, kUWide, false, true>);
+  take((const void*)k_enum<I, kUWide, true, true>);
   return best;
 }
 

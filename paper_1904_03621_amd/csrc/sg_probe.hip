@@ -10,6 +10,7 @@ namespace sg {
 
 constexpr int kProbeIters = 4096;
 constexpr int kProbeThreads = 256;
+constexpr int kProbeMixBase = 21;  // first instruction-mix code (after the single kinds)
 
 // Instruction kinds measured (one asm template each; %0 accumulates, %1 and
 // %2 are loop-invariant operands).
@@ -31,7 +32,10 @@ constexpr int kProbeThreads = 256;
   X(14, "v_pk_add_u16 %0, %0, %1")                      \
   X(15, "v_pk_min_i16 %0, %0, %1")                      \
   X(16, "v_exp_f32 %0, %1")                             \
-  X(17, "v_sub_u32 %0, %1, %0")
+  X(17, "v_sub_u32 %0, %1, %0")                         \
+  X(18, "v_and_b32 %0, %0, %1")                         \
+  X(19, "v_cvt_i32_f32 %0, %1")                         \
+  X(20, "v_lshl_add_u32 %0, %0, 16, %1")
 
 template <int kOp>
 __global__ __launch_bounds__(kProbeThreads) void k_probe(uint32_t seed, uint32_t* out) {
@@ -62,6 +66,60 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe(uint32_t seed, uint32_t
   if (x == 0x12345678u) out[0] = t;  // keeps the chains live
 }
 
+// Instruction mixes of the search walk's inner steps, 8 independent chains per
+// lane, each asm block two Gray steps (two states):
+//   kMix 0 (fp32 walk): ga = g + w0; g = ga + w1; m = min3(m, ga, g)
+//          -- two adds and one 3-input min, 3 instructions per 2 states;
+//   kMix 1 (two 16-bit fields per 32-bit word): g += p0; a &= g; g -= p1; a &= g
+//          -- an integer add and an AND per step, 4 instructions per 2 states.
+//   kMix 2: kMix 1 with one chain per lane (the walk's dependence: every add
+//          waits for the last, every AND for the last AND and its add);
+//   kMix 3: kMix 1 with two chains per lane;
+//   kMix 4: kMix 0 with one chain per lane.
+constexpr int kMixInsts[5] = {3, 4, 4, 4, 3};
+
+template <int kMix>
+__global__ __launch_bounds__(kProbeThreads) void k_probe_mix(uint32_t seed, uint32_t* out) {
+  constexpr int kChains = kMix == 2 || kMix == 4 ? 1 : kMix == 3 ? 2 : 8;
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t g[8], m[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    g[k] = 0x3f800000u | ((t + k) & 0xffu);
+    m[k] = g[k];
+  }
+  const uint32_t w0 = 0x33800000u + (seed & 7u), w1 = 0xb3800000u + (seed & 3u);
+  for (int it = 0; it < kProbeIters; ++it) {
+#pragma unroll
+    for (int u = 0; u < 4 * 8 / kChains; ++u) {
+#pragma unroll
+      for (int k = 0; k < kChains; ++k) {
+        uint32_t ga;
+        if (kMix == 0 || kMix == 4) {
+          asm volatile(
+              "v_add_f32 %1, %0, %3\n\t"
+              "v_add_f32 %0, %1, %4\n\t"
+              "v_min3_f32 %2, %2, %1, %0"
+              : "+v"(g[k]), "=&v"(ga), "+v"(m[k])
+              : "v"(w0), "v"(w1));
+        } else {
+          asm volatile(
+              "v_add_u32 %0, %0, %2\n\t"
+              "v_and_b32 %1, %1, %0\n\t"
+              "v_sub_u32 %0, %0, %3\n\t"
+              "v_and_b32 %1, %1, %0"
+              : "+v"(g[k]), "+v"(m[k])
+              : "v"(w0), "v"(w1));
+        }
+      }
+    }
+  }
+  uint32_t x = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) x ^= g[k] ^ m[k];
+  if (x == 0x12345678u) out[0] = t;  // keeps the chains live
+}
+
 // Lane-instructions per second of instruction kind `op` (SG_PROBE_OPS), over
 // `waves_per_simd` resident waves per SIMD on every CU.  Returns < 0 on error.
 double probe_valu(int op, int waves_per_simd) {
@@ -85,6 +143,21 @@ double probe_valu(int op, int waves_per_simd) {
     break;
       SG_PROBE_OPS(L)
 #undef L
+      case kProbeMixBase:
+        hipLaunchKernelGGL(k_probe_mix<0>, dim3(blocks), dim3(kProbeThreads), 0, st, seed, out);
+        break;
+      case kProbeMixBase + 1:
+        hipLaunchKernelGGL(k_probe_mix<1>, dim3(blocks), dim3(kProbeThreads), 0, st, seed, out);
+        break;
+      case kProbeMixBase + 2:
+        hipLaunchKernelGGL(k_probe_mix<2>, dim3(blocks), dim3(kProbeThreads), 0, st, seed, out);
+        break;
+      case kProbeMixBase + 3:
+        hipLaunchKernelGGL(k_probe_mix<3>, dim3(blocks), dim3(kProbeThreads), 0, st, seed, out);
+        break;
+      case kProbeMixBase + 4:
+        hipLaunchKernelGGL(k_probe_mix<4>, dim3(blocks), dim3(kProbeThreads), 0, st, seed, out);
+        break;
       default: break;
     }
   };
@@ -96,7 +169,8 @@ double probe_valu(int op, int waves_per_simd) {
   if (hipEventSynchronize(b) == hipSuccess) {
     float ms = 0.0f;
     (void)hipEventElapsedTime(&ms, a, b);
-    const double lane_ops = 4.0 * (double)blocks * kProbeThreads * kProbeIters * 4 * 8;
+    const double per_asm = op >= kProbeMixBase ? kMixInsts[op - kProbeMixBase] : 1.0;
+    const double lane_ops = 4.0 * (double)blocks * kProbeThreads * kProbeIters * 4 * 8 * per_asm;
     rate = ms > 0.0f ? lane_ops / (ms * 1e-3) : -1.0;
   }
   (void)hipEventDestroy(a);
