@@ -409,7 +409,8 @@ def main() -> int:
         rates = {op: sg.sg_probe_valu(code, 8) for op, code in sg._lib.PROBE_OPS.items()}
         mixes = {op: {w: sg.sg_probe_valu(op, w) for w in (1, 2, 4, 8)}
                  for op in ("mix_f32_walk", "mix_packed_walk", "mix_packed_walk_1chain",
-                            "mix_packed_walk_2chains", "mix_f32_walk_1chain")}
+                            "mix_packed_walk_2chains", "mix_f32_walk_1chain",
+                            "mix_packed_walk_1chain_64vgpr", "mix_packed_walk_1chain_long")}
         print(json.dumps({"valu_lane_ops_per_s": rates, "waves_per_simd": 8,
                           "mix_by_waves_per_simd": mixes}), flush=True)
         return 0

@@ -84,11 +84,14 @@ typedef enum {
  *   states_out   device uint64[S]  masks, ascending by (energy, mask)
  *   energies_out device float[S]   energies of those states
  *
- * The enumeration accumulates energies incrementally in fp32 with a
- * from-scratch re-anchor every 2^10 Gray-code flips, prunes with a margin
- * that bounds the accumulated rounding, and rescores every surviving
- * candidate from scratch in fp64; the returned energies are those fp64
- * values rounded to fp32 (-0 is returned as +0).
+ * The enumeration accumulates energies incrementally in fp32 (block-start
+ * values, with the states of a block in 16-bit fixed point relative to the
+ * pruning bound where a lane walks at least 10 spins), re-anchors from
+ * scratch every 2^10 Gray-code flips (2^14 in the fixed-point walk, whose
+ * fp32 part rounds far less often), prunes with a margin that bounds the
+ * accumulated rounding, and rescores every surviving candidate from scratch
+ * in fp64; the returned energies are those fp64 values rounded to fp32 (-0
+ * is returned as +0).
  */
 sg_status sg_low_spectrum_f32(int N, const float *J, const float *h, int S,
                               uint64_t *states_out, float *energies_out,
@@ -325,7 +328,8 @@ void sg_set_kernel_timing(int enable);
  * independent chains per lane (21: two v_add_f32 and one v_min3_f32 per two
  * states, the fp32 walk; 22: v_add_u32, v_and_b32, v_sub_u32, v_and_b32 per two
  * steps, the walk over two 16-bit fields per word; 23 and 24: 22 with one
- * and two chains per lane; 25: 21 with one chain per lane), with
+ * and two chains per lane; 25: 21 with one chain per lane; 26: 23 with 57
+ * more registers live; 27: 23 as one straight run of 1024 steps), with
  * `waves_per_simd` (1..8) resident waves on every SIMD.
  * Synchronous (own stream); returns < 0 on error.  Context for the
  * enumeration kernel's roofline: which instructions issue at the doubled

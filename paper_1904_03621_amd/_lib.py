@@ -44,7 +44,8 @@ PROBE_OPS = {"v_add_f32": 0, "v_min3_f32": 1, "v_add_u32": 2, "v_min3_i32": 3, "
              "v_and_b32": 18, "v_cvt_i32_f32": 19, "v_lshl_add_u32": 20,
              # instruction mixes of the walk's steps (lane-instructions/s)
              "mix_f32_walk": 21, "mix_packed_walk": 22, "mix_packed_walk_1chain": 23,
-             "mix_packed_walk_2chains": 24, "mix_f32_walk_1chain": 25}
+             "mix_packed_walk_2chains": 24, "mix_f32_walk_1chain": 25,
+             "mix_packed_walk_1chain_64vgpr": 26, "mix_packed_walk_1chain_long": 27}
 
 
 class SgError(RuntimeError):

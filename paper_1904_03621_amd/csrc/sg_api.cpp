@@ -995,7 +995,7 @@ sg_status sg_get_run_info(void* stream, sg_run_info* out) {
 void sg_set_kernel_timing(int enable) { g_timing = enable != 0; }
 
 double sg_probe_valu(int op, int waves_per_simd) {
-  if (op < 0 || op > 25 || waves_per_simd < 1 || waves_per_simd > 8) return -1.0;
+  if (op < 0 || op > 27 || waves_per_simd < 1 || waves_per_simd > 8) return -1.0;
   return probe_valu(op, waves_per_simd);
 }
 

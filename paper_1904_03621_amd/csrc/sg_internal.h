@@ -35,6 +35,15 @@ constexpr int kMaxHigh = kMaxFree - kU;
 constexpr int kRecWords = 16;         // per-block table record (64 B: cB, R, Wu_0..U-1, U <= 14)
 constexpr int kReanchorLog2 = 10;     // fp32: fresh G every 2^10 flips
 constexpr int kReanchorBlocks = 1 << (kReanchorLog2 - kU);
+// The paired walk carries G in fp32 only from block to block (a boundary step
+// of two rounded adds, the block's net step of two, and the two roundings of
+// that step's value: 6 per block of 2^kUWide flips), so it re-anchors every
+// 2^14 flips and stays inside the rounding count the margin allows between
+// anchors for the plain walk (2^(10 - U) (2^U - 1 + 3U + 3) with U = kUWide).
+constexpr int kPkReanchorLog2 = 14;
+static_assert((1 << (kPkReanchorLog2 - kUWide)) * 6 <=
+                  (1 << (kReanchorLog2 - kUWide)) * ((1 << kUWide) - 1 + 3 * kUWide + 3),
+              "paired-walk re-anchor period exceeds the margin's rounding count");
 // The log Z walk uses blocks of its own, U low spins with fp64 records of
 // 2 + U doubles (cB, R, Wu_0..U-1): U = 6 (64 configurations) for the
 // gradient walk, U = 8 (256) for the partition sums when N >= 8.

@@ -769,7 +769,8 @@ __device__ __forceinline__ void enum_walk(const Batch& bt, const void* __restric
   };
 
   if constexpr (kPk) {
-    static_assert(!kPk || (kWF && U == kUWide), "paired walk: fp32 walks, blocks of 8");
+    static_assert(!kPk || (kWF && U == kUWide && (!kSplit || kSub == 64)),
+                  "paired walk: fp32 walks, blocks of 8, sub-blocks of 64");
     // ---- paired walk ----------------------------------------------------------
     // Blocks T and T + half (half = nblocks / 2, n >= U + 2: both of the same
     // parity) are walked together as the low and high 16-bit fields of one
@@ -795,12 +796,9 @@ __device__ __forceinline__ void enum_walk(const Batch& bt, const void* __restric
       const uint32_t TB = T + half;
       const uint32_t* recA = tab + (size_t)T * kRecWords;
       const uint32_t* recB = tab + (size_t)TB * kRecWords;
-      V ra[2 + U], rb[2 + U];
-#pragma unroll
-      for (int k = 0; k < 2 + U; ++k) {
-        ra[k] = (V)__uint_as_float(recA[k]);
-        rb[k] = (V)__uint_as_float(recB[k]);
-      }
+      // record words are read where they are used (the re-walk reads its
+      // steps itself), so that few of them stay live across the walk
+      auto rw = [&](const uint32_t* rec, int k) -> V { return (V)__uint_as_float(rec[k]); };
       uint32_t rpk[U];
 #pragma unroll
       for (int f = 0; f < U; ++f) rpk[f] = f < kPkInA ? recA[kPkWord + f] : recB[kPkWord + f - kPkInA];
@@ -808,7 +806,7 @@ __device__ __forceinline__ void enum_walk(const Batch& bt, const void* __restric
       if (T + 1 < half) ynext = s_y[__builtin_ctz(T + 1) * kEnumBlock + tid];
       const bool odd = T & 1u;
       if (T == 0) {
-        const float fb = fresh_g(TB, rb[1]);
+        const float fb = fresh_g(TB, rw(recB, 1));
         GB = valid ? (V)fb : G;
       } else {
         // boundary step of both blocks: flip high spin U + c, old value +1
@@ -816,11 +814,12 @@ __device__ __forceinline__ void enum_walk(const Batch& bt, const void* __restric
         const int c = __builtin_ctz(T);
         GA = ((T >> (c + 1)) & 1u) ? GA + ycur : GA - ycur;
         GB = ((TB >> (c + 1)) & 1u) ? GB + ycur : GB - ycur;
-        GA = GA + ra[0];
-        GB = GB + rb[0];
-        if (!kInt && (T & (kReBlocks - 1)) == 0) {
-          const float fa = valid ? fresh_g(T, ra[1]) : (float)GA;
-          const float fb = valid ? fresh_g(TB, rb[1]) : (float)GB;
+        GA = GA + rw(recA, 0);
+        GB = GB + rw(recB, 0);
+        constexpr uint32_t kPkReBlocks = 1u << (kPkReanchorLog2 - U);
+        if (!kInt && (T & (kPkReBlocks - 1)) == 0) {
+          const float fa = valid ? fresh_g(T, rw(recA, 1)) : (float)GA;
+          const float fb = valid ? fresh_g(TB, rw(recB, 1)) : (float)GB;
           drift = fmaxf(drift, fmaxf(fabsf((float)GA - fa), fabsf((float)GB - fb)));
           GA = (V)fa;
           GB = (V)fb;
@@ -836,75 +835,55 @@ __device__ __forceinline__ void enum_walk(const Batch& bt, const void* __restric
 #pragma unroll
       for (int f = 0; f < U - 1; ++f) pk[f] = wlpk[f] + rpk[f];
       pk[U - 1] = (odd ? wlpk[U - 1] : 0u - wlpk[U - 1]) + rpk[U - 1];
+      // Four sub-blocks of 64 steps in a loop.  Steps 64w + j, j = 1..63,
+      // flip spin ctz(j) <= 5 with the sign of step j of sub-block 0, except
+      // spin 5 (j = 32), whose sign alternates with w; step 64(w + 1) flips
+      // spin 6 (down, then up) or 7.  (Unrolled over the whole block, the same
+      // steps measured 43% of the VALU instructions issued in pairs against
+      // 81% for the loop, and 18% slower.)
+      // fired (batches): bit w (field A) / bit 8 + w (field B) set when
+      // sub-block w may hold a state below the bound
       uint32_t g = za + (zb << 16);
-      uint32_t acc = g;
-      uint32_t accs[kNSub];  // one accumulator per sub-block
-#if SG_PK_GROUP4
-      // Groups of four steps: inside group k the states are the group's first
-      // b and b - pk0, b - pk0 + s pk1, b + s pk1 (spins 0 and 1; s = +1 for
-      // odd k, -1 for even k), three adds that depend on b only; the next
-      // group starts from the last state by one step of spin ctz(4(k+1)).
-      // The ANDs pair the states before they meet the accumulator.
-      const uint32_t m0 = 0u - pk[0];
-      const uint32_t qo = pk[1] - pk[0], qe = 0u - pk[1] - pk[0];
-      const uint32_t no = pk[1], ne = 0u - pk[1];
+      uint32_t acc = 0xFFFFFFFFu;
+      uint32_t fired = 0u;
+      const uint32_t pk5[2] = {0u - pk[5], pk[5]};
+#pragma nounroll
+      for (int w = 0; w < kSteps / 64; ++w) {
+        const uint32_t p5 = pk5[w & 1];
+        uint32_t accw = g;  // state 64w
 #pragma unroll
-      for (int k = 0; k < kSteps / 4; ++k) {
-        const bool ko = k & 1;
-        const uint32_t b = g;
-        const uint32_t g1 = b + m0;
-        const uint32_t g2 = b + (ko ? qo : qe);
-        const uint32_t g3 = b + (ko ? no : ne);
-        if (4 * k + 4 < kSteps) {
-          const int i = 4 * k + 4;
-          const int f = __builtin_ctz(i);
-          if (f == U - 1) g = g3 + pk[f];
-          else g = ((i >> (f + 1)) & 1) ? g3 + pk[f] : g3 - pk[f];
+        for (int j = 1; j < 64; ++j) {
+          const int f = __builtin_ctz(j);
+          if (f == 5) g = g + p5;
+          else g = ((j >> (f + 1)) & 1) ? g + pk[f] : g - pk[f];
+          // the AND in walk order: left to the compiler, the chain of ANDs
+          // is re-associated into a tree that keeps every step's value live
+          asm volatile("v_and_b32 %0, %0, %1" : "+v"(accw) : "v"(g));
         }
-        uint32_t t, u;
-        asm volatile("v_and_b32 %0, %1, %2" : "=v"(t) : "v"(g1), "v"(g2));
-        asm volatile("v_and_b32 %0, %1, %2" : "=v"(u) : "v"(b), "v"(g3));
-        if (k != 0 && (4 * k) % kSub == 0) {
-          // group k opens sub-block 4k / kSub
-          accs[4 * k / kSub - 1] = acc;
-          acc = 0xFFFFFFFFu;
-        }
-        asm volatile("v_and_b32 %0, %0, %1" : "+v"(acc) : "v"(t));
-        asm volatile("v_and_b32 %0, %0, %1" : "+v"(acc) : "v"(u));
-      }
-#else
-#pragma unroll
-      for (int i = 1; i < kSteps; ++i) {
-        const int f = __builtin_ctz(i);
-        if (f == U - 1) g = g + pk[f];
-        else g = ((i >> (f + 1)) & 1) ? g + pk[f] : g - pk[f];
-        if (i % kSub == 0) {
-          // step i opens sub-block i / kSub
-          accs[i / kSub - 1] = acc;
-          acc = g;
+        if (kSplit) {
+          fired |= ((((accw >> 15) & 1u) ^ 1u) << w) | ((((accw >> 31) & 1u) ^ 1u) << (8 + w));
         } else {
-          // the AND in walk order: left to the compiler, the chain of ANDs is
-          // re-associated into a tree that keeps every step's value live
-          asm volatile("v_and_b32 %0, %0, %1" : "+v"(acc) : "v"(g));
+          acc &= accw;
         }
+        if (w + 1 < kSteps / 64) g = g + (w == 1 ? pk[U - 1] : (w == 0 ? 0u - pk[6] : pk[6]));
       }
-#endif
-      accs[kNSub - 1] = acc;
       bool pa[kNSub], pb[kNSub];
       bool anya = false, anyb = false;
 #pragma unroll
       for (int w = 0; w < kNSub; ++w) {
-        pa[w] = valid && (!armed || (accs[w] & 0x8000u) == 0u);
-        pb[w] = valid && (!armed || (accs[w] & 0x80000000u) == 0u);
+        const bool fa = kSplit ? ((fired >> w) & 1u) != 0u : (acc & 0x8000u) == 0u;
+        const bool fb = kSplit ? ((fired >> (8 + w)) & 1u) != 0u : (acc & 0x80000000u) == 0u;
+        pa[w] = valid && (!armed || fa);
+        pb[w] = valid && (!armed || fb);
         anya = anya || pa[w];
         anyb = anyb || pb[w];
       }
       const V wl = odd ? WL[U - 1] : -WL[U - 1];
       // the fp32 steps of a block, formed only on the rare re-walk
-      auto steps = [&](const V (&r)[2 + U], V (&W)[U]) {
+      auto steps = [&](const uint32_t* rec, V (&W)[U]) {
 #pragma unroll
-        for (int f = 0; f < U - 1; ++f) W[f] = WL[f] + r[2 + f];
-        W[U - 1] = wl + r[2 + U - 1];
+        for (int f = 0; f < U - 1; ++f) W[f] = WL[f] + rw(rec, 2 + f);
+        W[U - 1] = wl + rw(rec, 2 + U - 1);
       };
       // G at every sub-block start, from the block start: a low spin f < U-1
       // that is up at step i flipped an odd number of times from -1 (net
@@ -923,19 +902,19 @@ __device__ __forceinline__ void enum_walk(const Batch& bt, const void* __restric
       };
       if (__ballot(anya) != 0ull) {
         V W[U], gs[kNSub];
-        steps(ra, W);
+        steps(recA, W);
         starts(GA, W, gs);
         rewalk(T, W, gs, pa);
       }
       if (__ballot(anyb) != 0ull) {
         V W[U], gs[kNSub];
-        steps(rb, W);
+        steps(recB, W);
         starts(GB, W, gs);
         rewalk(TB, W, gs, pb);
       }
       // the blocks end with spin U-1 up and every other low spin back down
-      GA = GA + (wl + ra[2 + U - 1]);
-      GB = GB + (wl + rb[2 + U - 1]);
+      GA = GA + (wl + rw(recA, 2 + U - 1));
+      GB = GB + (wl + rw(recB, 2 + U - 1));
     }
   } else {
     V ynext = nblocks > 1 ? s_y[tid] : (V)0;  // block 1 flips high spin U

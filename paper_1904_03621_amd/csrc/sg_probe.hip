@@ -75,12 +75,17 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe(uint32_t seed, uint32_t
 //   kMix 2: kMix 1 with one chain per lane (the walk's dependence: every add
 //          waits for the last, every AND for the last AND and its add);
 //   kMix 3: kMix 1 with two chains per lane;
-//   kMix 4: kMix 0 with one chain per lane.
-constexpr int kMixInsts[5] = {3, 4, 4, 4, 3};
+//   kMix 4: kMix 0 with one chain per lane;
+//   kMix 5: kMix 2 with 57 more registers live through the loop (the walk
+//          kernel's register footprint: 64 VGPRs per lane at 8 waves/SIMD);
+//   kMix 6: kMix 2 unrolled into one straight run of 1024 steps per loop
+//          iteration (the walk kernel's long unrolled blocks).
+constexpr int kMixInsts[7] = {3, 4, 4, 4, 3, 4, 4};
 
 template <int kMix>
 __global__ __launch_bounds__(kProbeThreads) void k_probe_mix(uint32_t seed, uint32_t* out) {
-  constexpr int kChains = kMix == 2 || kMix == 4 ? 1 : kMix == 3 ? 2 : 8;
+  constexpr int kChains = kMix == 2 || kMix == 4 || kMix >= 5 ? 1 : kMix == 3 ? 2 : 8;
+  constexpr int kUnroll = kMix == 6 ? 16 : 1;  // asm blocks per chain and loop pass: x kUnroll
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   uint32_t g[8], m[8];
 #pragma unroll
@@ -89,9 +94,16 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe_mix(uint32_t seed, uint
     m[k] = g[k];
   }
   const uint32_t w0 = 0x33800000u + (seed & 7u), w1 = 0xb3800000u + (seed & 3u);
-  for (int it = 0; it < kProbeIters; ++it) {
+  uint32_t x[57];
 #pragma unroll
-    for (int u = 0; u < 4 * 8 / kChains; ++u) {
+  for (int k = 0; k < 57; ++k) x[k] = t * (k + 3) + seed;
+  for (int it = 0; it < kProbeIters / kUnroll; ++it) {
+    if (kMix == 5) {
+#pragma unroll
+      for (int k = 0; k < 57; ++k) asm volatile("" : "+v"(x[k]));
+    }
+#pragma unroll
+    for (int u = 0; u < 4 * 8 / kChains * kUnroll; ++u) {
 #pragma unroll
       for (int k = 0; k < kChains; ++k) {
         uint32_t ga;
@@ -114,10 +126,14 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe_mix(uint32_t seed, uint
       }
     }
   }
-  uint32_t x = 0;
+  uint32_t r = 0;
 #pragma unroll
-  for (int k = 0; k < 8; ++k) x ^= g[k] ^ m[k];
-  if (x == 0x12345678u) out[0] = t;  // keeps the chains live
+  for (int k = 0; k < 8; ++k) r ^= g[k] ^ m[k];
+  if (kMix == 5) {
+#pragma unroll
+    for (int k = 0; k < 57; ++k) r ^= x[k];
+  }
+  if (r == 0x12345678u) out[0] = t;  // keeps the chains live
 }
 
 // Lane-instructions per second of instruction kind `op` (SG_PROBE_OPS), over
@@ -157,6 +173,12 @@ double probe_valu(int op, int waves_per_simd) {
         break;
       case kProbeMixBase + 4:
         hipLaunchKernelGGL(k_probe_mix<4>, dim3(blocks), dim3(kProbeThreads), 0, st, seed, out);
+        break;
+      case kProbeMixBase + 5:
+        hipLaunchKernelGGL(k_probe_mix<5>, dim3(blocks), dim3(kProbeThreads), 0, st, seed, out);
+        break;
+      case kProbeMixBase + 6:
+        hipLaunchKernelGGL(k_probe_mix<6>, dim3(blocks), dim3(kProbeThreads), 0, st, seed, out);
         break;
       default: break;
     }
