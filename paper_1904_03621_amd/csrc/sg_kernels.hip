@@ -846,10 +846,8 @@ __device__ __forceinline__ void enum_walk(const Batch& bt, const void* __restric
       uint32_t g = za + (zb << 16);
       uint32_t acc = 0xFFFFFFFFu;
       uint32_t fired = 0u;
-      const uint32_t pk5[2] = {0u - pk[5], pk[5]};
-#pragma nounroll
-      for (int w = 0; w < kSteps / 64; ++w) {
-        const uint32_t p5 = pk5[w & 1];
+      // one 63-step sub-block from state g (its first state already in g)
+      auto sub = [&](const uint32_t p5, const int w) {
         uint32_t accw = g;  // state 64w
 #pragma unroll
         for (int j = 1; j < 64; ++j) {
@@ -865,7 +863,21 @@ __device__ __forceinline__ void enum_walk(const Batch& bt, const void* __restric
         } else {
           acc &= accw;
         }
-        if (w + 1 < kSteps / 64) g = g + (w == 1 ? pk[U - 1] : (w == 0 ? 0u - pk[6] : pk[6]));
+      };
+      // four passes, one per sub-block; spin 5 flips down in even sub-blocks
+      // and up in odd ones, and the steps between them (64: spin 6 down,
+      // 128: spin 7, 192: spin 6 up) rotate through three registers, so the
+      // loop selects nothing.  (Unrolled into two passes of two sub-blocks,
+      // the pairing fell from 86% to 72% and the search took 5% longer.)
+      uint32_t p5 = 0u - pk[5];
+      uint32_t s0 = 0u - pk[6], s1 = pk[U - 1], s2 = pk[6];
+#pragma nounroll
+      for (int w = 0; w < kSteps / 64; ++w) {
+        sub(p5, w);
+        g = g + s0;  // after the last sub-block g is not used
+        s0 = s1;
+        s1 = s2;
+        p5 = 0u - p5;
       }
       bool pa[kNSub], pb[kNSub];
       bool anya = false, anyb = false;

@@ -266,8 +266,9 @@ __device__ inline double exp2_wide(double x) {
 }
 
 // Workgroups per CU to fit: the backward for up to three beta keeps 3 waves
-// per SIMD (168 VGPRs, 3 values spilled), 28% faster than 2 waves without a
-// spill; with four beta it keeps 2 rather than spill more.  The forward fits 4
+// per SIMD (at most 168 VGPRs; no scratch since the slot targets are formed
+// again at the lane's end), 28% faster than 2 waves; with four beta it keeps
+// 2.  The forward fits 4
 // or more waves either way (5 measured no faster than 4).
 template <int kMode, int NB>
 constexpr int lz_min_blocks() {
@@ -367,7 +368,7 @@ __global__ __launch_bounds__(256, (lz_min_blocks<kMode, NB>())) void k_logz(LzAr
   // distributed free x free slots of this lane
   const int ln = tid & 63, wv = tid >> 6;
   const int nslots = 15 + U * H + H * (H - 1) / 2;
-  int sc[2] = {0, 0}, st[2] = {0, 0};
+  int sc[2] = {0, 0}, st[2] = {0, 0};  // st: set-up only (targets are formed again at the end)
   uint32_t sm[2] = {0u, 0u};
   double dacc[2] = {0.0, 0.0};
   if (kMode == 1) {
@@ -585,10 +586,17 @@ __global__ __launch_bounds__(256, (lz_min_blocks<kMode, NB>())) void k_logz(LzAr
       }
     }
   }
-  // free x free pairs from the distributed slots
+  // free x free pairs from the distributed slots (their targets are formed
+  // again here rather than carried through the walk)
 #pragma unroll
-  for (int r = 0; r < 2; ++r)
-    if (ln + 64 * r < nslots) atomicAdd(acc + st[r], dacc[r]);
+  for (int r = 0; r < 2; ++r) {
+    if (ln + 64 * r < nslots) {
+      int c2 = 0, t2 = 0;
+      uint32_t m2 = 0u;
+      lz_slot(ln + 64 * r, H, N, &c2, &m2, &t2);
+      atomicAdd(acc + t2, dacc[r]);
+    }
+  }
 }
 
 // ---------------------------------------------------------------- finalize
