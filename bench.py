@@ -41,22 +41,26 @@ OPS_PER_STATE = 1.0
 SURVEY_STATES_PER_S = 256 * 64 * 2.4e9 / 2.0
 # size of the plain device copy that calibrates the HBM byte counters
 COPY_BYTES = 512 << 20
-# HBM bytes per k_enum launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes
-# (KiB per dispatch, averaged over the 447 dispatches of one search), scaled by
-# what the same counters read for the 512 MiB copy (fetch x2.0, write x1.0);
-# valid for the k_enum source with this SHA-256 prefix only
-TRAFFIC = {"kenum_sha256_16": "34361f53900017ab", "fetch_kib": 1131293.9375 / 447,
-           "write_kib": 41122.125 / 447, "fetch_factor": 524288.0 / 262162.0, "write_factor": 1.0,
+# HBM bytes per paired-walk k_enum launch from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# passes (KiB per dispatch, averaged over the 417 paired-walk dispatches of one
+# search), scaled by what the same counters read for the 512 MiB copy (fetch
+# x2.0, write x1.0); valid for the k_enum source with this SHA-256 prefix only
+TRAFFIC = {"kenum_sha256_16": "b1272f6e9b81a0b9", "fetch_kib": 1119780.0 / 417,
+           "write_kib": 36575.0 / 417, "fetch_factor": 524288.0 / 262172.0, "write_factor": 1.0,
            "profile": "profiles/k_enum_f32_dense48_counters.md"}
 
-
-# VALU counters of the search's enumeration launches (rocprofv3 --pmc, one
-# search of this instance; see the profile), valid for the k_enum source with
-# this hash only: SQ_INSTS_VALU (wave instructions) x 64 / 2^48 per
-# configuration, SQ_ACTIVE_INST_VALU x 4 / (1024 SIMDs x cycles) as the
-# VALU-active fraction, and GRBM_GUI_ACTIVE / 8 XCDs / kernel time as sclk.
-COUNTERS = {"kenum_sha256_16": None, "valu_insts_per_state": None, "valu_active": None,
-            "sclk_ghz": None, "profile": "profiles/k_enum_f32_dense48_counters.md"}
+# VALU counters of the search's paired-walk launches (rocprofv3 --pmc, one
+# search of this instance, 417 dispatches, 5.123 s of kernel time), valid for
+# the k_enum source with this hash only: SQ_INSTS_VALU (wave instructions) x 64
+# / 2^48 per configuration; the fraction of the doubled-rate issue capacity
+# used, SQ_INSTS_VALU / (1024 SIMDs x cycles x 1/2); the share issued in pairs,
+# 2 SQ_ACTIVE_INST_VALU2 / SQ_INSTS_VALU; and sclk = GRBM_GUI_ACTIVE / 8 XCDs /
+# kernel time.
+COUNTERS = {"kenum_sha256_16": "b1272f6e9b81a0b9", "valu_insts_per_state": 4.96185e12 * 64 / 2 ** 48,
+            "valu_active": 4.96185e12 / (1024 * 9.29629e10 / 8 * 0.5),
+            "valu_paired": 2 * 2.14899e12 / 4.96185e12,
+            "sclk_ghz": 9.29629e10 / 8 / 5.123 / 1e9,
+            "profile": "profiles/k_enum_f32_dense48_counters.md"}
 
 
 def kenum_source_hash() -> str:
@@ -79,7 +83,8 @@ def valu_counters():
     source differs from the one they were taken on."""
     if COUNTERS["kenum_sha256_16"] != kenum_source_hash():
         return None
-    return {k: COUNTERS[k] for k in ("valu_insts_per_state", "valu_active", "sclk_ghz")}
+    return {k: COUNTERS[k] for k in ("valu_insts_per_state", "valu_active", "valu_paired",
+                                     "sclk_ghz")}
 
 
 def traffic_per_launch():
@@ -497,6 +502,7 @@ def main() -> int:
                 "frac_of_measured_mix_peak": achieved / mix_peak if mix_peak > 0 else None,
                 "valu_insts_per_state": counters["valu_insts_per_state"] if counters else None,
                 "valu_active": counters["valu_active"] if counters else None,
+                "valu_paired": counters["valu_paired"] if counters else None,
                 "sclk_ghz": counters["sclk_ghz"] if counters else None,
                 "survey_algorithmic_frac": value / SURVEY_STATES_PER_S}
 
