@@ -5,10 +5,10 @@ count leaves: an N = 24 search on the full device walks one 256-state block
 per lane, and a log Z batch of a few instances has no high spins.  The test
 hooks sg_debug_set_fill and sg_debug_set_batch_shift shrink the lane count the
 plans assume, so these instances run the decompositions of the N = 48 search
-(22 free spins per lane: block boundaries, high-spin fields, fp32 re-anchors
-every 2^10 flips), of the upper batch levels (16 free spins) and of the
-256 x N = 28 log Z batch (14 free spins: 6 high spins in the partition sums,
-8 in the gradient walk).  Every result is compared with the oracle state by
+(22 free spins per lane: the paired walk, block boundaries, high-spin fields,
+fp32 re-anchors every 2^14 flips), of the upper batch levels (16 free spins)
+and of the 256 x N = 28 log Z batch (14 free spins: 6 high spins in the
+partition sums, 8 in the gradient walk).  Every result is compared with the oracle state by
 state: integer instances bit-exact, fp32 ones under the tolerance rules, log Z
 within 1e-6 relative and gradients within 1e-5 of the largest entry, per
 instance and inverse temperature.
@@ -82,7 +82,8 @@ def bound(J, h):
 @pytest.mark.parametrize("N,S", [(20, 1000), (22, 1000), (24, 1000), (24, 50)])
 def test_search_f32_full_walk(orc, torch_dev, N, S):
     """fp32 dense instances (the N = 48 workload's distribution) walked with
-    up to 22 free spins per lane: margin > 0, re-anchors every 4 blocks."""
+    up to 22 free spins per lane: margin > 0, the paired walk re-anchoring
+    every 64 blocks."""
     J, h = I.random_f32_dense(N, 300 + N + S)
     with plan_fill(2):
         m, e, info = search(torch_dev, J, h, S)
@@ -93,6 +94,30 @@ def test_search_f32_full_walk(orc, torch_dev, N, S):
     # drift guard: the walk re-anchored (drift measured) inside its margin
     assert info["margin"] > 0.0
     assert 0.0 < info["max_drift"] <= info["margin"], info
+
+
+@pytest.mark.parametrize("N,S,lanes", [(14, 100, 4), (13, 100, 2), (12, 50, 1), (14, 600, 4)])
+@pytest.mark.parametrize("isint", [False, True])
+def test_paired_walk_small_geometries(orc, torch_dev, N, S, lanes, isint):
+    """The paired walk's smallest tables: n = 10 (two block pairs per lane),
+    11 and 12 free spins, in chunks that run with no threshold yet (every
+    block re-walked) and in chunks with one (the fixed-point test decides)."""
+    from paper_1904_03621_amd import _lib
+    plan = _lib.sg_debug_plan(N, S, 0, 1 << N, lanes)
+    assert min(n for _, n, _ in plan) >= 10, plan
+    if isint:
+        J, h = I.random_int_dense(N, 600 + N + lanes)
+    else:
+        J, h = I.random_f32_dense(N, 600 + N + lanes)
+    with plan_fill(lanes):
+        m, e, info = search(torch_dev, J, h, S)
+    assert info["free_bits_max"] == max(n for _, n, _ in plan), info
+    om, oe = orc.low_spectrum(J, h, S)
+    if isint:
+        check_int(m, e, om, oe, "paired N=%d lanes %d" % (N, lanes))
+    else:
+        check_f32(N, J, m, e, om, oe, lambda x: orc.energy(J, h, x),
+                  "paired N=%d lanes %d" % (N, lanes))
 
 
 @pytest.mark.parametrize("N,S,seed", [(22, 100, 1), (24, 100, 2), (24, 1000, 3)])
