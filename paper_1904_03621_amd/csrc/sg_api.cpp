@@ -630,7 +630,7 @@ sg_status lz_buffers(Workspace* w, int B, int N) {
   GROW_TRY(grow(w, &w->lzq, &w->nlzq, Bz * kMaxBeta * kLzQStride));
   GROW_TRY(grow(w, &w->lzqmin, &w->nlzqmin, Bz));
   GROW_TRY(grow(w, &w->lz_acc, &w->nlz_acc, Bz * stride));
-  GROW_TRY(grow(w, &w->lz_coef, &w->nlz_coef, Bz * kMaxBeta));
+  GROW_TRY(grow(w, &w->lz_coef, &w->nlz_coef, Bz * 2 * kMaxBeta));
   return SG_OK;
 }
 
@@ -639,9 +639,9 @@ LzArgs lz_args(Workspace* w, int B, int N, int nb, int S, const float* h, const 
   LzArgs a{};
   a.B = B;
   a.N = N;
-  // low spins per block: the partition sums take the larger blocks whenever
-  // the instance has that many spins
-  a.U = (mode == 0 && N >= kLzUF) ? kLzUF : kLzU;
+  // low spins per block (record): the larger blocks whenever the instance
+  // has that many spins
+  a.U = N >= kLzUF ? kLzUF : kLzU;
   // free spins per lane: at most kLzFree, fewer when the batch alone would
   // not give every resident lane of the device a prefix
   a.n = std::min(kLzFree, N);

@@ -161,7 +161,8 @@ struct LzArgs {
   const float* h_in;    // [B][N] fields
   const float* beta;    // [nb]
   const float* e0;      // [B] shift (ground energy)
-  double* coef;         // [B][kMaxBeta]: backward weights g_b beta_b / Z_b
+  double* coef;         // [B][2][kMaxBeta]: backward weights g_b beta_b / Z_b, then
+                        // -beta_b / ln 2
   double* acc;          // forward: [B][kMaxBeta]; backward: [B][N*N + N]
   int acc_stride;
   uint32_t* sticky;

@@ -25,13 +25,16 @@
 // with bq (U = 8 when N >= 8: 16 x 16; else U = 6: 8 x 8); block sums are
 // fp32, lane totals fp64, one fp64 atomic per wave and beta.
 //
-// Backward (kMode 1, U = 6): the gradient of sum_b g_b log Z(beta_b) needs, for every
+// Backward: the gradient of sum_b g_b log Z(beta_b) needs, for every
 // pair and every spin, sum_s omega(s) s_i s_j and sum_s omega(s) s_i with the
 // combined weight omega = sum_b (g_b beta_b / Z_b) exp(-beta_b (E - E0)).
-// omega is formed for each of the 64 states of a block from the factors, and
-// the block contributes the order <= 2 Walsh coefficients of omega over the
-// low spins (total, 6 singles, 15 pairs), built hierarchically over the Gray
-// order of the block (the halves of a group differ in one spin).  Prefix spins
+// omega is formed for each of the 64 states of a block of 6 low spins from the
+// factors, and the block contributes the order <= 2 Walsh coefficients of
+// omega over those spins (total, 6 singles, 15 pairs), built hierarchically
+// over the Gray order of the block (the halves of a group differ in one
+// spin).  When N >= 8 (k_lz_grad8) the blocks of 6 are the four sub-blocks
+// of a record of 8 low spins, whose bound and factors are formed once per
+// record; with N = 7, blocks of 6 (k_logz<1>).  Prefix spins
 // are constant per lane and high spins constant per block, so:
 //   prefix-involving moments  <- per-lane fp64 totals (Omega, A_f, M_g) times
 //                                prefix signs, reduced at the end of the lane;
@@ -54,14 +57,35 @@ constexpr int kCoefStride = 24;  // a row's coefficient sums in LDS (16-byte row
 // bq tables of every beta, the accumulators cleared, E0 (forward) or the
 // combined gradient weights g_b beta_b / Z~_b (backward).
 
-// U low spins per block; the forward reads bq by configuration only (2^U
-// entries per beta), the backward also by Gray step for both block parities.
+// bq floats per beta: the forward reads bq by configuration (2^U entries);
+// the gradient walk over blocks of 6 by configuration and by Gray step for
+// both block parities (3 x 64), and over records of 8 by sub-block and Gray
+// step (4 x 64).
+template <int kMode, int U>
+constexpr int lz_q_floats() {
+  return kMode == 0 ? (1 << U) : (U == kLzUF ? (1 << U) : 3 * (1 << U));
+}
+
+// Low configuration (bit f: spin f up) of entry r of a bq table.
+template <int kMode, int U>
+__device__ inline int lz_q_config(int r) {
+  constexpr int kSteps = 1 << U;
+  if (kMode == 0) return r;
+  if (U == kLzUF) {  // sub-block j: spins 6 and 7 = gray2(j), spins 0..5 = gray6(i)
+    const int j = r >> kLzU, i = r & (kLzSteps - 1);
+    return (i ^ (i >> 1)) | ((j ^ (j >> 1)) << kLzU);
+  }
+  if (r < kSteps) return r;
+  const int i = r & (kSteps - 1);
+  return (i ^ (i >> 1)) ^ ((r >= 2 * kSteps) ? (1 << (U - 1)) : 0);
+}
+
 template <int kMode, int U>
 __global__ void k_lz_prep(LzArgs a, const float* __restrict__ J, float* lzq, double* lzqmin,
                           const float* energies, float* e0_out, const double* logz,
                           const double* grad) {
   constexpr int kSteps = 1 << U;
-  constexpr int kQ = kMode == 0 ? kSteps : 3 * kSteps;
+  constexpr int kQ = lz_q_floats<kMode, U>();
   static_assert(kQ <= kLzQStride, "bq tables exceed their stride");
   __shared__ double s_q[kSteps];
   __shared__ double s_qmin;
@@ -89,11 +113,7 @@ __global__ void k_lz_prep(LzArgs a, const float* __restrict__ J, float* lzq, dou
   const double qmin = s_qmin;
   for (int e = tid; e < a.nb * kQ; e += blockDim.x) {
     const int k = e / kQ, r = e - k * kQ;
-    int x = r;
-    if (r >= kSteps) {
-      const int i = r & (kSteps - 1);
-      x = (i ^ (i >> 1)) ^ ((r >= 2 * kSteps) ? (1 << (U - 1)) : 0);
-    }
+    const int x = lz_q_config<kMode, U>(r);
     const double bk = (double)a.beta[k];
     lzq[((size_t)b * kMaxBeta + k) * kLzQStride + r] = (float)exp(-bk * (s_q[x] - qmin));
   }
@@ -115,14 +135,16 @@ __global__ void k_lz_prep(LzArgs a, const float* __restrict__ J, float* lzq, dou
       e0_out[b] = energies[(size_t)b * a.S];
     } else {
       for (int k = 0; k < kMaxBeta; ++k) {
-        double c = 0.0;
+        double c = 0.0, c2 = 0.0;
         if (k < a.nb) {
           const double bk = (double)a.beta[k];
           // Z~_b = sum exp(-beta (E - E0)) = exp(log Z + beta E0)
           const double zt = exp(logz[(size_t)b * a.nb + k] + bk * (double)a.e0[b]);
           c = grad[(size_t)b * a.nb + k] * bk / zt;
+          c2 = -bk * 1.4426950408889634;
         }
-        a.coef[(size_t)b * kMaxBeta + k] = c;
+        a.coef[(size_t)b * 2 * kMaxBeta + k] = c;
+        a.coef[(size_t)b * 2 * kMaxBeta + kMaxBeta + k] = c2;
       }
     }
   }
@@ -141,13 +163,17 @@ struct Coefs {
 
 constexpr int pidx(int f, int g) { return g * (g - 1) / 2 + f; }
 
-template <int NB>
+// kSub: a sub-block of a record of 8 (spin 5 starts down, B scaled by d);
+// otherwise a block of 6 of either parity (spin 5's value on the first half
+// in sgn5).
+template <int NB, bool kSub>
 struct BlockWalk {
   const float (*A)[8];   // [NB][8] factor products of spins 0-2, times the beta's weight
   const float (*B)[8];   // [NB][8] factor products of spins 3-5, indexed by the Gray
                          // code's bits (block parity folded in)
-  const float* const* bq;  // [NB] -> bq by Gray step for this block's parity
-  float sgn5;            // value of spin U-1 in the block's first half
+  const float* const* bq;  // [NB] -> bq by Gray step for this block (sub-block)
+  const float* d;        // [NB] sub-block factors of spins 6 and 7 (kSub)
+  float sgn5;            // value of spin U-1 in the block's first half (!kSub)
 
   // combined weight of Gray step I of the block
   template <int I>
@@ -155,7 +181,12 @@ struct BlockWalk {
     constexpr int g = I ^ (I >> 1);
     float om = 0.0f;
 #pragma unroll
-    for (int k = 0; k < NB; ++k) om = fmaf(A[k][g & 7] * B[k][g >> 3], bq[k][I], om);
+    for (int k = 0; k < NB; ++k) {
+      float bk = B[k][g >> 3];
+      if constexpr (kSub) bk *= d[k];
+      const float t = A[k][g & 7] * bk;
+      om = k == 0 ? t * bq[k][I] : fmaf(t, bq[k][I], om);
+    }
     return om;
   }
 
@@ -178,7 +209,7 @@ struct BlockWalk {
       for (int f1 = 1; f1 < g; ++f1)
 #pragma unroll
         for (int f0 = 0; f0 < f1; ++f0) r.p[pidx(f0, f1)] = a.p[pidx(f0, f1)] + b.p[pidx(f0, f1)];
-      if (g == kLzU - 1) {
+      if (!kSub && g == kLzU - 1) {
         r.s[g] = sgn5 * (a.o - b.o);
 #pragma unroll
         for (int f = 0; f < g; ++f) r.p[pidx(f, g)] = sgn5 * (a.s[f] - b.s[f]);
@@ -477,7 +508,7 @@ __global__ __launch_bounds__(256, (lz_min_blocks<kMode, NB>())) void k_logz(LzAr
 #pragma unroll
       for (int k = 0; k < NB; ++k) {
         const double P = valid ? exp2_wide(c2[k] * Lb) : 0.0;
-        const float sk = (float)(a.coef[(size_t)b * kMaxBeta + k] * P);
+        const float sk = (float)(a.coef[(size_t)b * 2 * kMaxBeta + k] * P);
         float cp[U], cm[U];
         factors(k, cp, cm);
         cp[0] *= sk;
@@ -486,7 +517,7 @@ __global__ __launch_bounds__(256, (lz_min_blocks<kMode, NB>())) void k_logz(LzAr
         factor_products<3>(cp + 3, cm + 3, Bf[k]);
         bqs[k] = s_bq + k * kQ + kSteps * (odd ? 2 : 1);
       }
-      BlockWalk<NB> bw{Af, Bf, bqs, odd ? 1.0f : -1.0f};
+      BlockWalk<NB, false> bw{Af, Bf, bqs, nullptr, odd ? 1.0f : -1.0f};
       const Coefs C = bw.template walk<U, 0>();
       // per-lane totals for the prefix-involving moments
       Om += (double)C.o;
@@ -599,6 +630,340 @@ __global__ __launch_bounds__(256, (lz_min_blocks<kMode, NB>())) void k_logz(LzAr
   }
 }
 
+// ------------------------------------------- gradient walk over records of 8
+// The records of kLzUF = 8 low spins (those of the partition sums): spins
+// 8..n-1 are fixed per record T, and the record is walked as four sub-blocks
+// of the 64 configurations of spins 0..5, sub-block j with spins 6 and 7 set
+// to gray2(j).  Within the record
+//   E(x) = K_T + sum_{f<8} phi_f s_f + Q8(x),
+// Q8 the energy of the couplings among spins 0..7, so a sub-block's combined
+// weights are
+//   omega(x) = sum_b coef_b P_T,b prod_{f<6} c_f(s_f) * c_6(s_6) c_7(s_7) * bq8_b(x)
+// with bq8_b(x) = exp(-beta_b (Q8(x) - min Q8)) tabulated by sub-block and
+// Gray step.  The record's bound, its 24 exponentials and the factor tables
+// are formed once per 256 configurations; a sub-block scales B (spins 3-5) by
+// its factors of spins 6 and 7.  Walsh coefficients, slots and per-lane totals
+// are those of the blocks of 6, spins 6 and 7 counting as high spins.
+
+// A wave-uniform value in scalar registers.
+__device__ inline float uniform_f(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ inline double uniform_d(double v) {
+  const uint64_t u = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// Wave sums of the 22 block coefficients v[0..21].  v_permlane32_swap trades
+// the upper half-wave of coefficient i for the lower half-wave of i + 11, so
+// one add leaves each lane the sum of lanes l and l ^ 32 of one of the two;
+// v_permlane16_swap does the same between rows for i and i + 5 of the 11
+// left (the last one with itself); each lane then holds 6 sums of 4 lanes,
+// and DPP row shifts finish the row totals in each row's last lane.  Which
+// coefficient a row's u[i] totals follows from the same exchanges applied to
+// the coefficient numbers (coef_rows), so nothing here depends on which half
+// of a swap moves which way: row r ends with coefficients c_r + i (i < 5) and
+// one of the two unpaired ones in u[5].
+__device__ inline void coef_wave_sums(const float* v, float* u) {
+  float w[11];
+#pragma unroll
+  for (int i = 0; i < 11; ++i) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[i]),
+                                                    __float_as_uint(v[i + 11]), false, false);
+    w[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    const float x = w[i], z = i < 5 ? w[i + 5] : w[10];
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(i < 5 ? x : z),
+                                                    __float_as_uint(z), false, false);
+    u[i] = row_total(__uint_as_float(r[0]) + __uint_as_float(r[1]));
+  }
+}
+
+// Coefficient numbers of a lane's u[0] and u[5] after coef_wave_sums.
+__device__ inline void coef_rows(int* c0, int* c5) {
+  int w[11];
+#pragma unroll
+  for (int i = 0; i < 11; ++i) {
+    const auto r = __builtin_amdgcn_permlane32_swap((uint32_t)i, (uint32_t)(i + 11), false, false);
+    w[i] = (int)r[0];
+  }
+  const auto r0 = __builtin_amdgcn_permlane16_swap((uint32_t)w[0], (uint32_t)w[5], false, false);
+  const auto r5 = __builtin_amdgcn_permlane16_swap((uint32_t)w[10], (uint32_t)w[10], false, false);
+  *c0 = (int)r0[0];
+  *c5 = (int)r5[0];
+}
+
+template <int NB>
+__global__ __launch_bounds__(256, (lz_min_blocks<1, NB>())) void k_lz_grad8(
+    LzArgs a, const float* __restrict__ J, const float* __restrict__ h,
+    const double* __restrict__ table64, const float* __restrict__ lzq,
+    const double* __restrict__ lzqmin, int bpi) {
+  constexpr int U = kLzUF;                 // spins per record
+  constexpr int V = kLzU;                  // spins per sub-block (the Walsh tree's)
+  constexpr int kSub = 1 << (U - V);       // sub-blocks per record
+  constexpr int kQ = lz_q_floats<1, U>();  // bq floats per beta
+  static_assert(kQ == kSub * (1 << V), "one bq row of 64 per sub-block");
+  __shared__ double s_y[kLzFree * 256];  // y_f of every free spin, read per record
+  __shared__ double s_m[kLzHigh * 256];  // per-lane totals M_k of the high spins
+  __shared__ float s_t[4 * kNCoef];
+  __shared__ float s_bq[NB * kQ];
+
+  const int b = blockIdx.x / bpi;
+  const int blk = blockIdx.x - b * bpi;
+  const int tid = threadIdx.x;
+  const int N = a.N, n = a.n, H = n - V;  // H: high spins 6..n-1 of the slots
+  for (int e = tid; e < NB * kQ; e += 256) {
+    const int k = e / kQ;
+    s_bq[e] = lzq[((size_t)b * kMaxBeta + k) * kLzQStride + (e - k * kQ)];
+  }
+  const int64_t lane = (int64_t)blk * 256 + tid;
+  const bool valid = lane < a.lanes;
+  const uint64_t p = valid ? (uint64_t)lane : 0ull;
+  const float* Jt = J + (size_t)b * N * N;
+  const float* ht = h + (size_t)b * N;
+  const double* tab = table64 + ((size_t)b * a.table_recs + (size_t)a.table_offset) * (2 + U);
+
+  // ---- per-lane init (fp64): y_f = sum_q J_fq s_q, the field on free spin f
+  // from the prefix spins; E_P the energy of the prefix spins alone
+  double ysum = 0.0, y7 = 0.0;  // sum_{f<7} y_f, y_7
+  for (int f = 0; f < n; ++f) {
+    double acc = 0.0;
+    for (int q = n; q < N; ++q) {
+      const double jq = (double)Jt[f * N + q];
+      acc += ((p >> (q - n)) & 1ull) ? jq : -jq;
+    }
+    s_y[f * 256 + tid] = acc;
+    if (f < U - 1) ysum += acc;
+    if (f == U - 1) y7 = acc;
+  }
+  double EP = 0.0;
+  for (int q = n; q < N; ++q) {
+    const double sq = ((p >> (q - n)) & 1ull) ? 1.0 : -1.0;
+    double f = (double)ht[q];
+    for (int r = q + 1; r < N; ++r) {
+      const double jr = (double)Jt[q * N + r];
+      f += ((p >> (r - n)) & 1ull) ? jr : -jr;
+    }
+    EP -= sq * f;
+  }
+  // E_P - sum_{f<8} s_f y_f at a record start: spins 0..6 down, spin 7 up in
+  // odd records
+  const double epa0 = EP + ysum + y7, epa1 = EP + ysum - y7;
+  const double base = uniform_d(lzqmin[b] - (double)a.e0[b]);
+
+  // per-beta constants, loaded (not computed) so that they stay in scalar
+  // registers
+  const double* cb = a.coef + (size_t)b * 2 * kMaxBeta;
+  double c2[NB];   // -beta / ln 2
+  float c2f2[NB];  // 2 c2, for the factor exponents
+  double cf[NB];   // the beta's gradient weight
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+    c2[k] = cb[kMaxBeta + k];
+    c2f2[k] = uniform_f((float)(2.0 * c2[k]));
+    cf[k] = cb[k];
+  }
+
+  // per-lane totals for the prefix-involving moments (M_k in LDS, updated
+  // once per record)
+  double Om = 0.0, A[V];
+#pragma unroll
+  for (int f = 0; f < V; ++f) A[f] = 0.0;
+#pragma unroll
+  for (int k = 0; k < kLzHigh; ++k) s_m[k * 256 + tid] = 0.0;
+  // distributed free x free slots of this lane
+  const int ln = tid & 63, wv = tid >> 6;
+  const int nslots = 15 + V * H + H * (H - 1) / 2;
+  int sc[2] = {0, 0};
+  uint32_t sm[2] = {0u, 0u};
+  double dacc[2] = {0.0, 0.0};
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    int t = 0;
+    if (ln + 64 * r < nslots) lz_slot(ln + 64 * r, H, N, &sc[r], &sm[r], &t);
+  }
+  // where a row's last lane leaves its coefficient totals
+  int c0 = 0, c5 = 0;
+  coef_rows(&c0, &c5);
+  float* const t0 = s_t + wv * kNCoef + c0;
+  float* const t5 = s_t + wv * kNCoef + c5;
+  const bool row_end = (ln & 15) == 15;
+  __syncthreads();  // s_y, s_bq
+
+  // field energy of the high spins 8..n-1, -sum_k s_k y_(8+k), all down at
+  // T = 0; updated by one flip per record (fp64, at most 2^(n-8) - 1 terms)
+  double gh = 0.0;
+  for (int k = U; k < n; ++k) gh += s_y[k * 256 + tid];
+
+  const uint32_t nrec = 1u << (n - U);
+  for (uint32_t T = 0; T < nrec; ++T) {
+    const double* rec = tab + (size_t)T * (2 + U);
+    const bool odd = T & 1u;
+    const uint32_t x8 = T ^ (T >> 1);  // spins 8.. of this record (bit k: spin 8 + k)
+    if (T) {
+      const int kb = __builtin_ctz(T);  // the spin that flipped
+      const double yb = 2.0 * s_y[(U + kb) * 256 + tid];
+      gh = ((x8 >> kb) & 1u) ? gh - yb : gh + yb;
+    }
+    // energy at the record start without the low-low part
+    const double G0 = (odd ? epa1 : epa0) + rec[1] + gh;
+    double phi[U];
+#pragma unroll
+    for (int f = 0; f < U - 1; ++f) phi[f] = -(s_y[f * 256 + tid] + 0.5 * rec[2 + f]);
+    phi[U - 1] = -(s_y[(U - 1) * 256 + tid] + 0.5 * (odd ? rec[2 + U - 1] : -rec[2 + U - 1]));
+    double K = odd ? G0 - phi[U - 1] : G0 + phi[U - 1];
+    double sabs = 0.0;
+#pragma unroll
+    for (int f = 0; f < U; ++f) {
+      if (f < U - 1) K += phi[f];
+      sabs += fabs(phi[f]);
+    }
+    const double Lb = K - sabs + base;  // lower bound of E - E0 over the record
+
+    // factors: c_f(s_f) at beta k is 1 for the sign that lowers phi_f s_f,
+    // 2^(2 c2 |phi_f|) for the other
+    // spins 6 and 7: a6, a7 their non-1 factors, costly when up (the sign
+    // that raises phi_f s_f is +1) or down
+    float Af[NB][8], Bf[NB][8], a6[NB], a7[NB];
+    const bool hi6 = phi[6] > 0.0, hi7 = phi[7] > 0.0;
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+      const double P = valid ? exp2_wide(c2[k] * Lb) : 0.0;
+      const float sk = (float)(cf[k] * P);
+      float cp[U], cm[U];
+#pragma unroll
+      for (int f = 0; f < U; ++f) {
+        const float af = __builtin_amdgcn_exp2f(c2f2[k] * (float)fabs(phi[f]));
+        const bool up = phi[f] > 0.0;
+        cp[f] = up ? af : 1.0f;
+        cm[f] = up ? 1.0f : af;
+      }
+      cp[0] *= sk;
+      cm[0] *= sk;
+      factor_products<3>(cp, cm, Af[k]);
+      factor_products<3>(cp + 3, cm + 3, Bf[k]);
+      a6[k] = hi6 ? cp[6] : cm[6];
+      a7[k] = hi7 ? cp[7] : cm[7];
+    }
+
+    float om_r = 0.0f, a_r[V], m6 = 0.0f, m7 = 0.0f;  // record partial sums
+#pragma unroll
+    for (int f = 0; f < V; ++f) a_r[f] = 0.0f;
+#pragma nounroll
+    for (int j = 0; j < kSub; ++j) {
+      // the bq rows are read from LDS in every sub-block instead of being
+      // held in registers
+      asm volatile("" ::: "memory");
+      const int gj = j ^ (j >> 1);  // bit 0: spin 6 up, bit 1: spin 7 up
+      const bool up6 = gj & 1, up7 = gj & 2;
+      const bool x6 = up6 == hi6, x7 = up7 == hi7;  // spin 6 (7) takes its factor
+      float d[NB];
+      const float* bqs[NB];
+#pragma unroll
+      for (int k = 0; k < NB; ++k) {
+        d[k] = (x6 ? a6[k] : 1.0f) * (x7 ? a7[k] : 1.0f);
+        bqs[k] = s_bq + k * kQ + j * (1 << V);
+      }
+      BlockWalk<NB, true> bw{Af, Bf, bqs, d, 0.0f};
+      const Coefs C = bw.template walk<V, 0>();
+      om_r += C.o;
+#pragma unroll
+      for (int f = 0; f < V; ++f) a_r[f] += C.s[f];
+      m6 += up6 ? C.o : -C.o;
+      m7 += up7 ? C.o : -C.o;
+      // wave sums of the 22 coefficients, then the slots' signed sums
+      float v[kNCoef], u[6];
+      v[0] = C.o;
+#pragma unroll
+      for (int f = 0; f < V; ++f) v[1 + f] = C.s[f];
+#pragma unroll
+      for (int k = 0; k < 15; ++k) v[1 + V + k] = C.p[k];
+      coef_wave_sums(v, u);
+      if (row_end) {
+#pragma unroll
+        for (int i = 0; i < 5; ++i) t0[i] = u[i];
+        *t5 = u[5];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const uint32_t xh = (uint32_t)gj | (x8 << 2);  // bit k: spin 6 + k
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        if (ln + 64 * r < nslots) {
+          const float tv = s_t[wv * kNCoef + sc[r]];
+          // product of the high signs in the mask: -1 per high spin that is down
+          const int downs = __popc(sm[r]) - __popc(sm[r] & xh);
+          dacc[r] += (downs & 1) ? -(double)tv : (double)tv;
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+    }
+    Om += (double)om_r;
+#pragma unroll
+    for (int f = 0; f < V; ++f) A[f] += (double)a_r[f];
+    s_m[tid] += (double)m6;
+    s_m[256 + tid] += (double)m7;
+#pragma unroll
+    for (int k = 2; k < kLzHigh; ++k)
+      if (k < H) s_m[k * 256 + tid] += ((x8 >> (k - 2)) & 1u) ? (double)om_r : -(double)om_r;
+  }
+
+  // ---- lane end: reduce over the lanes of the wave, one atomic per value
+  double* acc = a.acc + (size_t)b * a.acc_stride;
+  const bool lead = ln == 0;
+  auto sp = [&](int q) -> double { return ((p >> (q - n)) & 1ull) ? 1.0 : -1.0; };
+#pragma unroll
+  for (int f = 0; f < V; ++f) {
+    const double t = wave_sum(A[f]);
+    if (lead) atomicAdd(acc + N * N + f, t);
+  }
+  double M[kLzHigh];
+#pragma unroll
+  for (int g = 0; g < kLzHigh; ++g) {
+    M[g] = s_m[g * 256 + tid];
+    if (g < H) {
+      const double t = wave_sum(M[g]);
+      if (lead) atomicAdd(acc + N * N + V + g, t);
+    }
+  }
+  for (int q = n; q < N; ++q) {
+    const double sq = sp(q);
+    double t = wave_sum(sq * Om);
+    if (lead) atomicAdd(acc + N * N + q, t);
+    for (int r = q + 1; r < N; ++r) {
+      t = wave_sum(sq * sp(r) * Om);
+      if (lead) atomicAdd(acc + q * N + r, t);
+    }
+#pragma unroll
+    for (int f = 0; f < V; ++f) {
+      t = wave_sum(sq * A[f]);
+      if (lead) atomicAdd(acc + f * N + q, t);
+    }
+#pragma unroll
+    for (int g = 0; g < kLzHigh; ++g) {
+      if (g < H) {
+        t = wave_sum(sq * M[g]);
+        if (lead) atomicAdd(acc + (V + g) * N + q, t);
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    if (ln + 64 * r < nslots) {
+      int c = 0, t = 0;
+      uint32_t m = 0u;
+      lz_slot(ln + 64 * r, H, N, &c, &m, &t);
+      atomicAdd(acc + t, dacc[r]);
+    }
+  }
+}
+
 // ---------------------------------------------------------------- finalize
 
 __global__ void k_lz_final_fwd(LzArgs a, double* logz) {
@@ -637,6 +1002,9 @@ hipError_t launch_lz_prep(int mode, const LzArgs& a, const float* J, float* lzq,
   else if (mode == 1 && a.U == kLzU)
     hipLaunchKernelGGL((k_lz_prep<1, kLzU>), dim3(a.B), dim3(256), 0, st, a, J, lzq, lzqmin,
                        energies, e0_out, logz, grad);
+  else if (mode == 1 && a.U == kLzUF)
+    hipLaunchKernelGGL((k_lz_prep<1, kLzUF>), dim3(a.B), dim3(256), 0, st, a, J, lzq, lzqmin,
+                       energies, e0_out, logz, grad);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -650,7 +1018,18 @@ hipError_t launch_logz(int mode, const LzArgs& a, const float* J, const float* h
 #define SG_LZ_LAUNCH(M, NBV, UV)                                                          \
   hipLaunchKernelGGL((k_logz<M, NBV, UV>), grid, dim3(256), 0, st, a, J, h, table64, lzq, lzqmin, \
                      bpi)
-  if (mode == 0 && a.U == kLzUF) {
+  if (mode == 1 && a.U == kLzUF) {
+#define SG_LZ8_LAUNCH(NBV)                                                                 \
+  hipLaunchKernelGGL((k_lz_grad8<NBV>), grid, dim3(256), 0, st, a, J, h, table64, lzq, lzqmin, bpi)
+    switch (a.nb) {
+      case 1: SG_LZ8_LAUNCH(1); break;
+      case 2: SG_LZ8_LAUNCH(2); break;
+      case 3: SG_LZ8_LAUNCH(3); break;
+      case 4: SG_LZ8_LAUNCH(4); break;
+      default: return hipErrorInvalidValue;
+    }
+#undef SG_LZ8_LAUNCH
+  } else if (mode == 0 && a.U == kLzUF) {
     switch (a.nb) {
       case 1: SG_LZ_LAUNCH(0, 1, kLzUF); break;
       case 2: SG_LZ_LAUNCH(0, 2, kLzUF); break;
