@@ -324,15 +324,17 @@ __global__ __launch_bounds__(256, (lz_min_blocks<kMode, NB>())) void k_logz(LzAr
   __shared__ double s_y[kHigh * 256];
   __shared__ __align__(16) float s_c[kMode ? 4 * 4 * kCoefStride : 1];
   __shared__ float s_t[kMode ? 4 * kNCoef : 1];
-  __shared__ float s_bq[NB * kQ];  // this instance's bq tables (uniform reads)
+  __shared__ float s_bq[kMode ? NB * kQ : 1];  // the gradient walk's bq tables
 
   const int b = blockIdx.x / bpi;
   const int blk = blockIdx.x - b * bpi;
   const int tid = threadIdx.x;
   const int N = a.N, n = a.n, H = n - U;
-  for (int e = tid; e < NB * kQ; e += 256) {
-    const int k = e / kQ;
-    s_bq[e] = lzq[((size_t)b * kMaxBeta + k) * kLzQStride + (e - k * kQ)];
+  if (kMode == 1) {
+    for (int e = tid; e < NB * kQ; e += 256) {
+      const int k = e / kQ;
+      s_bq[e] = lzq[((size_t)b * kMaxBeta + k) * kLzQStride + (e - k * kQ)];
+    }
   }
   const int64_t lane = (int64_t)blk * 256 + tid;
   const bool valid = lane < a.lanes;
@@ -474,11 +476,11 @@ __global__ __launch_bounds__(256, (lz_min_blocks<kMode, NB>())) void k_logz(LzAr
         factors(k, cp, cm);
         factor_products<U / 2>(cp, cm, Af);
         factor_products<U / 2>(cp + U / 2, cm + U / 2, Bf);
-        // bq by configuration (uniform LDS reads), one row of 2^(U/2) read
-        // ahead of its products.  The empty asm after each row ties the
-        // row's products (through S) to the reads (memory clobber), so later
-        // rows are not fetched early into registers.
-        const float* q = s_bq + k * kQ;
+        // bq by configuration (wave-uniform, so scalar loads into SGPRs),
+        // one row of 2^(U/2) read ahead of its products.  The empty asm
+        // after each row ties the row's products (through S) to the reads
+        // (memory clobber), so later rows are not fetched early.
+        const float* q = lzq + ((size_t)b * kMaxBeta + k) * kLzQStride;
         float qc[kM], qn[kM];
 #pragma unroll
         for (int x1 = 0; x1 < kM; ++x1) qc[x1] = q[x1];
@@ -710,16 +712,11 @@ __global__ __launch_bounds__(256, (lz_min_blocks<1, NB>())) void k_lz_grad8(
   __shared__ double s_y[kLzFree * 256];  // y_f of every free spin, read per record
   __shared__ double s_m[kLzHigh * 256];  // per-lane totals M_k of the high spins
   __shared__ float s_t[4 * kNCoef];
-  __shared__ float s_bq[NB * kQ];
 
   const int b = blockIdx.x / bpi;
   const int blk = blockIdx.x - b * bpi;
   const int tid = threadIdx.x;
   const int N = a.N, n = a.n, H = n - V;  // H: high spins 6..n-1 of the slots
-  for (int e = tid; e < NB * kQ; e += 256) {
-    const int k = e / kQ;
-    s_bq[e] = lzq[((size_t)b * kMaxBeta + k) * kLzQStride + (e - k * kQ)];
-  }
   const int64_t lane = (int64_t)blk * 256 + tid;
   const bool valid = lane < a.lanes;
   const uint64_t p = valid ? (uint64_t)lane : 0ull;
@@ -792,8 +789,6 @@ __global__ __launch_bounds__(256, (lz_min_blocks<1, NB>())) void k_lz_grad8(
   float* const t0 = s_t + wv * kNCoef + c0;
   float* const t5 = s_t + wv * kNCoef + c5;
   const bool row_end = (ln & 15) == 15;
-  __syncthreads();  // s_y, s_bq
-
   // field energy of the high spins 8..n-1, -sum_k s_k y_(8+k), all down at
   // T = 0; updated by one flip per record (fp64, at most 2^(n-8) - 1 terms)
   double gh = 0.0;
@@ -855,8 +850,9 @@ __global__ __launch_bounds__(256, (lz_min_blocks<1, NB>())) void k_lz_grad8(
     for (int f = 0; f < V; ++f) a_r[f] = 0.0f;
 #pragma nounroll
     for (int j = 0; j < kSub; ++j) {
-      // the bq rows are read from LDS in every sub-block instead of being
-      // held in registers
+      // the sub-block's bq rows are wave-uniform: scalar loads into SGPRs,
+      // issued per sub-block (the memory clobber keeps them from being
+      // hoisted out of the loop)
       asm volatile("" ::: "memory");
       const int gj = j ^ (j >> 1);  // bit 0: spin 6 up, bit 1: spin 7 up
       const bool up6 = gj & 1, up7 = gj & 2;
@@ -866,7 +862,7 @@ __global__ __launch_bounds__(256, (lz_min_blocks<1, NB>())) void k_lz_grad8(
 #pragma unroll
       for (int k = 0; k < NB; ++k) {
         d[k] = (x6 ? a6[k] : 1.0f) * (x7 ? a7[k] : 1.0f);
-        bqs[k] = s_bq + k * kQ + j * (1 << V);
+        bqs[k] = lzq + ((size_t)b * kMaxBeta + k) * kLzQStride + j * (1 << V);
       }
       BlockWalk<NB, true> bw{Af, Bf, bqs, d, 0.0f};
       const Coefs C = bw.template walk<V, 0>();
