@@ -7,8 +7,9 @@ hooks sg_debug_set_fill and sg_debug_set_batch_shift shrink the lane count the
 plans assume, so these instances run the decompositions of the N = 48 search
 (22 free spins per lane: the paired walk, block boundaries, high-spin fields,
 fp32 re-anchors every 2^14 flips), of the upper batch levels (16 free spins)
-and of the 256 x N = 28 log Z batch (14 free spins: 6 high spins in the
-partition sums, 8 in the gradient walk).  Every result is compared with the oracle state by
+and of the 256 x N = 28 log Z batch (14 free spins: records of 8 low spins
+with 6 high spins in both walks; the gradient walk's sub-blocks of 6 give its
+pair slots 8 high spins).  Every result is compared with the oracle state by
 state: integer instances bit-exact, fp32 ones under the tolerance rules, log Z
 within 1e-6 relative and gradients within 1e-5 of the largest entry, per
 instance and inverse temperature.
@@ -290,9 +291,9 @@ def check_against_moments(lz, gJ, gh, J, h, betas, orc, what):
 
 @pytest.mark.parametrize("N", [16, 20])
 def test_logz_high_spin_walk(orc, torch_dev, N):
-    """14 free spins per lane (as at the 256 x N = 28 workload): the partition
-    sums walk blocks of 8 low spins with 6 high spins, the gradient walk blocks
-    of 6 with 8 high spins (low-high and high-high pair slots)."""
+    """14 free spins per lane (as at the 256 x N = 28 workload): both walks take
+    records of 8 low spins with 6 high spins; the gradient walk's sub-blocks of
+    6 give its low-high and high-high pair slots 8 high spins."""
     B = 2
     J, h = I.logz_batch(B, N, 500 + N)
     with plan_fill(1):
@@ -305,7 +306,7 @@ def test_logz_high_spin_walk(orc, torch_dev, N):
 @pytest.mark.timeout(900)
 def test_logz_workload_instance0(orc, torch_dev):
     """The 256 x N = 28 workload as run by the benchmark (14 free spins per
-    lane, 8 high spins in the gradient walk): instance 0's log Z and both
+    lane, records of 8 with 6 high spins): instance 0's log Z and both
     gradients at each beta against the oracle, entry by entry."""
     w = I.workload("logz256")
     lz, gJ, gh = gpu_logz_per_beta(torch_dev, w["J"], w["h"], w["beta"])
