@@ -412,7 +412,15 @@ sg_status search_on(Workspace* w, bool isint, int N, const void* J, const void* 
                     void* energies_out, hipStream_t st) {
   const int U = search_block(N);
   const int ncap = std::min(kMaxFree, std::max(N, U));
-  const Batch bt = make_batch(w, J, h, nullptr, N, N, 1, S, (int64_t)recs, cap);
+  Batch bt = make_batch(w, J, h, nullptr, N, N, 1, S, (int64_t)recs, cap);
+  // chunks of n >= kUPk + 2 free spins walk blocks of kUPk (paired, fp32
+  // walks); their tables follow the records of U = kUWide
+  const bool use10 = U == kUWide && ncap >= kUPk + 2;
+  bt.table_base10w = (int64_t)(((size_t)1 << (ncap - kUWide + 1)) - 1) * kRecWords;
+  if (use10 && (size_t)bt.table_base10w + (((size_t)1 << (ncap - kUPk + 1)) - 1) *
+                                               (size_t)rec_words(kUPk) >
+                   recs * (size_t)kRecWords)
+    return fail(SG_EUNSUPPORTED, "table buffer too small for the blocks of 10");
 
   HIP_TRY(launch_prep(isint, bt, st));
   const int score_grid = std::max(1, w->cus) * 4;
@@ -420,6 +428,7 @@ sg_status search_on(Workspace* w, bool isint, int N, const void* J, const void* 
   w->ev_used = 0;
   w->last_launches = 0;
   if (N >= U) HIP_TRY(launch_tables(isint, U, bt, ncap, true, st));
+  if (use10) HIP_TRY(launch_tables(isint, kUPk, bt, ncap, true, st));
   const std::vector<PlanChunk> plan = plan_chunks(N, S, lo, hi, w->fill[isint ? 1 : 0], U);
   double states = 0.0;
   for (const PlanChunk& pc : plan) {
@@ -436,14 +445,16 @@ sg_status search_on(Workspace* w, bool isint, int N, const void* J, const void* 
     ch.prefix_base = pc.first_mask >> pc.n;
     ch.lanes = pc.lanes;
     ch.n = pc.n;
-    ch.table_offset = (1 << (pc.n - U)) - 1;
+    const int Uc = use10 && pc.n >= kUPk + 2 ? kUPk : U;
+    ch.table_offset = (1 << (pc.n - Uc)) - 1;
+    ch.table_offset8 = (1 << (pc.n - U)) - 1;
     // a chunk with more states than candidate slots may overflow: it gets
     // up to kRetries repeated passes, each run only if the last overflowed
     const uint64_t cstates = (uint64_t)pc.lanes << pc.n;
     const int passes = cstates > (uint64_t)cap ? 1 + kRetries : 1;
     for (int r = 0; r < passes; ++r) {
       ch.retry = r;
-      HIP_TRY(enum_timed(w, isint, U, false, bt, ch, 1, st));
+      HIP_TRY(enum_timed(w, isint, Uc, false, bt, ch, 1, st));
       HIP_TRY(launch_score(isint, bt, 0, score_grid, N, r, st));
       HIP_TRY(launch_merge(bt, 0, r, r == passes - 1, st));
     }

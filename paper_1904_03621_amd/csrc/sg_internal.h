@@ -25,14 +25,26 @@ namespace sg {
 // states.
 constexpr int kU = 7;
 constexpr int kUWide = 8;
+// The paired walk of a single search takes blocks of kUPk = 10 (2^10 steps)
+// where a lane has at least kUPk + 2 free spins and the walk is in fp32: its
+// per-block work (fixed-point start values, fp32 G updates, record reads,
+// the bound test) then comes once per 2^10 steps instead of 2^8.
+constexpr int kUPk = 10;
 constexpr int kBlockSteps = 1 << kU;
 // qtab words per instance: the tables of U = kU (both block parities), then
-// those of U = kUWide
-constexpr int kQStride = (2 << kU) + (2 << kUWide);
-constexpr int qtab_base(int U) { return U == kUWide ? (2 << kU) : 0; }
+// those of U = kUWide, then those of U = kUPk (single searches only)
+constexpr int kQStride = (2 << kU) + (2 << kUWide) + (2 << kUPk);
+constexpr int qtab_base(int U) {
+  return U == kUPk ? (2 << kU) + (2 << kUWide) : U == kUWide ? (2 << kU) : 0;
+}
+// index of a block size's Q minimum in Params::qmin_f / qmin_i
+constexpr int qmin_index(int U) { return U == kUPk ? 2 : U == kUWide ? 1 : 0; }
 constexpr int kMaxFree = 22;          // largest n (free spins per lane)
 constexpr int kMaxHigh = kMaxFree - kU;
 constexpr int kRecWords = 16;         // per-block table record (64 B: cB, R, Wu_0..U-1, U <= 14)
+// records of the blocks of kUPk: 32 words (128 B), every packed step in the
+// first record of a pair
+constexpr int rec_words(int U) { return U == kUPk ? 32 : kRecWords; }
 constexpr int kReanchorLog2 = 10;     // fp32: fresh G every 2^10 flips
 constexpr int kReanchorBlocks = 1 << (kReanchorLog2 - kU);
 // The paired walk carries G in fp32 only from block to block (a boundary step
@@ -42,6 +54,9 @@ constexpr int kReanchorBlocks = 1 << (kReanchorLog2 - kU);
 // anchors for the plain walk (2^(10 - U) (2^U - 1 + 3U + 3) with U = kUWide).
 constexpr int kPkReanchorLog2 = 14;
 static_assert((1 << (kPkReanchorLog2 - kUWide)) * 6 <=
+                  (1 << (kReanchorLog2 - kUWide)) * ((1 << kUWide) - 1 + 3 * kUWide + 3),
+              "paired-walk re-anchor period exceeds the margin's rounding count");
+static_assert((1 << (kPkReanchorLog2 - kUPk)) * 6 <=
                   (1 << (kReanchorLog2 - kUWide)) * ((1 << kUWide) - 1 + 3 * kUWide + 3),
               "paired-walk re-anchor period exceeds the margin's rounding count");
 // The log Z walk uses blocks of its own, U low spins with fp64 records of
@@ -81,8 +96,8 @@ struct Params {
   uint64_t thr_mask;
   // instance-derived
   float margin;          // fp32 pruning margin (bound on incremental error)
-  float qmin_f[2];       // min over low configs of Q (rounded down), [U == kUWide]
-  int32_t qmin_i[2];
+  float qmin_f[3];       // min over low configs of Q (rounded down), [qmin_index(U)]
+  int32_t qmin_i[3];
   uint32_t err;          // sticky error bits
   // per-chunk counters
   uint32_t cand_count;   // candidates appended by the current chunk
@@ -104,15 +119,19 @@ struct Params {
   // field offset 2^15 so that rounding never hides a state below the bound
   float pk_scale;
   int32_t pk_slack;
+  float pk_scale10;      // the same for the blocks of kUPk (slack kUPk + 1)
+  int32_t pk_slack10;
 };
 
 // Paired walk: the record of block T < half of a table (n >= U + 2 free
-// spins, U = kUWide) holds, in words kPkWord .. kRecWords - 1, the packed
-// record steps pk_f = (Wx_f(T + half) << 16) + Wx_f(T) of f = 0 .. 5 (integer
-// sum mod 2^32, Wx the fixed-point value of the record's Wu_f), and the record
-// of block T + half holds f = 6, 7 in its words kPkWord, kPkWord + 1.
-constexpr int kPkWord = 2 + kUWide;
-constexpr int kPkInA = kRecWords - kPkWord;  // packed steps stored in the first record
+// spins, U = kUWide or kUPk) holds, from word pk_word(U), the packed record
+// steps pk_f = (Wx_f(T + half) << 16) + Wx_f(T) (integer sum mod 2^32, Wx the
+// fixed-point value of the record's Wu_f) of f < pk_in_a(U); with U = kUWide
+// the record of block T + half holds f = 6, 7 in its words pk_word(U) + 0, 1.
+constexpr int pk_word(int U) { return 2 + U; }
+constexpr int pk_in_a(int U) { return U == kUPk ? U : kRecWords - pk_word(U); }
+static_assert(pk_word(kUPk) + kUPk <= rec_words(kUPk), "packed steps exceed the record");
+static_assert(pk_word(kUWide) + kUWide <= 2 * kRecWords - pk_word(kUWide), "packed steps split");
 
 // Extra passes over a chunk whose candidates overflowed the buffer.
 constexpr int kRetries = 2;
@@ -133,6 +152,7 @@ struct Batch {
   uint32_t* qtab;      // [B][kQStride] low-low energies by block parity and step
   uint32_t* table;     // [B][table_recs][kRecWords]
   int64_t table_recs;
+  int64_t table_base10w;  // first word of the U = kUPk tables (single searches)
   int64_t table_base8; // first record of the U = kUWide tables (search tables)
   uint64_t* cand;      // [B][cap] candidate masks
   uint32_t* ckey;      // [B][cap] orderable key of each candidate's walk energy
@@ -175,6 +195,8 @@ struct Chunk {
   int64_t lanes;
   int n;
   int table_offset;       // record index of block 0 in the table for this n
+  int table_offset8;      // the same in the U = kUWide table, for a chunk of
+                          // U = kUPk whose instance takes the int32 walk
   int retry;              // 0: first pass; r >= 1: r-th repeat (only if redo)
 };
 

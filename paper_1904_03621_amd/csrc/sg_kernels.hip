@@ -128,8 +128,16 @@ __device__ double prep_qtab(const T* Jb, int ld, int Nc, bool walk_f32, uint32_t
     else qtab[e] = __float_as_uint((float)q);
   }
   __syncthreads();
-  static_assert(kSteps <= 256, "one thread per pair of the minimum's first round");
-  for (int st = kSteps; st > 0; st >>= 1) {
+  // minimum: a strided pass down to 256 values, then halving
+  if (2 * kSteps > 256) {
+    double m0 = s_q[tid];
+    for (int e = tid + 256; e < 2 * kSteps; e += 256) m0 = fmin(m0, s_q[e]);
+    __syncthreads();
+    s_q[tid] = m0;
+    __syncthreads();
+  }
+  constexpr int kTop = 2 * kSteps > 256 ? 128 : kSteps;
+  for (int st = kTop; st > 0; st >>= 1) {
     if (tid < st) s_q[tid] = fmin(s_q[tid], s_q[tid + st]);
     __syncthreads();
   }
@@ -205,10 +213,14 @@ __global__ void k_prep(Batch bt) {
   // then hold fp32 values.
   const bool walk_f32 = kInt && bt.allow_f32_walk && 2.1 * Bv < 16777216.0;
   // Q tables of both block sizes and their minima
-  __shared__ double s_q[2 << kUWide];
+  __shared__ double s_q[2 << kUPk];
   const double qmin7 = prep_qtab<kInt, kU>(Jb, ld, Nc, walk_f32, qtab + qtab_base(kU), s_q);
   const double qmin8 =
       prep_qtab<kInt, kUWide>(Jb, ld, Nc, walk_f32, qtab + qtab_base(kUWide), s_q);
+  // blocks of kUPk: single searches whose walk is in fp32
+  const bool pk10 = !bt.Ns && (!kInt || walk_f32);
+  const double qmin10 =
+      pk10 ? prep_qtab<kInt, kUPk>(Jb, ld, Nc, walk_f32, qtab + qtab_base(kUPk), s_q) : 0.0;
   if (tid == 0) {
     uint32_t err = 0;
     if (badN) err |= kErrInval;
@@ -251,22 +263,22 @@ __global__ void k_prep(Batch bt) {
     // margin); sc is the largest power of two with R sc + slack + U + 2
     // <= 2^15, so no field ever leaves [0, 2^16).  A slack of U + 1 units
     // keeps every state whose value is at or below fastThr below 2^15.
-    float pk_scale = 0.0f;
-    const int pk_slack = kUWide + 1;
-    if ((!kInt || walk_f32) && !anybad && !badN) {
+    auto pk_scale_of = [&](int U) -> float {
+      if (!(!kInt || walk_f32) || anybad || badN) return 0.0f;
       double BQ = 0.0;
-      for (int a = 0; a < kUWide && a < Nc; ++a)
-        for (int c = a + 1; c < kUWide && c < Nc; ++c) BQ += fabs((double)Jb[a * ld + c]);
+      for (int a = 0; a < U && a < Nc; ++a)
+        for (int c = a + 1; c < U && c < Nc; ++c) BQ += fabs((double)Jb[a * ld + c]);
       const double R = 2.0 * Bv + 2.0 * BQ + 2.0 * margin + 1.0;
-      const double room = 32768.0 - pk_slack - kUWide - 2.0;
-      if (isfinite(R)) {
-        int e = (int)floor(log2(room / R)) + 1;
-        while (ldexp(R, e) > room) --e;
-        if (e >= -100) pk_scale = (float)ldexp(1.0, e);
-      }
-    }
-    P->pk_scale = pk_scale;
-    P->pk_slack = pk_slack;
+      const double room = 32768.0 - (U + 1) - U - 2.0;
+      if (!isfinite(R)) return 0.0f;
+      int e = (int)floor(log2(room / R)) + 1;
+      while (ldexp(R, e) > room) --e;
+      return e >= -100 ? (float)ldexp(1.0, e) : 0.0f;
+    };
+    P->pk_scale = pk_scale_of(kUWide);
+    P->pk_slack = kUWide + 1;
+    P->pk_scale10 = pk10 ? pk_scale_of(kUPk) : 0.0f;
+    P->pk_slack10 = kUPk + 1;
     P->thr_key = 0xFFFFFFFFu;
     P->rec_count = 0;
     P->thr_mask = ~0ull;
@@ -275,6 +287,8 @@ __global__ void k_prep(Batch bt) {
     P->qmin_i[0] = (int32_t)qmin7;
     P->qmin_f[1] = f32_down(qmin8);
     P->qmin_i[1] = (int32_t)qmin8;
+    P->qmin_f[2] = f32_down(qmin10);
+    P->qmin_i[2] = (int32_t)qmin10;
     P->err = err;
     P->cand_count = 0;
     P->surv_count = 0;
@@ -303,12 +317,13 @@ __global__ void k_prep(Batch bt) {
 //                 step 2^(U-1) flips it).
 // Tables for n = U .. nmax are concatenated; the table of n starts at record
 // 2^(n-U) - 1.  grid.y indexes the instance.  The search uses U = kU or
-// kUWide (words of kRecWords); the log Z walk (kF64) U = kLzU or kLzUF and
-// records of 2 + U doubles.
+// kUWide (words of kRecWords) and kUPk (single searches, rec_words(kUPk)
+// words); the log Z walk (kF64) U = kLzU or kLzUF and records of 2 + U
+// doubles.
 
 template <bool kInt, bool kF64, int U>
 __global__ void k_tables(Batch bt, int ncap, void* out, int paired) {
-  static_assert(kF64 || 2 + U <= kRecWords, "record exceeds kRecWords");
+  static_assert(kF64 || 2 + U <= rec_words(U), "record exceeds its words");
   const int b = blockIdx.y;
   const int N = inst_N(bt, b);
   if (N < U || N > bt.ld) return;
@@ -368,9 +383,16 @@ __global__ void k_tables(Batch bt, int ncap, void* out, int paired) {
     for (int f = 0; f < U; ++f) rec[2 + f] = wu[f];
     return;
   }
-  // search tables of U = kUWide follow those of U = kU at record table_base8
-  const int64_t base = U == kUWide ? bt.table_base8 : 0;
-  uint32_t* rec = bt.table + ((size_t)b * bt.table_recs + (size_t)(base + r)) * kRecWords;
+  // search tables of U = kUWide follow those of U = kU at record table_base8;
+  // those of U = kUPk (records of rec_words(kUPk)) start at word table_base10w
+  uint32_t* rec;
+  if (U == kUPk) {
+    rec = bt.table + (size_t)b * bt.table_recs * kRecWords + (size_t)bt.table_base10w +
+          (size_t)r * rec_words(U);
+  } else {
+    const int64_t base = U == kUWide ? bt.table_base8 : 0;
+    rec = bt.table + ((size_t)b * bt.table_recs + (size_t)(base + r)) * kRecWords;
+  }
   if (kInt && !bt.P[b].walk_f32) {
     rec[0] = (uint32_t)(int32_t)cB;
     rec[1] = (uint32_t)(int32_t)R;
@@ -380,18 +402,19 @@ __global__ void k_tables(Batch bt, int ncap, void* out, int paired) {
     rec[1] = __float_as_uint((float)R);
     for (int f = 0; f < U; ++f) rec[2 + f] = __float_as_uint((float)wu[f]);
     // packed steps of the paired walk: blocks T and T ^ half (same parity)
-    const float sc = bt.P[b].pk_scale;
-    if (paired && U == kUWide && n >= U + 2 && sc > 0.0f) {
+    const float sc = U == kUPk ? bt.P[b].pk_scale10 : bt.P[b].pk_scale;
+    if (paired && (U == kUWide || U == kUPk) && n >= U + 2 && sc > 0.0f) {
       const uint32_t half = 1u << (n - U - 1);
       const uint32_t T2 = T ^ half;
       double wp[U];
       wu_of(gray32(T2 << U), wp);
       const bool first = T < half;  // this record is block A of its pair
-      for (int f = first ? 0 : kPkInA; f < (first ? kPkInA : U); ++f) {
+      constexpr int kIn = pk_in_a(U);
+      for (int f = first ? 0 : kIn; f < (first ? kIn : U); ++f) {
         const int32_t xs = (int32_t)rintf((float)wu[f] * sc);
         const int32_t xp = (int32_t)rintf((float)wp[f] * sc);
         const uint32_t xa = (uint32_t)(first ? xs : xp), xb = (uint32_t)(first ? xp : xs);
-        rec[kPkWord + (first ? f : f - kPkInA)] = xa + (xb << 16);
+        rec[pk_word(U) + (first ? f : f - kIn)] = xa + (xb << 16);
       }
     }
   }
@@ -406,7 +429,8 @@ __global__ void k_tables(Batch bt, int ncap, void* out, int paired) {
 // threshold can exceed.  Two walks:
 //   plain  -- G in fp32 (or int32); the block minimum, one 3-input min per
 //             two states, against the bound;
-//   paired -- (blocks of 8, n >= 10, fp32 walks) blocks T
+//   paired -- (fp32 walks; blocks of 8 with n >= 10, and in single
+//             searches blocks of 10 with n >= 12) blocks T
 //             and T + 2^(n-U-1) in the two 16-bit fixed-point fields of one
 //             word: one integer add and one AND per step for both states,
 //             the sign bit of each field the test.
@@ -436,11 +460,15 @@ __device__ __forceinline__ void enum_walk(const Batch& bt, const void* __restric
                                           int b, int blk, int N, int n, int64_t lanes, Params* P,
                                           uint32_t* s_yw, void* s_Fw, void* s_Rw, void* s_EHw);
 
-// U: low spins per block (kU or kUWide; n >= U for every chunk).  kSplit: the
+// U: low spins per block (kU, kUWide or kUPk; n >= U for every chunk).  kSplit: the
 // bound is tested per sub-block of 64 steps instead of per block (batches,
 // whose short levels bring many candidates per state).
+// Resident waves: 8 per SIMD (64 VGPRs); the walk over blocks of kUPk
+// carries ten packed steps and three group steps and takes 7 (72 VGPRs,
+// 4825 ms per N = 48 search against 4929 ms at 8 waves, where it spills its
+// per-block values).
 template <bool kInt, int U, bool kSplit, bool kPk>
-__global__ __launch_bounds__(kEnumBlock, 8) void k_enum(Batch bt, const void* __restrict__ Jv,
+__global__ __launch_bounds__(kEnumBlock, U == kUPk ? 7 : 8) void k_enum(Batch bt, const void* __restrict__ Jv,
                                                         const void* __restrict__ hv,
                                                         const uint32_t* __restrict__ table,
                                                         const uint32_t* __restrict__ qtab_all,
@@ -467,12 +495,26 @@ __global__ __launch_bounds__(kEnumBlock, 8) void k_enum(Batch bt, const void* __
   __shared__ A s_F[2][kMaxFree + 8];
   __shared__ A s_R[2][kMaxN];
   __shared__ A s_EH[2];
-  if (kInt && P->walk_f32)
-    enum_walk<true, true, U, kSplit, kPk>(bt, Jv, hv, table, qtab_all, ch, b, blk, N, n, lanes,
-                                          P, s_y, s_F, s_R, s_EH);
-  else
-    enum_walk<kInt, !kInt, U, kSplit, kPk && !kInt>(bt, Jv, hv, table, qtab_all, ch, b, blk, N,
-                                                    n, lanes, P, s_y, s_F, s_R, s_EH);
+  if constexpr (U == kUPk) {
+    // blocks of 10: fp32 walks; an integer instance that takes the int32
+    // walk walks the chunk's blocks of 8 instead
+    if (!kInt || P->walk_f32) {
+      enum_walk<kInt, true, kUPk, false, true>(bt, Jv, hv, table, qtab_all, ch, b, blk, N, n,
+                                               lanes, P, s_y, s_F, s_R, s_EH);
+    } else if constexpr (kInt) {
+      Chunk c8 = ch;
+      c8.table_offset = ch.table_offset8;
+      enum_walk<true, false, kUWide, false, false>(bt, Jv, hv, table, qtab_all, c8, b, blk, N,
+                                                   n, lanes, P, s_y, s_F, s_R, s_EH);
+    }
+  } else {
+    if (kInt && P->walk_f32)
+      enum_walk<true, true, U, kSplit, kPk>(bt, Jv, hv, table, qtab_all, ch, b, blk, N, n,
+                                            lanes, P, s_y, s_F, s_R, s_EH);
+    else
+      enum_walk<kInt, !kInt, U, kSplit, kPk && !kInt>(bt, Jv, hv, table, qtab_all, ch, b, blk, N,
+                                                      n, lanes, P, s_y, s_F, s_R, s_EH);
+  }
 }
 
 // The walk of k_enum.  kInt: the instance is int32 (exact set-up in int64,
@@ -493,7 +535,8 @@ __device__ __forceinline__ void enum_walk(const Batch& bt, const void* __restric
   constexpr int kReBlocks = 1 << (kReanchorLog2 - U);       // fp32: blocks per re-anchor
   V* s_y = (V*)s_yw;
   const uint32_t* qtab = qtab_all + (size_t)b * kQStride + qtab_base(U);  // uniform: SGPRs
-  constexpr int kQi = U == kUWide;  // this block size's Q minimum
+  constexpr int kQi = qmin_index(U);  // this block size's Q minimum
+  constexpr int kRW = rec_words(U);   // words per table record
 
   const int tid = threadIdx.x;
   const int ld = bt.ld;
@@ -503,7 +546,9 @@ __device__ __forceinline__ void enum_walk(const Batch& bt, const void* __restric
   const uint64_t p0 = ch.prefix_base + (uint64_t)blk * kEnumBlock;
   const uint64_t p = p0 + (uint64_t)(valid ? tid : 0);
   const uint32_t* tab =
-      table + ((size_t)b * bt.table_recs + (size_t)ch.table_offset) * kRecWords;
+      U == kUPk ? table + (size_t)b * bt.table_recs * kRecWords + (size_t)bt.table_base10w +
+                      (size_t)ch.table_offset * kRW
+                : table + ((size_t)b * bt.table_recs + (size_t)ch.table_offset) * kRecWords;
   uint64_t* cand = bt.cand + (size_t)b * bt.cap;
   uint32_t* ckey = bt.ckey + (size_t)b * bt.cap;
   const uint32_t cand_cap = bt.cap;
@@ -678,6 +723,7 @@ __device__ __forceinline__ void enum_walk(const Batch& bt, const void* __restric
   // the states at or below thrE in lanes that passed become candidates.
   auto rewalk = [&](uint32_t T, const V (&W)[U], const V (&gsub)[kNSub],
                     const bool (&pass)[kNSub]) {
+   if constexpr (kSteps <= 256) {
     ++slow;
     const uint32_t* q = qtab + (T & 1u) * kSteps;
     const V Gs = gsub[0];
@@ -752,6 +798,72 @@ __device__ __forceinline__ void enum_walk(const Batch& bt, const void* __restric
         ++slot;
       }
     }
+   }
+  };
+
+  // Re-walk of a block of more than 256 steps (fp32 walks), as a loop over
+  // passes of 64 steps: the hits of a pass are appended at its end, with one
+  // slot reservation per wave and pass that has any.
+  auto rewalk_long = [&](uint32_t T, const V (&W)[U], V G0, bool pass) {
+    ++slow;
+    const uint32_t* q = qtab + (T & 1u) * kSteps;
+    auto qv = [&](int i) -> V { return (V)__uint_as_float(q[i]); };
+    V g2 = G0;
+    asm volatile("" : "+v"(g2));
+    const uint64_t pl = ch.prefix_base + (uint64_t)lane;
+#pragma nounroll
+    for (int w = 0; w < kSteps / 64; ++w) {
+      if (w > 0) {
+        // step 64 w flips spin 6 + ctz(w): old value +1 iff the next bit of
+        // the step index is set; spin U-1 flips once, up
+        const int f = 6 + __builtin_ctz((uint32_t)w);
+        V wf = W[6];
+#pragma unroll
+        for (int k = 7; k < U; ++k) wf = f == k ? W[k] : wf;
+        if (f == U - 1) g2 = g2 + wf;
+        else g2 = (((uint32_t)(64 * w) >> (f + 1)) & 1u) ? g2 + wf : g2 - wf;
+      }
+      uint64_t hw = (g2 + qv(64 * w) <= thrE) ? 1ull : 0ull;
+#pragma unroll
+      for (int j = 1; j < 64; ++j) {
+        const int f = __builtin_ctz(j);
+        if (f == 5) g2 = (w & 1) ? g2 + W[5] : g2 - W[5];
+        else g2 = ((j >> (f + 1)) & 1) ? g2 + W[f] : g2 - W[f];
+        if (g2 + qv(64 * w + j) <= thrE) hw |= 1ull << j;
+      }
+      if (!(valid && pass)) hw = 0ull;
+      const uint32_t nh = (uint32_t)__popcll(hw);
+      uint32_t incl = nh;
+#pragma unroll
+      for (int o = 1; o < kWaveLanes; o <<= 1) {
+        const uint32_t y = __shfl_up(incl, o);
+        if ((int)__lane_id() >= o) incl += y;
+      }
+      const uint32_t total = __shfl(incl, kWaveLanes - 1);
+      if (total == 0) continue;  // wave-uniform
+      uint32_t base = 0;
+      if (__lane_id() == 0) base = atomicAdd(&P->cand_count, total);
+      uint32_t slot = __shfl(base, 0) + incl - nh;
+      while (hw) {
+        const int i = 64 * w + __builtin_ctzll(hw);
+        hw &= hw - 1ull;
+        const uint64_t t = ((uint64_t)T << U) | (uint64_t)i;
+        const uint64_t mask = (pl << n) | (t ^ (t >> 1));
+        const uint32_t gi = (uint32_t)(i ^ (i >> 1));
+        V e = G0;
+#pragma unroll
+        for (int f = 0; f < U - 1; ++f)
+          if ((gi >> f) & 1u) e = e - W[f];
+        if ((gi >> (U - 1)) & 1u) e = e + W[U - 1];
+        e = e + qv(i);
+        const uint32_t key = key_f32((float)e);
+        if (slot < cand_cap) {
+          cand[slot] = mask;
+          ckey[slot] = key;
+        }
+        ++slot;
+      }
+    }
   };
 
   // fresh G at the start of block T (fp32 walks): E_P minus the prefix fields
@@ -769,11 +881,13 @@ __device__ __forceinline__ void enum_walk(const Batch& bt, const void* __restric
   };
 
   if constexpr (kPk) {
-    static_assert(!kPk || (kWF && U == kUWide && (!kSplit || kSub == 64)),
-                  "paired walk: fp32 walks, blocks of 8, sub-blocks of 64");
+    static_assert(!kPk || (kWF && (U == kUWide || (U == kUPk && !kSplit)) &&
+                           (!kSplit || kSub == 64)),
+                  "paired walk: fp32 walks, blocks of 8 (or 10 unsplit), sub-blocks of 64");
     // ---- paired walk ----------------------------------------------------------
-    // Blocks T and T + half (half = nblocks / 2, n >= U + 2: both of the same
-    // parity) are walked together as the low and high 16-bit fields of one
+    // (blocks of kUWide, or of kUPk for the chunks of a single search with
+    // n >= kUPk + 2.)  Blocks T and T + half (half = nblocks / 2, n >= U + 2:
+    // both of the same parity) are walked together as the low and high 16-bit fields of one
     // 32-bit word, in fixed point with the power-of-two scale sc: a field
     // holds (G - fastThr) sc + 2^15 - slack, so that its bit 15 is clear iff
     // its state may lie below the bound.  Every Gray step is one integer add
@@ -783,25 +897,35 @@ __device__ __forceinline__ void enum_walk(const Batch& bt, const void* __restric
     // carried in fp32 from block to block (boundary steps, the block's net
     // step +W_{U-1}, re-anchors) and turned into fixed point once per block.
     const uint32_t half = nblocks >> 1;
-    const float sc = P->pk_scale;
-    const uint32_t off = 32768u - (uint32_t)P->pk_slack;
+    const float sc = U == kUPk ? P->pk_scale10 : P->pk_scale;
+    const uint32_t off = 32768u - (uint32_t)(U == kUPk ? P->pk_slack10 : P->pk_slack);
     const bool armed = full && sc > 0.0f;  // else every block is re-walked
     const float ftsc = armed ? fastThr * sc : 0.0f;  // exact: sc is a power of two
-    uint32_t wlpk[U];  // the lane's part of the packed steps: the same in both fields
+    // packed steps of the current pair: the lane's part (the same in both
+    // fields) plus the records' part.  They are carried from pair to pair,
+    // pk_f(T) = pk_f(T - 1) + (rpk_f(T) - rpk_f(T - 1)) with a wave-uniform
+    // difference, and for the top spin, whose lane part changes sign with
+    // the block parity, pk(T) = rpk(T) + rpk(T - 1) - pk(T - 1); so the lane
+    // part is not kept in registers.
+    uint32_t pk[U], rprev[U];
 #pragma unroll
-    for (int f = 0; f < U; ++f) wlpk[f] = (uint32_t)(int32_t)rintf((float)WL[f] * sc) * 65537u;
+    for (int f = 0; f < U; ++f) {
+      pk[f] = (uint32_t)(int32_t)rintf((float)WL[f] * sc) * 65537u;
+      rprev[f] = 0u;
+    }
     V GA = G, GB = G;
     V ynext = s_y[tid];  // pair 1 flips high spin U in both blocks
     for (uint32_t T = 0; T < half; ++T) {
       const uint32_t TB = T + half;
-      const uint32_t* recA = tab + (size_t)T * kRecWords;
-      const uint32_t* recB = tab + (size_t)TB * kRecWords;
+      const uint32_t* recA = tab + (size_t)T * kRW;
+      const uint32_t* recB = tab + (size_t)TB * kRW;
       // record words are read where they are used (the re-walk reads its
       // steps itself), so that few of them stay live across the walk
       auto rw = [&](const uint32_t* rec, int k) -> V { return (V)__uint_as_float(rec[k]); };
       uint32_t rpk[U];
 #pragma unroll
-      for (int f = 0; f < U; ++f) rpk[f] = f < kPkInA ? recA[kPkWord + f] : recB[kPkWord + f - kPkInA];
+      for (int f = 0; f < U; ++f)
+        rpk[f] = f < pk_in_a(U) ? recA[pk_word(U) + f] : recB[pk_word(U) + f - pk_in_a(U)];
       const V ycur = ynext;
       if (T + 1 < half) ynext = s_y[__builtin_ctz(T + 1) * kEnumBlock + tid];
       const bool odd = T & 1u;
@@ -831,10 +955,12 @@ __device__ __forceinline__ void enum_walk(const Batch& bt, const void* __restric
       const float gb = valid ? fmaf((float)GB, sc, -ftsc) : 0.0f;
       const uint32_t za = (uint32_t)(int32_t)rintf(ga) + off;
       const uint32_t zb = (uint32_t)(int32_t)rintf(gb) + off;
-      uint32_t pk[U];
 #pragma unroll
-      for (int f = 0; f < U - 1; ++f) pk[f] = wlpk[f] + rpk[f];
-      pk[U - 1] = (odd ? wlpk[U - 1] : 0u - wlpk[U - 1]) + rpk[U - 1];
+      for (int f = 0; f < U - 1; ++f) pk[f] = pk[f] + (rpk[f] - rprev[f]);
+      // block 0 is even: its top-spin lane part is minus the lane's value
+      pk[U - 1] = T == 0 ? rpk[U - 1] - pk[U - 1] : (rpk[U - 1] + rprev[U - 1]) - pk[U - 1];
+#pragma unroll
+      for (int f = 0; f < U; ++f) rprev[f] = rpk[f];
       // Four sub-blocks of 64 steps in a loop.  Steps 64w + j, j = 1..63,
       // flip spin ctz(j) <= 5 with the sign of step j of sub-block 0, except
       // spin 5 (j = 32), whose sign alternates with w; step 64(w + 1) flips
@@ -870,14 +996,40 @@ __device__ __forceinline__ void enum_walk(const Batch& bt, const void* __restric
       // loop selects nothing.  (Unrolled into two passes of two sub-blocks,
       // the pairing fell from 86% to 72% and the search took 5% longer.)
       uint32_t p5 = 0u - pk[5];
-      uint32_t s0 = 0u - pk[6], s1 = pk[U - 1], s2 = pk[6];
+      if constexpr (U == kUWide) {
+        uint32_t s0 = 0u - pk[6], s1 = pk[U - 1], s2 = pk[6];
 #pragma nounroll
-      for (int w = 0; w < kSteps / 64; ++w) {
-        sub(p5, w);
-        g = g + s0;  // after the last sub-block g is not used
-        s0 = s1;
-        s1 = s2;
-        p5 = 0u - p5;
+        for (int w = 0; w < kSteps / 64; ++w) {
+          sub(p5, w);
+          g = g + s0;  // after the last sub-block g is not used
+          s0 = s1;
+          s1 = s2;
+          p5 = 0u - p5;
+        }
+      } else {
+        // blocks of 10: four groups of the same four passes.  Within a group
+        // the steps between passes flip spin 6 (down), 7, 6 (up), spin 7 down
+        // in even groups and up in odd ones; between groups spin 8 (down),
+        // 9 (the block's top spin, up), 8 (up).  The group's last pass adds
+        // spin 6's step once more, which the group step t takes back.
+        uint32_t s7 = 0u - pk[7];
+        uint32_t t0 = 0u - pk[8] - pk[6], t1 = pk[U - 1] - pk[6], t2 = pk[8] - pk[6];
+#pragma nounroll
+        for (int o = 0; o < kSteps / 256; ++o) {
+          uint32_t s0 = 0u - pk[6], s1 = s7, s2 = pk[6];
+#pragma nounroll
+          for (int w = 0; w < 4; ++w) {
+            sub(p5, 4 * o + w);
+            g = g + s0;
+            s0 = s1;
+            s1 = s2;
+            p5 = 0u - p5;
+          }
+          g = g + t0;  // after the last group g is not used
+          t0 = t1;
+          t1 = t2;
+          s7 = 0u - s7;
+        }
       }
       bool pa[kNSub], pb[kNSub];
       bool anya = false, anyb = false;
@@ -915,20 +1067,29 @@ __device__ __forceinline__ void enum_walk(const Batch& bt, const void* __restric
       if (__ballot(anya) != 0ull) {
         V W[U], gs[kNSub];
         steps(recA, W);
-        starts(GA, W, gs);
-        rewalk(T, W, gs, pa);
+        if constexpr (kSteps > 256) {
+          rewalk_long(T, W, GA, pa[0]);
+        } else {
+          starts(GA, W, gs);
+          rewalk(T, W, gs, pa);
+        }
       }
       if (__ballot(anyb) != 0ull) {
         V W[U], gs[kNSub];
         steps(recB, W);
-        starts(GB, W, gs);
-        rewalk(TB, W, gs, pb);
+        if constexpr (kSteps > 256) {
+          rewalk_long(TB, W, GB, pb[0]);
+        } else {
+          starts(GB, W, gs);
+          rewalk(TB, W, gs, pb);
+        }
       }
       // the blocks end with spin U-1 up and every other low spin back down
       GA = GA + (wl + rw(recA, 2 + U - 1));
       GB = GB + (wl + rw(recB, 2 + U - 1));
     }
   } else {
+    static_assert(U <= kUWide, "plain walk: blocks of at most 2^8 steps (unrolled)");
     V ynext = nblocks > 1 ? s_y[tid] : (V)0;  // block 1 flips high spin U
 
     for (uint32_t T = 0; T < nblocks; ++T) {
@@ -1411,7 +1572,7 @@ hipError_t launch_prep(bool isint, const Batch& bt, hipStream_t st) {
 // paired: also write the packed steps of the paired walk
 hipError_t launch_tables(bool isint, int U, const Batch& bt, int ncap, bool paired,
                          hipStream_t st) {
-  if ((U != kU && U != kUWide) || ncap < U) return hipErrorInvalidValue;
+  if ((U != kU && U != kUWide && U != kUPk) || ncap < U) return hipErrorInvalidValue;
   const int64_t total = ((int64_t)1 << (ncap - U + 1)) - 1;  // search records
   const dim3 grid((unsigned)((total + 255) / 256), (unsigned)bt.B);
 #define SG_TABLES(I, UV) \
@@ -1419,10 +1580,12 @@ hipError_t launch_tables(bool isint, int U, const Batch& bt, int ncap, bool pair
                      paired ? 1 : 0)
   if (isint) {
     if (U == kU) SG_TABLES(true, kU);
-    else SG_TABLES(true, kUWide);
+    else if (U == kUWide) SG_TABLES(true, kUWide);
+    else SG_TABLES(true, kUPk);
   } else {
     if (U == kU) SG_TABLES(false, kU);
-    else SG_TABLES(false, kUWide);
+    else if (U == kUWide) SG_TABLES(false, kUWide);
+    else SG_TABLES(false, kUPk);
   }
 #undef SG_TABLES
   return hipGetLastError();
@@ -1444,13 +1607,16 @@ hipError_t launch_tables64(const Batch& bt, int ncap, int U, double* out, hipStr
 
 // The paired walk takes the chunks (single searches) and levels (batches)
 // with blocks of kUWide and at least two high spins (its tables hold the
-// packed steps of those n).
-bool enum_paired(int U, int n) { return U == kUWide && n >= kUWide + 2; }
+// packed steps of those n); blocks of kUPk always walk paired (n >= kUPk + 2).
+bool enum_paired(int U, int n) {
+  return (U == kUWide && n >= kUWide + 2) || (U == kUPk && n >= kUPk + 2);
+}
 
 // split: test the bound per 64-step sub-block (batched searches)
 hipError_t launch_enum(bool isint, int U, bool split, const Batch& bt, const Chunk& ch, int ninst,
                        hipStream_t st) {
-  if ((U != kU && U != kUWide) || ch.n < U) return hipErrorInvalidValue;
+  if ((U != kU && U != kUWide && U != kUPk) || ch.n < U) return hipErrorInvalidValue;
+  if (U == kUPk && (split || !enum_paired(U, ch.n))) return hipErrorInvalidValue;
   const int bpi = (int)((ch.lanes + kEnumBlock - 1) / kEnumBlock);
   const dim3 grid((unsigned)((int64_t)bpi * ninst));
 #define SG_ENUM(I, UV, SP, PK)                                                                 \
@@ -1459,7 +1625,10 @@ hipError_t launch_enum(bool isint, int U, bool split, const Batch& bt, const Chu
 #define SG_ENUM_U(I, SP)                 \
   if (U == kU) SG_ENUM(I, kU, SP, false); \
   else SG_ENUM(I, kUWide, SP, false)
-  if (enum_paired(U, ch.n)) {
+  if (U == kUPk) {
+    if (isint) SG_ENUM(true, kUPk, false, true);
+    else SG_ENUM(false, kUPk, false, true);
+  } else if (enum_paired(U, ch.n)) {
     if (isint) {
       if (split) SG_ENUM(true, kUWide, true, true);
       else SG_ENUM(true, kUWide, false, true);
@@ -1536,6 +1705,7 @@ int enum_occupancy_t() {
   take((const void*)k_enum<I, kUWide, true, false>);
   take((const void*)k_enum<I, kUWide, false, true>);
   take((const void*)k_enum<I, kUWide, true, true>);
+  take((const void*)k_enum<I, kUPk, false, true>);
   return best;
 }
 

@@ -97,22 +97,27 @@ def test_search_f32_full_walk(orc, torch_dev, N, S):
     assert 0.0 < info["max_drift"] <= info["margin"], info
 
 
-@pytest.mark.parametrize("N,S,lanes", [(14, 100, 4), (13, 100, 2), (12, 50, 1), (14, 600, 4)])
+@pytest.mark.parametrize("N,S,lanes,nmax", [(20, 100, 16, 15), (18, 100, 4, 15), (18, 600, 16, 13),
+                                            (18, 20000, 4, 15), (16, 2000, 16, 11)])
 @pytest.mark.parametrize("isint", [False, True])
-def test_paired_walk_small_geometries(orc, torch_dev, N, S, lanes, isint):
-    """The paired walk's smallest tables: n = 10 (two block pairs per lane),
-    11 and 12 free spins, in chunks that run with no threshold yet (every
-    block re-walked) and in chunks with one (the fixed-point test decides)."""
+def test_paired_walk_small_geometries(orc, torch_dev, N, S, lanes, nmax, isint):
+    """The paired walks' smallest tables.  The chunks of a search double in
+    size, so one search runs the plain walk (n = 8, 9 free spins), the paired
+    walk over blocks of 8 (n = 10, 11: two and four block pairs per lane) and
+    the one over blocks of 10 (n = 12 .. 15: two to sixteen pairs), in chunks
+    that run with no threshold yet (every block re-walked; S = 20000 keeps the
+    record open into the first chunk of blocks of 10) and in chunks with one
+    (the fixed-point test decides)."""
     from paper_1904_03621_amd import _lib
     plan = _lib.sg_debug_plan(N, S, 0, 1 << N, lanes)
-    assert min(n for _, n, _ in plan) >= 10, plan
+    assert max(n for _, n, _ in plan) == nmax, plan
     if isint:
         J, h = I.random_int_dense(N, 600 + N + lanes)
     else:
         J, h = I.random_f32_dense(N, 600 + N + lanes)
     with plan_fill(lanes):
         m, e, info = search(torch_dev, J, h, S)
-    assert info["free_bits_max"] == max(n for _, n, _ in plan), info
+    assert info["free_bits_max"] == nmax, info
     om, oe = orc.low_spectrum(J, h, S)
     if isint:
         check_int(m, e, om, oe, "paired N=%d lanes %d" % (N, lanes))
