@@ -42,24 +42,25 @@ SURVEY_STATES_PER_S = 256 * 64 * 2.4e9 / 2.0
 # size of the plain device copy that calibrates the HBM byte counters
 COPY_BYTES = 512 << 20
 # HBM bytes per paired-walk k_enum launch from rocprofv3 FETCH_SIZE / WRITE_SIZE
-# passes (KiB per dispatch, averaged over the 417 paired-walk dispatches of one
-# search), scaled by what the same counters read for the 512 MiB copy (fetch
-# x2.0, write x1.0); valid for the k_enum source with this SHA-256 prefix only
-TRAFFIC = {"kenum_sha256_16": "b1272f6e9b81a0b9", "fetch_kib": 1119780.0 / 417,
-           "write_kib": 36575.0 / 417, "fetch_factor": 524288.0 / 262172.0, "write_factor": 1.0,
+# passes (KiB per dispatch, averaged over the 486 dispatches of the walk over
+# blocks of 10 in one search), scaled by what the same counters read for the
+# 512 MiB copy (fetch x2.0, write x1.0); valid for the k_enum source with this
+# SHA-256 prefix only
+TRAFFIC = {"kenum_sha256_16": "5566fac3a3ce0dda", "fetch_kib": 1825452.3 / 486,
+           "write_kib": 14967418.8 / 486, "fetch_factor": 524288.0 / 262172.5, "write_factor": 1.0,
            "profile": "profiles/k_enum_f32_dense48_counters.md"}
 
 # VALU counters of the search's paired-walk launches (rocprofv3 --pmc, one
-# search of this instance, 417 dispatches, 5.123 s of kernel time), valid for
+# search of this instance, 486 dispatches, 4.959 s of kernel time), valid for
 # the k_enum source with this hash only: SQ_INSTS_VALU (wave instructions) x 64
 # / 2^48 per configuration; the fraction of the doubled-rate issue capacity
 # used, SQ_INSTS_VALU / (1024 SIMDs x cycles x 1/2); the share issued in pairs,
 # 2 SQ_ACTIVE_INST_VALU2 / SQ_INSTS_VALU; and sclk = GRBM_GUI_ACTIVE / 8 XCDs /
 # kernel time.
-COUNTERS = {"kenum_sha256_16": "b1272f6e9b81a0b9", "valu_insts_per_state": 4.96185e12 * 64 / 2 ** 48,
-            "valu_active": 4.96185e12 / (1024 * 9.29629e10 / 8 * 0.5),
-            "valu_paired": 2 * 2.14899e12 / 4.96185e12,
-            "sclk_ghz": 9.29629e10 / 8 / 5.123 / 1e9,
+COUNTERS = {"kenum_sha256_16": "5566fac3a3ce0dda", "valu_insts_per_state": 4.72181e12 * 64 / 2 ** 48,
+            "valu_active": 4.72181e12 / (1024 * 8.79117e10 / 8 * 0.5),
+            "valu_paired": 2 * 2.10129e12 / 4.72181e12,
+            "sclk_ghz": 8.79117e10 / 8 / 4.959 / 1e9,
             "profile": "profiles/k_enum_f32_dense48_counters.md"}
 
 
