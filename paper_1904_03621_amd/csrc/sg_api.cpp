@@ -651,8 +651,10 @@ LzArgs lz_args(Workspace* w, int B, int N, int nb, int S, const float* h, const 
   a.B = B;
   a.N = N;
   // low spins per block (record): the larger blocks whenever the instance
-  // has that many spins
-  a.U = N >= kLzUF ? kLzUF : kLzU;
+  // has that many spins (the gradient walk's records hold four sub-blocks
+  // of kLzU; the partition sums of four beta keep records of 8, which fit
+  // their registers)
+  a.U = (mode == 0 && N >= kLzUW && nb <= 3) ? kLzUW : N >= kLzUF ? kLzUF : kLzU;
   // free spins per lane: at most kLzFree, fewer when the batch alone would
   // not give every resident lane of the device a prefix
   a.n = std::min(kLzFree, N);

@@ -60,12 +60,18 @@ static_assert((1 << (kPkReanchorLog2 - kUPk)) * 6 <=
                   (1 << (kReanchorLog2 - kUWide)) * ((1 << kUWide) - 1 + 3 * kUWide + 3),
               "paired-walk re-anchor period exceeds the margin's rounding count");
 // The log Z walk uses blocks of its own, U low spins with fp64 records of
-// 2 + U doubles (cB, R, Wu_0..U-1): U = 6 (64 configurations) for the
-// gradient walk, U = 8 (256) for the partition sums when N >= 8.
+// 2 + U doubles (cB, R, Wu_0..U-1): the partition sums take U = 10 (1024
+// configurations) when N >= 10 and at most three beta, else U = 8 when
+// N >= 8; the gradient walk U = 8 (four sub-blocks of 6) when N >= 8; N = 7
+// takes U = 6 in both.
 constexpr int kLzU = 6;
 constexpr int kLzUF = 8;
+constexpr int kLzUW = 10;  // the partition sums' records when N >= 10
 constexpr int kLzSteps = 1 << kLzU;
-constexpr int kLzQStride = 256;  // floats per (instance, beta) of the bq tables
+// floats per (instance, beta) of the bq tables: 256 up to records of 8, 1024
+// for records of 10 (the same buffer, [B][kMaxBeta][stride])
+constexpr int lz_q_stride(int U) { return U > kLzUF ? 1 << U : 1 << kLzUF; }
+constexpr int kLzQStride = lz_q_stride(kLzUW);  // the buffer's floats per (instance, beta)
 constexpr int kWaveLanes = 64;
 constexpr int kEnumBlock = 256;       // threads per enumeration workgroup
 constexpr int kMergeThreads = 1024;   // threads of the single-workgroup merge

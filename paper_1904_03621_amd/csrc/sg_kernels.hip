@@ -1593,10 +1593,13 @@ hipError_t launch_tables(bool isint, int U, const Batch& bt, int ncap, bool pair
 
 // fp64 records (2 + U doubles each) of an fp32 batch, for the log Z walk.
 hipError_t launch_tables64(const Batch& bt, int ncap, int U, double* out, hipStream_t st) {
-  if (U != kLzU && U != kLzUF) return hipErrorInvalidValue;
+  if (U != kLzU && U != kLzUF && U != kLzUW) return hipErrorInvalidValue;
   const int64_t total = ((int64_t)1 << (ncap - U + 1)) - 1;
   const dim3 grid((unsigned)((total + 255) / 256), (unsigned)bt.B);
-  if (U == kLzU)
+  if (U == kLzUW)
+    hipLaunchKernelGGL((k_tables<false, true, kLzUW>), grid, dim3(256), 0, st, bt, ncap, (void*)out,
+                       0);
+  else if (U == kLzU)
     hipLaunchKernelGGL((k_tables<false, true, kLzU>), grid, dim3(256), 0, st, bt, ncap, (void*)out,
                        0);
   else

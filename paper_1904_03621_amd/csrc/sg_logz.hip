@@ -22,8 +22,10 @@
 //
 // Forward (kMode 0): the 2^U weights of a block are a 2^(U/2) x 2^(U/2)
 // contraction of the factor products of the lower and upper U/2 low spins
-// with bq (U = 8 when N >= 8: 16 x 16; else U = 6: 8 x 8); block sums are
-// fp32, lane totals fp64, one fp64 atomic per wave and beta.
+// with bq (U = 10 when N >= 10 and at most three beta: 32 x 32; U = 8 when
+// N >= 8: 16 x 16; else U = 6: 8 x 8); block sums are fp32 (two chains of at
+// most 32 fused multiply-adds over terms in (0, 1]: relative error at most
+// 64 2^-24), lane totals fp64, one fp64 atomic per wave and beta.
 //
 // Backward: the gradient of sum_b g_b log Z(beta_b) needs, for every
 // pair and every spin, sum_s omega(s) s_i s_j and sum_s omega(s) s_i with the
@@ -86,7 +88,7 @@ __global__ void k_lz_prep(LzArgs a, const float* __restrict__ J, float* lzq, dou
                           const double* grad) {
   constexpr int kSteps = 1 << U;
   constexpr int kQ = lz_q_floats<kMode, U>();
-  static_assert(kQ <= kLzQStride, "bq tables exceed their stride");
+  static_assert(kQ <= lz_q_stride(U), "bq tables exceed their stride");
   __shared__ double s_q[kSteps];
   __shared__ double s_qmin;
   const int b = blockIdx.x;
@@ -115,7 +117,7 @@ __global__ void k_lz_prep(LzArgs a, const float* __restrict__ J, float* lzq, dou
     const int k = e / kQ, r = e - k * kQ;
     const int x = lz_q_config<kMode, U>(r);
     const double bk = (double)a.beta[k];
-    lzq[((size_t)b * kMaxBeta + k) * kLzQStride + r] = (float)exp(-bk * (s_q[x] - qmin));
+    lzq[((size_t)b * kMaxBeta + k) * lz_q_stride(U) + r] = (float)exp(-bk * (s_q[x] - qmin));
   }
   double* acc = a.acc + (size_t)b * a.acc_stride;
   for (int k = tid; k < a.acc_stride; k += blockDim.x) acc[k] = 0.0;
@@ -324,16 +326,20 @@ __global__ __launch_bounds__(256, (lz_min_blocks<kMode, NB>())) void k_logz(LzAr
   __shared__ double s_y[kHigh * 256];
   __shared__ __align__(16) float s_c[kMode ? 4 * 4 * kCoefStride : 1];
   __shared__ float s_t[kMode ? 4 * kNCoef : 1];
-  __shared__ float s_bq[kMode ? NB * kQ : 1];  // the gradient walk's bq tables
+  // bq tables in LDS: the gradient walk's, and the partition sums' of blocks
+  // of 10 (12 KB for three beta: more than the scalar cache keeps between
+  // blocks; blocks of 8 read their 3 KB with scalar loads)
+  constexpr bool kBqLds = kMode == 1 || U > kLzUF;
+  __shared__ float s_bq[kBqLds ? NB * kQ : 1];
 
   const int b = blockIdx.x / bpi;
   const int blk = blockIdx.x - b * bpi;
   const int tid = threadIdx.x;
   const int N = a.N, n = a.n, H = n - U;
-  if (kMode == 1) {
+  if (kBqLds) {
     for (int e = tid; e < NB * kQ; e += 256) {
       const int k = e / kQ;
-      s_bq[e] = lzq[((size_t)b * kMaxBeta + k) * kLzQStride + (e - k * kQ)];
+      s_bq[e] = lzq[((size_t)b * kMaxBeta + k) * lz_q_stride(U) + (e - k * kQ)];
     }
   }
   const int64_t lane = (int64_t)blk * 256 + tid;
@@ -476,28 +482,36 @@ __global__ __launch_bounds__(256, (lz_min_blocks<kMode, NB>())) void k_logz(LzAr
         factors(k, cp, cm);
         factor_products<U / 2>(cp, cm, Af);
         factor_products<U / 2>(cp + U / 2, cm + U / 2, Bf);
-        // bq by configuration (wave-uniform, so scalar loads into SGPRs),
-        // one row of 2^(U/2) read ahead of its products.  The empty asm
-        // after each row ties the row's products (through S) to the reads
-        // (memory clobber), so later rows are not fetched early.
-        const float* q = lzq + ((size_t)b * kMaxBeta + k) * kLzQStride;
-        float qc[kM], qn[kM];
+        // bq by configuration (wave-uniform: scalar loads into SGPRs for
+        // blocks of 8, broadcast LDS reads for blocks of 10), in chunks of
+        // kC = min(2^(U/2), 16) entries, each read one chunk ahead of its
+        // products.  The empty asm after each chunk ties its products
+        // (through u) to the reads (memory clobber), so later chunks are not
+        // fetched early.
+        const float* q =
+            kBqLds ? s_bq + k * kQ : lzq + ((size_t)b * kMaxBeta + k) * lz_q_stride(U);
+        constexpr int kC = kM < 16 ? kM : 16;
+        constexpr int kPer = kM / kC;  // chunks per row
+        float qc[kC], qn[kC];
 #pragma unroll
-        for (int x1 = 0; x1 < kM; ++x1) qc[x1] = q[x1];
-        float S = 0.0f;
+        for (int i = 0; i < kC; ++i) qc[i] = q[i];
+        float S = 0.0f, u = 0.0f;
 #pragma unroll
-        for (int x2 = 0; x2 < kM; ++x2) {
-          if (x2 + 1 < kM) {
+        for (int c = 0; c < kM * kPer; ++c) {
+          if (c + 1 < kM * kPer) {
 #pragma unroll
-            for (int x1 = 0; x1 < kM; ++x1) qn[x1] = q[x1 + kM * (x2 + 1)];
+            for (int i = 0; i < kC; ++i) qn[i] = q[kC * (c + 1) + i];
           }
-          float u = 0.0f;
+          const int x1 = kC * (c % kPer);
 #pragma unroll
-          for (int x1 = 0; x1 < kM; ++x1) u = fmaf(Af[x1], qc[x1], u);
-          S = fmaf(Bf[x2], u, S);
-          asm volatile("" : "+v"(S) : : "memory");
+          for (int i = 0; i < kC; ++i) u = fmaf(Af[x1 + i], qc[i], u);
+          if (c % kPer == kPer - 1) {
+            S = fmaf(Bf[c / kPer], u, S);
+            u = 0.0f;
+          }
+          asm volatile("" : "+v"(S), "+v"(u) : : "memory");
 #pragma unroll
-          for (int x1 = 0; x1 < kM; ++x1) qc[x1] = qn[x1];
+          for (int i = 0; i < kC; ++i) qc[i] = qn[i];
         }
         L[k] += P * (double)S;
       }
@@ -862,7 +876,7 @@ __global__ __launch_bounds__(256, (lz_min_blocks<1, NB>())) void k_lz_grad8(
 #pragma unroll
       for (int k = 0; k < NB; ++k) {
         d[k] = (x6 ? a6[k] : 1.0f) * (x7 ? a7[k] : 1.0f);
-        bqs[k] = lzq + ((size_t)b * kMaxBeta + k) * kLzQStride + j * (1 << V);
+        bqs[k] = lzq + ((size_t)b * kMaxBeta + k) * lz_q_stride(U) + j * (1 << V);
       }
       BlockWalk<NB, true> bw{Af, Bf, bqs, d, 0.0f};
       const Coefs C = bw.template walk<V, 0>();
@@ -989,7 +1003,10 @@ __global__ void k_lz_final_bwd(LzArgs a, float* grad_J, float* grad_h) {
 hipError_t launch_lz_prep(int mode, const LzArgs& a, const float* J, float* lzq, double* lzqmin,
                           const float* energies, float* e0_out, const double* logz,
                           const double* grad, hipStream_t st) {
-  if (mode == 0 && a.U == kLzUF)
+  if (mode == 0 && a.U == kLzUW)
+    hipLaunchKernelGGL((k_lz_prep<0, kLzUW>), dim3(a.B), dim3(256), 0, st, a, J, lzq, lzqmin,
+                       energies, e0_out, logz, grad);
+  else if (mode == 0 && a.U == kLzUF)
     hipLaunchKernelGGL((k_lz_prep<0, kLzUF>), dim3(a.B), dim3(256), 0, st, a, J, lzq, lzqmin,
                        energies, e0_out, logz, grad);
   else if (mode == 0 && a.U == kLzU)
@@ -1025,6 +1042,13 @@ hipError_t launch_logz(int mode, const LzArgs& a, const float* J, const float* h
       default: return hipErrorInvalidValue;
     }
 #undef SG_LZ8_LAUNCH
+  } else if (mode == 0 && a.U == kLzUW) {
+    switch (a.nb) {
+      case 1: SG_LZ_LAUNCH(0, 1, kLzUW); break;
+      case 2: SG_LZ_LAUNCH(0, 2, kLzUW); break;
+      case 3: SG_LZ_LAUNCH(0, 3, kLzUW); break;
+      default: return hipErrorInvalidValue;  // four beta take records of 8
+    }
   } else if (mode == 0 && a.U == kLzUF) {
     switch (a.nb) {
       case 1: SG_LZ_LAUNCH(0, 1, kLzUF); break;
