@@ -175,8 +175,9 @@ sg_status sg_low_spectrum_batched_i32(int B, const int32_t *N_dev, int N_max, co
  *                result of sg_low_spectrum_batched_f32 on the same batch
  *
  * The walk keeps its energy chain in fp64 and evaluates each weight in fp32
- * (shifted energy rounded to fp32, hardware exp2); block sums of 256 weights
- * (64 when N = 7) are fp32, every longer sum is fp64.  Relative error of
+ * (shifted energy rounded to fp32, hardware exp2); block sums of 1024 weights
+ * (256 when N = 8, 9 or n_beta = 4; 64 when N = 7) are fp32, every longer sum
+ * is fp64.  Relative error of
  * log Z: about 1e-7.  All
  * buffers are caller-owned; work is enqueued on `stream`.
  */
@@ -199,7 +200,8 @@ sg_status sg_logz_forward_f32(int B, int N, const float *J, const float *h, int 
  *   grad_J       device float[B][N][N]: written for i < j, zeros elsewhere
  *   grad_h       device float[B][N]
  *
- * Moments are summed in fp32 inside a 64-state block and in fp64 beyond it.
+ * Moments are summed in fp32 inside a 64-state block (and over the four
+ * blocks of a 256-state record) and in fp64 beyond.
  * All buffers are caller-owned; work is enqueued on `stream`.
  */
 sg_status sg_logz_backward_f32(int B, int N, const float *J, const float *h, int n_beta,
