@@ -60,8 +60,11 @@ def check_grad(gJ, gh, gJ_ref, gh_ref, what):
     assert np.all(gJ[low] == 0.0), "%s: grad_J nonzero on or below the diagonal" % what
 
 
-@pytest.mark.parametrize("N", [7, 8, 9, 13, 14, 15, 17, 20])
+@pytest.mark.parametrize("N", [7, 8, 9, 10, 11, 13, 14, 15, 17, 20])
 def test_forward_backward_vs_oracle(orc, torch_dev, N):
+    """Three instances, three beta: the partition sums over blocks of 6
+    (N = 7), 8 (N = 8, 9) and 10 (one record per lane at N = 10, two at 11),
+    the gradient walk over blocks of 6 and records of 8."""
     B = 3
     J, h = I.logz_batch(B, N, 40 + N)
     S = min(32, 1 << N)
@@ -83,8 +86,10 @@ def test_forward_backward_vs_oracle(orc, torch_dev, N):
 @pytest.mark.parametrize("betas", [[1.3], [0.25, 3.0], [0.2, 0.7, 1.5, 2.5]])
 @pytest.mark.parametrize("N", [7, 12])
 def test_beta_counts_vs_oracle(orc, torch_dev, N, betas):
-    """One, two and four inverse temperatures (each count is its own kernel),
-    with blocks of 6 low spins (N = 7) and of 8 (N = 12)."""
+    """One, two and four inverse temperatures (each count is its own kernel):
+    the partition sums over blocks of 6 low spins (N = 7), of 10 (N = 12, one
+    and two beta) and of 8 (N = 12, four beta); the gradient walk over blocks
+    of 6 (N = 7) and records of 8 (N = 12)."""
     B = 2
     J, h = I.logz_batch(B, N, 60 + N + len(betas))
     lz, _, _, _ = gpu_forward(torch_dev, J, h, betas, 8)
