@@ -553,14 +553,25 @@ std::vector<Level> batch_levels(int Nmax, int S, int shift) {
 // finalize into states_out / energies_out.
 sg_status batch_search(Workspace* w, bool isint, const Batch& bt0, int Nmax, int ncap,
                        uint64_t* states_out, void* energies_out, hipStream_t st) {
-  // levels whose lanes have n >= kUWide free spins walk blocks of kUWide,
-  // the others (n = kU) blocks of kU: the one record of n = kU comes first,
-  // then the records of kUWide for n = kUWide .. ncap
+  // levels whose lanes have n >= kUPk + 2 free spins walk blocks of kUPk,
+  // those of n >= kUWide blocks of kUWide, the others (n = kU) blocks of kU:
+  // the one record of n = kU comes first, then the records of kUWide for
+  // n = kUWide .. ncap, then those of kUPk
   Batch bt = bt0;
   bt.table_base8 = (int64_t)table_records(kU);
+  // levels of n >= kUPk + 2 walk blocks of kUPk (paired, fp32 walks), from
+  // tables that follow those of kUWide in each instance's region
+  const bool use10 = ncap >= kUPk + 2;
+  bt.table_base10w =
+      (bt.table_base8 + (int64_t)(((size_t)1 << (ncap - kUWide + 1)) - 1)) * kRecWords;
+  if (use10 && (size_t)bt.table_base10w + (((size_t)1 << (ncap - kUPk + 1)) - 1) *
+                                               (size_t)rec_words(kUPk) >
+                   (size_t)bt.table_recs * kRecWords)
+    return fail(SG_EUNSUPPORTED, "table buffer too small for the blocks of 10");
   HIP_TRY(launch_prep(isint, bt, st));
   HIP_TRY(launch_tables(isint, kU, bt, kU, false, st));
   if (ncap >= kUWide) HIP_TRY(launch_tables(isint, kUWide, bt, ncap, true, st));
+  if (use10) HIP_TRY(launch_tables(isint, kUPk, bt, ncap, true, st));
   const std::vector<Level> levels =
       batch_levels(Nmax, bt.S, batch_shift(bt.B, Nmax, bt.S, w->fill[isint ? 1 : 0]));
   w->ev_used = 0;
@@ -573,8 +584,10 @@ sg_status batch_search(Workspace* w, bool isint, const Batch& bt0, int Nmax, int
     ch.prefix_base = L.first >> L.n;
     ch.lanes = L.lanes;
     ch.n = L.n;
-    const int U = L.n >= kUWide ? kUWide : kU;
-    ch.table_offset = (U == kUWide ? (int)bt.table_base8 : 0) + (1 << (L.n - U)) - 1;
+    const int U = use10 && L.n >= kUPk + 2 ? kUPk : L.n >= kUWide ? kUWide : kU;
+    ch.table_offset = U == kUPk ? (1 << (L.n - kUPk)) - 1
+                                : (U == kUWide ? (int)bt.table_base8 : 0) + (1 << (L.n - U)) - 1;
+    ch.table_offset8 = (int)bt.table_base8 + (1 << (L.n - kUWide)) - 1;
     const uint64_t lstates = (uint64_t)L.lanes << L.n;
     const int passes = lstates > (uint64_t)bt.cap ? 1 + kRetries : 1;
     for (int r = 0; r < passes; ++r) {

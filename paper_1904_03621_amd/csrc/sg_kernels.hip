@@ -217,8 +217,8 @@ __global__ void k_prep(Batch bt) {
   const double qmin7 = prep_qtab<kInt, kU>(Jb, ld, Nc, walk_f32, qtab + qtab_base(kU), s_q);
   const double qmin8 =
       prep_qtab<kInt, kUWide>(Jb, ld, Nc, walk_f32, qtab + qtab_base(kUWide), s_q);
-  // blocks of kUPk: single searches whose walk is in fp32
-  const bool pk10 = !bt.Ns && (!kInt || walk_f32);
+  // blocks of kUPk: walks in fp32
+  const bool pk10 = !kInt || walk_f32;
   const double qmin10 =
       pk10 ? prep_qtab<kInt, kUPk>(Jb, ld, Nc, walk_f32, qtab + qtab_base(kUPk), s_q) : 0.0;
   if (tid == 0) {
@@ -499,13 +499,13 @@ __global__ __launch_bounds__(kEnumBlock, U == kUPk ? 7 : 8) void k_enum(Batch bt
     // blocks of 10: fp32 walks; an integer instance that takes the int32
     // walk walks the chunk's blocks of 8 instead
     if (!kInt || P->walk_f32) {
-      enum_walk<kInt, true, kUPk, false, true>(bt, Jv, hv, table, qtab_all, ch, b, blk, N, n,
-                                               lanes, P, s_y, s_F, s_R, s_EH);
+      enum_walk<kInt, true, kUPk, kSplit, true>(bt, Jv, hv, table, qtab_all, ch, b, blk, N, n,
+                                                lanes, P, s_y, s_F, s_R, s_EH);
     } else if constexpr (kInt) {
       Chunk c8 = ch;
       c8.table_offset = ch.table_offset8;
-      enum_walk<true, false, kUWide, false, false>(bt, Jv, hv, table, qtab_all, c8, b, blk, N,
-                                                   n, lanes, P, s_y, s_F, s_R, s_EH);
+      enum_walk<true, false, kUWide, kSplit, false>(bt, Jv, hv, table, qtab_all, c8, b, blk, N,
+                                                    n, lanes, P, s_y, s_F, s_R, s_EH);
     }
   } else {
     if (kInt && P->walk_f32)
@@ -802,27 +802,26 @@ __device__ __forceinline__ void enum_walk(const Batch& bt, const void* __restric
   };
 
   // Re-walk of a block of more than 256 steps (fp32 walks), as a loop over
-  // passes of 64 steps: the hits of a pass are appended at its end, with one
-  // slot reservation per wave and pass that has any.
-  auto rewalk_long = [&](uint32_t T, const V (&W)[U], V G0, bool pass) {
+  // its passes of 64 steps: pass w is walked when bit w of some lane's pmask
+  // is set, from its start value (G0 and the net steps of the spins that are
+  // up at step 64 w); its hits are appended at its end, with one slot
+  // reservation per wave and pass that has any.
+  auto rewalk_long = [&](uint32_t T, const V (&W)[U], V G0, uint32_t pmask) {
     ++slow;
     const uint32_t* q = qtab + (T & 1u) * kSteps;
     auto qv = [&](int i) -> V { return (V)__uint_as_float(q[i]); };
-    V g2 = G0;
-    asm volatile("" : "+v"(g2));
     const uint64_t pl = ch.prefix_base + (uint64_t)lane;
 #pragma nounroll
     for (int w = 0; w < kSteps / 64; ++w) {
-      if (w > 0) {
-        // step 64 w flips spin 6 + ctz(w): old value +1 iff the next bit of
-        // the step index is set; spin U-1 flips once, up
-        const int f = 6 + __builtin_ctz((uint32_t)w);
-        V wf = W[6];
+      const bool mine = (pmask >> w) & 1u;
+      if (__ballot(mine) == 0ull) continue;  // wave-uniform
+      const uint32_t g0 = (uint32_t)(64 * w) ^ (uint32_t)(32 * w);  // gray(64 w)
+      V g2 = G0;
 #pragma unroll
-        for (int k = 7; k < U; ++k) wf = f == k ? W[k] : wf;
-        if (f == U - 1) g2 = g2 + wf;
-        else g2 = (((uint32_t)(64 * w) >> (f + 1)) & 1u) ? g2 + wf : g2 - wf;
-      }
+      for (int f = 5; f < U - 1; ++f)
+        if ((g0 >> f) & 1u) g2 = g2 - W[f];
+      if ((g0 >> (U - 1)) & 1u) g2 = g2 + W[U - 1];
+      asm volatile("" : "+v"(g2));
       uint64_t hw = (g2 + qv(64 * w) <= thrE) ? 1ull : 0ull;
 #pragma unroll
       for (int j = 1; j < 64; ++j) {
@@ -831,7 +830,7 @@ __device__ __forceinline__ void enum_walk(const Batch& bt, const void* __restric
         else g2 = ((j >> (f + 1)) & 1) ? g2 + W[f] : g2 - W[f];
         if (g2 + qv(64 * w + j) <= thrE) hw |= 1ull << j;
       }
-      if (!(valid && pass)) hw = 0ull;
+      if (!mine) hw = 0ull;
       const uint32_t nh = (uint32_t)__popcll(hw);
       uint32_t incl = nh;
 #pragma unroll
@@ -881,9 +880,8 @@ __device__ __forceinline__ void enum_walk(const Batch& bt, const void* __restric
   };
 
   if constexpr (kPk) {
-    static_assert(!kPk || (kWF && (U == kUWide || (U == kUPk && !kSplit)) &&
-                           (!kSplit || kSub == 64)),
-                  "paired walk: fp32 walks, blocks of 8 (or 10 unsplit), sub-blocks of 64");
+    static_assert(!kPk || (kWF && (U == kUWide || U == kUPk) && (!kSplit || kSub == 64)),
+                  "paired walk: fp32 walks, blocks of 8 or 10, sub-blocks of 64");
     // ---- paired walk ----------------------------------------------------------
     // (blocks of kUWide, or of kUPk for the chunks of a single search with
     // n >= kUPk + 2.)  Blocks T and T + half (half = nblocks / 2, n >= U + 2:
@@ -967,8 +965,9 @@ __device__ __forceinline__ void enum_walk(const Batch& bt, const void* __restric
       // spin 6 (down, then up) or 7.  (Unrolled over the whole block, the same
       // steps measured 43% of the VALU instructions issued in pairs against
       // 81% for the loop, and 18% slower.)
-      // fired (batches): bit w (field A) / bit 8 + w (field B) set when
+      // fired (batches): bit w (field A) / bit kFHi + w (field B) set when
       // sub-block w may hold a state below the bound
+      constexpr int kFHi = kSteps / 64 <= 8 ? 8 : 16;
       uint32_t g = za + (zb << 16);
       uint32_t acc = 0xFFFFFFFFu;
       uint32_t fired = 0u;
@@ -985,7 +984,7 @@ __device__ __forceinline__ void enum_walk(const Batch& bt, const void* __restric
           asm volatile("v_and_b32 %0, %0, %1" : "+v"(accw) : "v"(g));
         }
         if (kSplit) {
-          fired |= ((((accw >> 15) & 1u) ^ 1u) << w) | ((((accw >> 31) & 1u) ^ 1u) << (8 + w));
+          fired |= ((((accw >> 15) & 1u) ^ 1u) << w) | ((((accw >> 31) & 1u) ^ 1u) << (kFHi + w));
         } else {
           acc &= accw;
         }
@@ -1031,16 +1030,27 @@ __device__ __forceinline__ void enum_walk(const Batch& bt, const void* __restric
           s7 = 0u - s7;
         }
       }
+      // which 64-step passes of each block to re-walk: bit w of ma / mb (every
+      // pass of a block whose whole-block test fired, without kSplit)
+      constexpr uint32_t kAll = (1u << (kSteps / 64)) - 1u;
+      uint32_t ma, mb;
+      if (kSplit) {
+        ma = fired & kAll;
+        mb = (fired >> kFHi) & kAll;
+      } else {
+        ma = (acc & 0x8000u) == 0u ? kAll : 0u;
+        mb = (acc & 0x80000000u) == 0u ? kAll : 0u;
+      }
+      if (!armed) ma = mb = kAll;
+      if (!valid) ma = mb = 0u;
+      const bool anya = ma != 0u, anyb = mb != 0u;
+      // per sub-block of the walk over blocks of 8 (one sub-block per block
+      // without kSplit, one per pass with it)
       bool pa[kNSub], pb[kNSub];
-      bool anya = false, anyb = false;
 #pragma unroll
       for (int w = 0; w < kNSub; ++w) {
-        const bool fa = kSplit ? ((fired >> w) & 1u) != 0u : (acc & 0x8000u) == 0u;
-        const bool fb = kSplit ? ((fired >> (8 + w)) & 1u) != 0u : (acc & 0x80000000u) == 0u;
-        pa[w] = valid && (!armed || fa);
-        pb[w] = valid && (!armed || fb);
-        anya = anya || pa[w];
-        anyb = anyb || pb[w];
+        pa[w] = kSplit ? ((ma >> w) & 1u) != 0u : anya;
+        pb[w] = kSplit ? ((mb >> w) & 1u) != 0u : anyb;
       }
       const V wl = odd ? WL[U - 1] : -WL[U - 1];
       // the fp32 steps of a block, formed only on the rare re-walk
@@ -1068,7 +1078,7 @@ __device__ __forceinline__ void enum_walk(const Batch& bt, const void* __restric
         V W[U], gs[kNSub];
         steps(recA, W);
         if constexpr (kSteps > 256) {
-          rewalk_long(T, W, GA, pa[0]);
+          rewalk_long(T, W, GA, ma);
         } else {
           starts(GA, W, gs);
           rewalk(T, W, gs, pa);
@@ -1078,7 +1088,7 @@ __device__ __forceinline__ void enum_walk(const Batch& bt, const void* __restric
         V W[U], gs[kNSub];
         steps(recB, W);
         if constexpr (kSteps > 256) {
-          rewalk_long(TB, W, GB, pb[0]);
+          rewalk_long(TB, W, GB, mb);
         } else {
           starts(GB, W, gs);
           rewalk(TB, W, gs, pb);
@@ -1619,7 +1629,7 @@ bool enum_paired(int U, int n) {
 hipError_t launch_enum(bool isint, int U, bool split, const Batch& bt, const Chunk& ch, int ninst,
                        hipStream_t st) {
   if ((U != kU && U != kUWide && U != kUPk) || ch.n < U) return hipErrorInvalidValue;
-  if (U == kUPk && (split || !enum_paired(U, ch.n))) return hipErrorInvalidValue;
+  if (U == kUPk && !enum_paired(U, ch.n)) return hipErrorInvalidValue;
   const int bpi = (int)((ch.lanes + kEnumBlock - 1) / kEnumBlock);
   const dim3 grid((unsigned)((int64_t)bpi * ninst));
 #define SG_ENUM(I, UV, SP, PK)                                                                 \
@@ -1629,8 +1639,13 @@ hipError_t launch_enum(bool isint, int U, bool split, const Batch& bt, const Chu
   if (U == kU) SG_ENUM(I, kU, SP, false); \
   else SG_ENUM(I, kUWide, SP, false)
   if (U == kUPk) {
-    if (isint) SG_ENUM(true, kUPk, false, true);
-    else SG_ENUM(false, kUPk, false, true);
+    if (isint) {
+      if (split) SG_ENUM(true, kUPk, true, true);
+      else SG_ENUM(true, kUPk, false, true);
+    } else {
+      if (split) SG_ENUM(false, kUPk, true, true);
+      else SG_ENUM(false, kUPk, false, true);
+    }
   } else if (enum_paired(U, ch.n)) {
     if (isint) {
       if (split) SG_ENUM(true, kUWide, true, true);
@@ -1709,6 +1724,7 @@ int enum_occupancy_t() {
   take((const void*)k_enum<I, kUWide, false, true>);
   take((const void*)k_enum<I, kUWide, true, true>);
   take((const void*)k_enum<I, kUPk, false, true>);
+  take((const void*)k_enum<I, kUPk, true, true>);
   return best;
 }
 
