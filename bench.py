@@ -46,21 +46,21 @@ COPY_BYTES = 512 << 20
 # blocks of 10 in one search), scaled by what the same counters read for the
 # 512 MiB copy (fetch x2.0, write x1.0); valid for the k_enum source with this
 # SHA-256 prefix only
-TRAFFIC = {"kenum_sha256_16": "5566fac3a3ce0dda", "fetch_kib": 1825452.3 / 486,
-           "write_kib": 14967418.8 / 486, "fetch_factor": 524288.0 / 262172.5, "write_factor": 1.0,
+TRAFFIC = {"kenum_sha256_16": "ab33227a98339046", "fetch_kib": 880124.75 / 486,
+           "write_kib": 2862972.7 / 486, "fetch_factor": 524288.0 / 262172.0, "write_factor": 1.0,
            "profile": "profiles/k_enum_f32_dense48_counters.md"}
 
 # VALU counters of the search's paired-walk launches (rocprofv3 --pmc, one
-# search of this instance, 486 dispatches, 4.959 s of kernel time), valid for
+# search of this instance, 486 dispatches, 4.879 s of kernel time), valid for
 # the k_enum source with this hash only: SQ_INSTS_VALU (wave instructions) x 64
 # / 2^48 per configuration; the fraction of the doubled-rate issue capacity
 # used, SQ_INSTS_VALU / (1024 SIMDs x cycles x 1/2); the share issued in pairs,
 # 2 SQ_ACTIVE_INST_VALU2 / SQ_INSTS_VALU; and sclk = GRBM_GUI_ACTIVE / 8 XCDs /
 # kernel time.
-COUNTERS = {"kenum_sha256_16": "5566fac3a3ce0dda", "valu_insts_per_state": 4.72181e12 * 64 / 2 ** 48,
-            "valu_active": 4.72181e12 / (1024 * 8.79117e10 / 8 * 0.5),
-            "valu_paired": 2 * 2.10129e12 / 4.72181e12,
-            "sclk_ghz": 8.79117e10 / 8 / 4.959 / 1e9,
+COUNTERS = {"kenum_sha256_16": "ab33227a98339046", "valu_insts_per_state": 4.73712e12 * 64 / 2 ** 48,
+            "valu_active": 4.73712e12 / (1024 * 8.67720e10 / 8 * 0.5),
+            "valu_paired": 2 * 2.12849e12 / 4.73712e12,
+            "sclk_ghz": 8.67720e10 / 8 / 4.879 / 1e9,
             "profile": "profiles/k_enum_f32_dense48_counters.md"}
 
 
