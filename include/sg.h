@@ -210,6 +210,35 @@ sg_status sg_logz_backward_f32(int B, int N, const float *J, const float *h, int
                                void *stream);
 
 /*
+ * The same gradients as sg_logz_backward_f32, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight training or
+ * serving loops, harnesses that forbid hipMalloc.  The call allocates
+ * nothing: its block records, bq tables, weights, fp64 accumulators and
+ * error word live in a static device array of SG_LOGZ_SCRATCH_BYTES bytes
+ * that each device running the library holds until the process ends (its
+ * device address is looked up once per device, on the first call there).
+ * Arguments, outputs and results are those of sg_logz_backward_f32 on the
+ * same stream (same decomposition, same kernels).
+ *
+ *   SG_EINVAL  also when B and N need more than SG_LOGZ_SCRATCH_BYTES: at
+ *              most B (14 KiB + 8 (N^2 + N) bytes), so every B <= 1200 fits
+ *              for N <= 40 (the message gives the bytes a refused call needs).
+ *
+ * All calls on one device share that device's array and it keeps the last
+ * call's contents (the accumulators are cleared by every call): calls that
+ * overlap on one device -- on different streams, or from different host
+ * threads -- race and must be serialised by the caller.  Device-side errors
+ * are ORed into the array's error word, which sg_get_error reports and
+ * clears (pass it the stream of the call, so that it waits for it).
+ */
+#define SG_LOGZ_SCRATCH_BYTES (32ull << 20)
+
+sg_status sg_logz_backward_noalloc_f32(int B, int N, const float *J, const float *h, int n_beta,
+                                       const float *beta, const float *e0, const double *logz,
+                                       const double *grad_logz, float *grad_J, float *grad_h,
+                                       void *stream);
+
+/*
  * QUBO front end (Sec. 2, Eqs. 2-3): the S lowest of
  *     F(q) = - sum_{i<j} a_ij q_i q_j - sum_i b_i q_i ,   q_i in {0, 1},
  * over all 2^N binary vectors, found by the Ising search on the instance of
@@ -289,7 +318,8 @@ sg_status sg_tune_batched_f32(int B, const int32_t *N_dev, int N_max, const floa
                               const float *h, int S, int *shift_out, void *stream);
 
 /* Waits for `stream`, then returns and clears the sticky device error of the
- * calls enqueued on it (SG_OK if none). */
+ * calls enqueued on it, together with that of the current device's static
+ * scratch (sg_logz_backward_noalloc_f32) (SG_OK if none). */
 sg_status sg_get_error(void *stream);
 
 /* Human-readable text of the last failure on the calling thread ("" if none). */

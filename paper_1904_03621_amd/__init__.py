@@ -16,6 +16,6 @@ from ._lib import (  # noqa: F401
     sg_low_spectrum_range_i32, sg_get_error, sg_get_run_info, sg_debug_plan,
     sg_set_kernel_timing, sg_probe_valu, sg_low_spectrum_batched_f32,
     sg_low_spectrum_batched_i32, sg_logz_forward_f32, sg_logz_backward_f32,
-    sg_reserve, sg_density_of_states_i32, sg_energy_bound_i32, sg_tune_batched_f32,
+    sg_logz_backward_noalloc_f32, sg_reserve, sg_density_of_states_i32, sg_energy_bound_i32, sg_tune_batched_f32,
     sg_low_spectrum_qubo_f32,
 )

@@ -30,7 +30,8 @@ EXPORTS = [
     "sg_low_spectrum_f32", "sg_low_spectrum_i32",
     "sg_low_spectrum_range_f32", "sg_low_spectrum_range_i32",
     "sg_low_spectrum_batched_f32", "sg_low_spectrum_batched_i32",
-    "sg_logz_forward_f32", "sg_logz_backward_f32", "sg_reserve",
+    "sg_logz_forward_f32", "sg_logz_backward_f32", "sg_logz_backward_noalloc_f32",
+    "sg_reserve",
     "sg_density_of_states_i32", "sg_energy_bound_i32", "sg_tune_batched_f32",
     "sg_low_spectrum_qubo_f32",
     "sg_get_error", "sg_last_error", "sg_get_run_info", "sg_debug_plan",
@@ -103,6 +104,9 @@ def lib() -> ctypes.CDLL:
         L.sg_logz_forward_f32.argtypes = [i32, i32, vp, vp, i32, vp, i32, vp, vp, vp, vp, vp]
         L.sg_logz_backward_f32.restype = i32
         L.sg_logz_backward_f32.argtypes = [i32, i32, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]
+        L.sg_logz_backward_noalloc_f32.restype = i32
+        L.sg_logz_backward_noalloc_f32.argtypes = [i32, i32, vp, vp, i32, vp, vp, vp, vp, vp, vp,
+                                                   vp]
         L.sg_density_of_states_i32.restype = i32
         L.sg_density_of_states_i32.argtypes = [i32, vp, vp, ctypes.c_longlong, i32, vp, vp]
         L.sg_energy_bound_i32.restype = i32
@@ -203,6 +207,13 @@ def sg_logz_backward_f32(B, N, J, h, n_beta, beta, e0, logz, grad_logz, grad_J, 
     return lib().sg_logz_backward_f32(B, N, _ptr(J), _ptr(h), n_beta, _ptr(beta), _ptr(e0),
                                       _ptr(logz), _ptr(grad_logz), _ptr(grad_J), _ptr(grad_h),
                                       _stream(stream))
+
+
+def sg_logz_backward_noalloc_f32(B, N, J, h, n_beta, beta, e0, logz, grad_logz, grad_J, grad_h,
+                                 stream=None) -> int:
+    return lib().sg_logz_backward_noalloc_f32(B, N, _ptr(J), _ptr(h), n_beta, _ptr(beta),
+                                              _ptr(e0), _ptr(logz), _ptr(grad_logz),
+                                              _ptr(grad_J), _ptr(grad_h), _stream(stream))
 
 
 def sg_density_of_states_i32(N, J, h, e_min, n_bins, counts_out, stream=None) -> int:

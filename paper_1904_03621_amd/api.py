@@ -113,9 +113,12 @@ def logz_forward(J, h, beta, S: int, stream=None, check: bool = True):
     return logz, e0, states, energies
 
 
-def logz_backward(J, h, beta, e0, logz, grad_logz, stream=None, check: bool = True):
+def logz_backward(J, h, beta, e0, logz, grad_logz, stream=None, check: bool = True,
+                  no_alloc: bool = False):
     """Gradients (grad_J [B, N, N], upper triangle; grad_h [B, N]) of
-    sum grad_logz * logz with respect to J and h."""
+    sum grad_logz * logz with respect to J and h.  no_alloc: take the entry
+    point whose buffers live in the library's static device scratch (it
+    allocates no device memory; limited in B and N)."""
     import torch
     J, h, beta = _prep_logz(J, h, beta)
     B, N, K = J.shape[0], J.shape[1], beta.shape[0]
@@ -126,8 +129,9 @@ def logz_backward(J, h, beta, e0, logz, grad_logz, stream=None, check: bool = Tr
     e0 = e0.to(torch.float32).contiguous()
     gJ = torch.empty((B, N, N), dtype=torch.float32, device=J.device)
     gh = torch.empty((B, N), dtype=torch.float32, device=J.device)
-    st = _lib.sg_logz_backward_f32(B, N, J, h, K, beta, e0, logz, grad_logz, gJ, gh, stream)
-    _lib.check(st, "sg_logz_backward_f32")
+    fn = _lib.sg_logz_backward_noalloc_f32 if no_alloc else _lib.sg_logz_backward_f32
+    st = fn(B, N, J, h, K, beta, e0, logz, grad_logz, gJ, gh, stream)
+    _lib.check(st, fn.__name__)
     if check:
         _lib.check(_lib.sg_get_error(stream), "device")
     return gJ, gh

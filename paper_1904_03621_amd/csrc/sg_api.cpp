@@ -41,6 +41,9 @@ hipError_t launch_logz(int mode, const LzArgs& a, const float* J, const float* h
                        hipStream_t st);
 hipError_t launch_lz_final(int mode, const LzArgs& a, double* logz, float* grad_J, float* grad_h,
                            hipStream_t st);
+hipError_t lz_scratch(void** ptr, bool* fresh);
+void* lz_scratch_resolved();
+hipError_t launch_clear_word(uint32_t* p, hipStream_t st);
 hipError_t launch_dos_prologue(const Batch& bt, long long e_min, int n_bins,
                                unsigned long long* counts, hipStream_t st);
 hipError_t launch_dos(const Batch& bt, const Chunk& ch, long long e_min, int n_bins,
@@ -658,8 +661,10 @@ sg_status lz_buffers(Workspace* w, int B, int N) {
   return SG_OK;
 }
 
-LzArgs lz_args(Workspace* w, int B, int N, int nb, int S, const float* h, const float* beta,
-               const float* e0, int mode) {
+// The walk's geometry for `fill` resident lanes; coef, acc and sticky are
+// left for the caller to point at its buffers.
+LzArgs lz_geometry(int64_t fill, int B, int N, int nb, int S, const float* h, const float* beta,
+                   const float* e0, int mode) {
   LzArgs a{};
   a.B = B;
   a.N = N;
@@ -671,7 +676,7 @@ LzArgs lz_args(Workspace* w, int B, int N, int nb, int S, const float* h, const 
   // free spins per lane: at most kLzFree, fewer when the batch alone would
   // not give every resident lane of the device a prefix
   a.n = std::min(kLzFree, N);
-  while (a.n > a.U && (int64_t)B * ((int64_t)1 << (N - a.n)) < w->fill[0]) --a.n;
+  while (a.n > a.U && (int64_t)B * ((int64_t)1 << (N - a.n)) < fill) --a.n;
   a.nb = nb;
   a.S = S;
   a.lanes = (int64_t)1 << (N - a.n);
@@ -680,11 +685,39 @@ LzArgs lz_args(Workspace* w, int B, int N, int nb, int S, const float* h, const 
   a.h_in = h;
   a.beta = beta;
   a.e0 = e0;
+  a.acc_stride = mode == 0 ? kMaxBeta : N * N + N;
+  return a;
+}
+
+LzArgs lz_args(Workspace* w, int B, int N, int nb, int S, const float* h, const float* beta,
+               const float* e0, int mode) {
+  LzArgs a = lz_geometry(w->fill[0], B, N, nb, S, h, beta, e0, mode);
   a.coef = w->lz_coef;
   a.acc = w->lz_acc;
-  a.acc_stride = mode == 0 ? kMaxBeta : N * N + N;
   a.sticky = w->sticky;
   return a;
+}
+
+// Resident lanes of the fp32 walk on device dev, for calls that have no
+// workspace (queried once per device; allocates no device memory).
+std::map<int, int64_t> g_dev_fill;
+
+sg_status device_fill(int dev, int64_t* fill) {
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_dev_fill.find(dev);
+    if (it != g_dev_fill.end()) {
+      *fill = it->second;
+      return SG_OK;
+    }
+  }
+  Workspace probe;
+  const sg_status v = ws_describe(dev, &probe);
+  if (v != SG_OK) return v;
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_dev_fill[dev] = probe.fill[0];
+  *fill = probe.fill[0];
+  return SG_OK;
 }
 
 Workspace* ws_find(hipStream_t st) {
@@ -801,6 +834,75 @@ sg_status sg_logz_backward_f32(int B, int N, const float* J, const float* h, int
   HIP_TRY(launch_tables64(b64, a.n, a.U, w->table64, st));
   HIP_TRY(launch_lz_prep(1, a, J, w->lzq, w->lzqmin, nullptr, nullptr, logz, grad_logz, st));
   HIP_TRY(launch_logz(1, a, J, h, w->table64, w->lzq, w->lzqmin, st));
+  HIP_TRY(launch_lz_final(1, a, nullptr, grad_J, grad_h, st));
+  return SG_OK;
+}
+
+static_assert(SG_LOGZ_SCRATCH_BYTES == kLzScratchBytes, "scratch size differs from the header");
+
+sg_status sg_logz_backward_noalloc_f32(int B, int N, const float* J, const float* h, int n_beta,
+                                       const float* beta, const float* e0, const double* logz,
+                                       const double* grad_logz, float* grad_J, float* grad_h,
+                                       void* stream) {
+  g_last_error.clear();
+  sg_status v = lz_validate(B, N, J, h, n_beta, beta);
+  if (v != SG_OK) return v;
+  if (!e0 || !logz || !grad_logz || !grad_J || !grad_h)
+    return fail(SG_EINVAL, "null pointer argument");
+  hipStream_t st = (hipStream_t)stream;
+  // the decomposition of sg_logz_backward_f32 on this stream
+  int64_t fill = 0;
+  if (Workspace* w = ws_find(st)) {
+    fill = w->fill[0];
+  } else {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    v = device_fill(dev, &fill);
+    if (v != SG_OK) return v;
+  }
+  LzArgs a = lz_geometry(fill, B, N, n_beta, 1, h, beta, e0, 1);
+  // scratch layout: the error word, then each buffer at a 256-byte boundary
+  const size_t Bz = (size_t)B;
+  size_t used = 256;
+  auto take = [&used](size_t bytes) {
+    const size_t at = used;
+    used += (bytes + 255) & ~(size_t)255;
+    return at;
+  };
+  const size_t o_tab = take(Bz * (size_t)a.table_recs * (2 + a.U) * sizeof(double));
+  const size_t o_q = take(Bz * kMaxBeta * (size_t)lz_q_stride(a.U) * sizeof(float));
+  const size_t o_qmin = take(Bz * sizeof(double));
+  const size_t o_acc = take(Bz * (size_t)a.acc_stride * sizeof(double));
+  const size_t o_coef = take(Bz * 2 * kMaxBeta * sizeof(double));
+  if (used > kLzScratchBytes)
+    return fail(SG_EINVAL, "B = " + std::to_string(B) + ", N = " + std::to_string(N) +
+                               " needs " + std::to_string(used) +
+                               " bytes of device scratch, more than the SG_LOGZ_SCRATCH_BYTES = " +
+                               std::to_string(kLzScratchBytes) +
+                               " this entry point holds (sg_logz_backward_f32 has no such limit)");
+  void* base = nullptr;
+  bool fresh = false;
+  HIP_TRY(lz_scratch(&base, &fresh));
+  char* sp = (char*)base;
+  uint32_t* err = (uint32_t*)sp;
+  if (fresh) HIP_TRY(launch_clear_word(err, st));
+  double* tab = (double*)(sp + o_tab);
+  float* lzq = (float*)(sp + o_q);
+  double* lzqmin = (double*)(sp + o_qmin);
+  a.acc = (double*)(sp + o_acc);  // cleared by the prep kernel
+  a.coef = (double*)(sp + o_coef);
+  a.sticky = err;
+  Batch b64{};
+  b64.J = J;
+  b64.h = h;
+  b64.Ns = nullptr;
+  b64.N0 = N;
+  b64.ld = N;
+  b64.B = B;
+  b64.table_recs = a.table_recs;
+  HIP_TRY(launch_tables64(b64, a.n, a.U, tab, st));
+  HIP_TRY(launch_lz_prep(1, a, J, lzq, lzqmin, nullptr, nullptr, logz, grad_logz, st));
+  HIP_TRY(launch_logz(1, a, J, h, tab, lzq, lzqmin, st));
   HIP_TRY(launch_lz_final(1, a, nullptr, grad_J, grad_h, st));
   return SG_OK;
 }
@@ -976,11 +1078,18 @@ sg_status sg_low_spectrum_qubo_f32(int N, const float* A, const float* b, int S,
 sg_status sg_get_error(void* stream) {
   hipStream_t st = (hipStream_t)stream;
   HIP_TRY(hipStreamSynchronize(st));
-  Workspace* w = ws_find(st);
-  if (!w) return SG_OK;
   uint32_t bits = 0;
-  HIP_TRY(hipMemcpy(&bits, w->sticky, sizeof(bits), hipMemcpyDeviceToHost));
-  HIP_TRY(hipMemset(w->sticky, 0, sizeof(uint32_t)));
+  if (Workspace* w = ws_find(st)) {
+    HIP_TRY(hipMemcpy(&bits, w->sticky, sizeof(bits), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemset(w->sticky, 0, sizeof(uint32_t)));
+  }
+  // the error word of the device's static scratch (allocation-free calls)
+  if (void* sp = lz_scratch_resolved()) {
+    uint32_t sbits = 0;
+    HIP_TRY(hipMemcpy(&sbits, sp, sizeof(sbits), hipMemcpyDeviceToHost));
+    if (sbits) HIP_TRY(hipMemset(sp, 0, sizeof(uint32_t)));
+    bits |= sbits;
+  }
   return status_of_bits(bits);
 }
 

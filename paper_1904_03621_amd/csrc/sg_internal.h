@@ -72,6 +72,9 @@ constexpr int kLzSteps = 1 << kLzU;
 // for records of 10 (the same buffer, [B][kMaxBeta][stride])
 constexpr int lz_q_stride(int U) { return U > kLzUF ? 1 << U : 1 << kLzUF; }
 constexpr int kLzQStride = lz_q_stride(kLzUW);  // the buffer's floats per (instance, beta)
+// Bytes of the static device array that the allocation-free log Z backward
+// takes its buffers from (one array per device, held until the process ends).
+constexpr unsigned long long kLzScratchBytes = 32ull << 20;
 constexpr int kWaveLanes = 64;
 constexpr int kEnumBlock = 256;       // threads per enumeration workgroup
 constexpr int kMergeThreads = 1024;   // threads of the single-workgroup merge

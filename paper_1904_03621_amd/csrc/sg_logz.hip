@@ -46,6 +46,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
+#include <mutex>
+
 #include "sg_internal.h"
 
 namespace sg {
@@ -1085,6 +1088,59 @@ hipError_t launch_lz_final(int mode, const LzArgs& a, double* logz, float* grad_
     hipLaunchKernelGGL(k_lz_final_bwd, dim3((tot + 255) / 256, a.B), dim3(256), 0, st, a, grad_J,
                        grad_h);
   }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ static scratch
+// The allocation-free backward keeps its block records, bq tables, weights,
+// accumulators and error word in this array instead of a workspace.  Every
+// device holds its own copy from the library's load until the process ends;
+// host code reaches it only through the device address that lz_scratch
+// resolves (the array's name is a host-side stand-in there).
+
+static __device__ __align__(256) unsigned char scratch[kLzScratchBytes];
+
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_addr;  // device -> address of its scratch
+
+__global__ void k_clear_word(uint32_t* p) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *p = 0u;
+}
+
+// Device address of the current device's scratch; *fresh is set on the call
+// that resolves it (once per device), after which the caller clears the
+// array's error word.
+hipError_t lz_scratch(void** ptr, bool* fresh) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_addr.find(dev);
+  if (it != g_scratch_addr.end()) {
+    *ptr = it->second;
+    *fresh = false;
+    return hipSuccess;
+  }
+  void* p = nullptr;
+  e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_addr[dev] = p;
+  *ptr = p;
+  *fresh = true;
+  return hipSuccess;
+}
+
+// The current device's scratch address if it was resolved, else null.
+void* lz_scratch_resolved() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_addr.find(dev);
+  return it == g_scratch_addr.end() ? nullptr : it->second;
+}
+
+hipError_t launch_clear_word(uint32_t* p, hipStream_t st) {
+  hipLaunchKernelGGL(k_clear_word, dim3(1), dim3(64), 0, st, p);
   return hipGetLastError();
 }
 

@@ -78,6 +78,8 @@ def test_batched_and_logz_validation_is_synchronous(L, case):
     if "S" not in case:
         st = lib.sg_logz_backward_f32(B, N, p, p, nb, p, p, p, p, p, p, 0)
         assert st == L.SG_EINVAL and L.last_error() != ""
+        st = lib.sg_logz_backward_noalloc_f32(B, N, p, p, nb, p, p, p, p, p, p, 0)
+        assert st == L.SG_EINVAL and L.last_error() != ""
     if "nb" not in case and not (N == 7 and S == 129):
         st = lib.sg_low_spectrum_batched_f32(B, p, N, p, p, S, p, p, 0)
         assert st == L.SG_EINVAL and L.last_error() != ""
