@@ -417,7 +417,9 @@ sg_status search_on(Workspace* w, bool isint, int N, const void* J, const void* 
   const int ncap = std::min(kMaxFree, std::max(N, U));
   Batch bt = make_batch(w, J, h, nullptr, N, N, 1, S, (int64_t)recs, cap);
   // chunks of n >= kUPk + 2 free spins walk blocks of kUPk (paired, fp32
-  // walks); their tables follow the records of U = kUWide
+  // walks; three at a time from n >= kUPk + kTriMinM); their tables follow
+  // the records of U = kUWide
+  bt.tri = 1;
   const bool use10 = U == kUWide && ncap >= kUPk + 2;
   bt.table_base10w = (int64_t)(((size_t)1 << (ncap - kUWide + 1)) - 1) * kRecWords;
   if (use10 && (size_t)bt.table_base10w + (((size_t)1 << (ncap - kUPk + 1)) - 1) *

@@ -130,7 +130,32 @@ struct Params {
   int32_t pk_slack;
   float pk_scale10;      // the same for the blocks of kUPk (slack kUPk + 1)
   int32_t pk_slack10;
+  // three-field walk (blocks of kUPk, single searches): the power-of-two
+  // scale of its values, and the part of the bound on a block's summed step
+  // magnitudes (units) that does not depend on the lane
+  float pk_scale3;
+  int32_t pk_rb3;
 };
+
+// Three-field walk: chunks of a single search with n >= kUPk + kTriMinM free
+// spins walk three blocks of kUPk at once, as the fields of one 32-bit word
+// (bits 0-10, 11-21 and 22-31).  A lane's 2^m blocks (m = n - kUPk) are taken
+// in levels: level l holds the triples (b + T, b + Q + T, b + 2Q + T), T < Q,
+// with Q = 2^(m - 2 - 2l) >= 2 and b = 2^m - 4Q; the 2 or 4 blocks left
+// after the last level are walked exactly.  The record of b + T holds the
+// triple's packed record steps.  Every field keeps a margin of kTriRoom
+// units on both sides of its test bit (the 10-bit field sets the limit).
+constexpr int kTriMinM = 4;
+constexpr int kTriShiftB = 11;
+constexpr int kTriShiftC = 22;
+constexpr int kTriRoom = 512;  // half the range of the 10-bit field
+constexpr uint32_t kTriBias = 1024u + (1024u << kTriShiftB) + (512u << kTriShiftC);
+constexpr uint32_t kTriLane = 1u + (1u << kTriShiftB) + (1u << kTriShiftC);
+// blocks of a lane with 2^m blocks that the levels cover (the rest, 2 or 4,
+// is the exact tail)
+__host__ __device__ constexpr uint32_t tri_covered(int m) {
+  return (1u << m) - ((m & 1) ? 2u : 4u);
+}
 
 // Paired walk: the record of block T < half of a table (n >= U + 2 free
 // spins, U = kUWide or kUPk) holds, from word pk_word(U), the packed record
@@ -174,6 +199,7 @@ struct Batch {
   uint64_t* tmask;     // [B][S]
   uint32_t* sticky;    // error bits accumulated over searches
   int allow_f32_walk;  // integer instances may take the fp32 walk (searches: 1)
+  int tri;             // single searches: tables of n >= kUPk + kTriMinM hold triples
   float margin_scale;  // factor on the fp32 pruning margin (1; test hook only)
 };
 

@@ -279,6 +279,43 @@ __global__ void k_prep(Batch bt) {
     P->pk_slack = kUWide + 1;
     P->pk_scale10 = pk10 ? pk_scale_of(kUPk) : 0.0f;
     P->pk_slack10 = kUPk + 1;
+    // Three-field walk: a field's value is u = (G - fastThr) sc - (U + 1)
+    // relative to its test bit, plus rounding, and a block moves it by at
+    // most Rb = sum_f |x_f| units, x_f = rint(WL_f sc) + rint(Wrec_f sc) the
+    // packed step of low spin f.  The walk clamps every start to
+    // [Rb - kTriRoom, kTriRoom - 1 - Rb] (re-walking the block when it lay
+    // below), so no field leaves its range while Rb <= (kTriRoom - 1) / 2.
+    // Rb = (lane part: sum_f |rint(WL_f sc)|, summed by the walk) + pk_rb3,
+    // with pk_rb3 >= sc Rrec + U / 2 and Rrec = sum_{f<U} 2 (|h_f| +
+    // sum_{U <= g < min(N, kMaxFree)} |J_fg|) >= sum_f |Wrec_f| for every
+    // block.  sc: the largest power of two for which Rrec plus 1.5 times the
+    // RMS size of the lane part (prefix spins from kUPk + kTriMinM up) stays
+    // inside that room -- lanes whose lane part exceeds it re-walk every
+    // block -- and at most 2^7 times the paired scale (so that every value
+    // of the start computation is exact in fp32).
+    float sc3 = 0.0f;
+    int rb3 = 0;
+    if (pk10 && P->pk_scale10 > 0.0f) {
+      double rrec = 0.0, lrms = 0.0;
+      for (int f = 0; f < kUPk && f < Nc; ++f) {
+        double a = fabs((double)hb[f]), q = 0.0;
+        for (int g = kUPk; g < Nc; ++g) {
+          const double j = (double)(f < g ? Jb[f * ld + g] : Jb[g * ld + f]);
+          if (g < kMaxFree) a += fabs(j);
+          if (g >= kUPk + kTriMinM) q += j * j;
+        }
+        rrec += 2.0 * a;
+        lrms += 2.0 * sqrt(q);
+      }
+      const double room = 0.5 * (kTriRoom - 1) - 0.5 * kUPk - 2.0;
+      const double need = (rrec + 1.5 * lrms) * (1.0 + 1.0 / 1024.0);
+      double s3 = 128.0 * (double)P->pk_scale10;
+      while (s3 * need > room && s3 > 1e-30) s3 *= 0.5;
+      sc3 = (float)s3;
+      rb3 = (int)ceil(s3 * rrec * (1.0 + 1.0 / 1024.0) + 0.5 * kUPk) + 1;
+    }
+    P->pk_scale3 = sc3;
+    P->pk_rb3 = rb3;
     P->thr_key = 0xFFFFFFFFu;
     P->rec_count = 0;
     P->thr_mask = ~0ull;
@@ -401,9 +438,32 @@ __global__ void k_tables(Batch bt, int ncap, void* out, int paired) {
     rec[0] = __float_as_uint((float)cB);
     rec[1] = __float_as_uint((float)R);
     for (int f = 0; f < U; ++f) rec[2 + f] = __float_as_uint((float)wu[f]);
+    // packed steps of the three-field walk: the record of block T of the
+    // first stream of a level (T - b < Q) holds those of the triple
+    // (T, T + Q, T + 2Q), all three of the parity of T
+    const float s3 = U == kUPk ? bt.P[b].pk_scale3 : 0.0f;
+    const bool tri = paired && U == kUPk && bt.tri && n >= U + kTriMinM && s3 > 0.0f;
+    if (tri) {
+      uint32_t base = 0, Q = 1u << (n - U - 2);
+      while (Q >= 2u && T >= base + 3u * Q) {
+        base += 3u * Q;
+        Q >>= 2;
+      }
+      if (Q >= 2u && T < base + Q) {
+        double wb[U], wc[U];
+        wu_of(gray32((T + Q) << U), wb);
+        wu_of(gray32((T + 2u * Q) << U), wc);
+        for (int f = 0; f < U; ++f) {
+          const uint32_t xa = (uint32_t)(int32_t)rintf((float)wu[f] * s3);
+          const uint32_t xb = (uint32_t)(int32_t)rintf((float)wb[f] * s3);
+          const uint32_t xc = (uint32_t)(int32_t)rintf((float)wc[f] * s3);
+          rec[pk_word(U) + f] = xa + (xb << kTriShiftB) + (xc << kTriShiftC);
+        }
+      }
+    }
     // packed steps of the paired walk: blocks T and T ^ half (same parity)
     const float sc = U == kUPk ? bt.P[b].pk_scale10 : bt.P[b].pk_scale;
-    if (paired && (U == kUWide || U == kUPk) && n >= U + 2 && sc > 0.0f) {
+    if (!tri && paired && (U == kUWide || U == kUPk) && n >= U + 2 && sc > 0.0f) {
       const uint32_t half = 1u << (n - U - 1);
       const uint32_t T2 = T ^ half;
       double wp[U];
@@ -452,7 +512,7 @@ struct Num<int32_t> {
   static __device__ inline int32_t big() { return 1 << 29; }
 };
 
-template <bool kInt, bool kWF, int U, bool kSplit, bool kPk>
+template <bool kInt, bool kWF, int U, bool kSplit, bool kPk, bool kTri = false>
 __device__ __forceinline__ void enum_walk(const Batch& bt, const void* __restrict__ Jv,
                                           const void* __restrict__ hv,
                                           const uint32_t* __restrict__ table,
@@ -466,8 +526,9 @@ __device__ __forceinline__ void enum_walk(const Batch& bt, const void* __restric
 // Resident waves: 8 per SIMD (64 VGPRs); the walk over blocks of kUPk
 // carries ten packed steps and three group steps and takes 7 (72 VGPRs,
 // 4825 ms per N = 48 search against 4929 ms at 8 waves, where it spills its
-// per-block values).
-template <bool kInt, int U, bool kSplit, bool kPk>
+// per-block values).  kTri: the three-field walk (blocks of kUPk, single
+// searches, n >= kUPk + kTriMinM).
+template <bool kInt, int U, bool kSplit, bool kPk, bool kTri = false>
 __global__ __launch_bounds__(kEnumBlock, U == kUPk ? 7 : 8) void k_enum(Batch bt, const void* __restrict__ Jv,
                                                         const void* __restrict__ hv,
                                                         const uint32_t* __restrict__ table,
@@ -499,8 +560,8 @@ __global__ __launch_bounds__(kEnumBlock, U == kUPk ? 7 : 8) void k_enum(Batch bt
     // blocks of 10: fp32 walks; an integer instance that takes the int32
     // walk walks the chunk's blocks of 8 instead
     if (!kInt || P->walk_f32) {
-      enum_walk<kInt, true, kUPk, kSplit, true>(bt, Jv, hv, table, qtab_all, ch, b, blk, N, n,
-                                                lanes, P, s_y, s_F, s_R, s_EH);
+      enum_walk<kInt, true, kUPk, kSplit, true, kTri>(bt, Jv, hv, table, qtab_all, ch, b, blk,
+                                                      N, n, lanes, P, s_y, s_F, s_R, s_EH);
     } else if constexpr (kInt) {
       Chunk c8 = ch;
       c8.table_offset = ch.table_offset8;
@@ -520,7 +581,7 @@ __global__ __launch_bounds__(kEnumBlock, U == kUPk ? 7 : 8) void k_enum(Batch bt
 // The walk of k_enum.  kInt: the instance is int32 (exact set-up in int64,
 // integer keys); kWF: the walk runs in fp32 (fp32 instances, and integer ones
 // whose values fit 24 bits, whose tables then hold fp32 values).
-template <bool kInt, bool kWF, int U, bool kSplit, bool kPk>
+template <bool kInt, bool kWF, int U, bool kSplit, bool kPk, bool kTri>
 __device__ __forceinline__ void enum_walk(const Batch& bt, const void* __restrict__ Jv,
                                           const void* __restrict__ hv,
                                           const uint32_t* __restrict__ table,
@@ -879,7 +940,181 @@ __device__ __forceinline__ void enum_walk(const Batch& bt, const void* __restric
     return a;
   };
 
-  if constexpr (kPk) {
+  if constexpr (kPk && kTri) {
+    static_assert(kWF && U == kUPk && !kSplit, "three-field walk: fp32, blocks of kUPk, searches");
+    // ---- three-field walk -----------------------------------------------------
+    // (chunks of a single search with n >= kUPk + kTriMinM.)  The blocks of a
+    // triple (TA, TA + Q, TA + 2Q, all of the parity of TA) are walked as the
+    // fields of one word: field k holds its bias plus u_k, u = (G - fastThr)
+    // sc - (U + 1) plus at most U + 1 units of rounding, so its top bit
+    // (bit 10, 21 or 31) is clear iff u < 0, which every state at or below
+    // fastThr satisfies.  Steps, AND and the bound test are those of the
+    // paired walk, on three blocks instead of two.  Each start u is clamped
+    // to [Rb - kTriRoom, kTriRoom - 1 - Rb] (Rb: the lane's bound on a
+    // block's summed step magnitudes), so that no field leaves its range; a
+    // clamp from above hides no state below the bound (the block's states
+    // all stay above the test bit), a clamp from below re-walks the block.
+    const float sc = P->pk_scale3;
+    const bool armed = full && sc > 0.0f;  // else every block is re-walked
+    const float ftsc = armed ? fastThr * sc : 0.0f;  // exact: sc is a power of two
+    // packed steps, carried from triple to triple as in the paired walk
+    // (the triples of a lane alternate in parity, also across levels)
+    uint32_t pk[U], rprev[U];
+    int rbl = P->pk_rb3;
+#pragma unroll
+    for (int f = 0; f < U; ++f) {
+      const int32_t xl = (int32_t)rintf((float)WL[f] * sc);
+      pk[f] = (uint32_t)xl * kTriLane;
+      rbl += xl < 0 ? -xl : xl;
+      rprev[f] = 0u;
+    }
+    const bool lane_ok = 2 * rbl <= kTriRoom - 1;  // else the lane re-walks every block
+    const float ulo = (float)(rbl - kTriRoom), uhi = (float)(kTriRoom - 1 - rbl);
+    constexpr uint32_t kAll = (1u << (kSteps / 64)) - 1u;
+    const int m = n - U;
+    V GA = G, GB = G, GC = G;
+    uint32_t base = 0;
+#pragma nounroll
+    for (uint32_t Q = 1u << (m - 2); Q >= 2u; Q >>= 2) {
+      V ynext = s_y[tid];  // triple 1 flips high spin U in all three blocks
+      for (uint32_t T = 0; T < Q; ++T) {
+        const uint32_t TA = base + T, TB = TA + Q, TC = TB + Q;
+        const uint32_t* recA = tab + (size_t)TA * kRW;
+        const uint32_t* recB = tab + (size_t)TB * kRW;
+        const uint32_t* recC = tab + (size_t)TC * kRW;
+        auto rw = [&](const uint32_t* rec, int k) -> V { return (V)__uint_as_float(rec[k]); };
+        uint32_t rpk[U];
+#pragma unroll
+        for (int f = 0; f < U; ++f) rpk[f] = recA[pk_word(U) + f];
+        const V ycur = ynext;
+        if (T + 1 < Q) ynext = s_y[__builtin_ctz(T + 1) * kEnumBlock + tid];
+        const bool odd = T & 1u;
+        if (T == 0) {
+          // a level's blocks start from fresh values (block 0 from the lane's G)
+          if (base != 0) GA = valid ? (V)fresh_g(TA, rw(recA, 1)) : G;
+          GB = valid ? (V)fresh_g(TB, rw(recB, 1)) : G;
+          GC = valid ? (V)fresh_g(TC, rw(recC, 1)) : G;
+        } else {
+          // boundary step of the three blocks: high spin U + c (base and Q
+          // are multiples of 2^(c+1)), old value +1 iff bit c+1 of the
+          // block's index is set
+          const int c = __builtin_ctz(T);
+          GA = ((TA >> (c + 1)) & 1u) ? GA + ycur : GA - ycur;
+          GB = ((TB >> (c + 1)) & 1u) ? GB + ycur : GB - ycur;
+          GC = ((TC >> (c + 1)) & 1u) ? GC + ycur : GC - ycur;
+          GA = GA + rw(recA, 0);
+          GB = GB + rw(recB, 0);
+          GC = GC + rw(recC, 0);
+          constexpr uint32_t kPkReBlocks = 1u << (kPkReanchorLog2 - U);
+          if (!kInt && (T & (kPkReBlocks - 1)) == 0) {
+            const float fa = valid ? fresh_g(TA, rw(recA, 1)) : (float)GA;
+            const float fb = valid ? fresh_g(TB, rw(recB, 1)) : (float)GB;
+            const float fc = valid ? fresh_g(TC, rw(recC, 1)) : (float)GC;
+            drift = fmaxf(drift, fmaxf(fabsf((float)GA - fa),
+                                       fmaxf(fabsf((float)GB - fb), fabsf((float)GC - fc))));
+            GA = (V)fa;
+            GB = (V)fb;
+            GC = (V)fc;
+          }
+        }
+        // clamped fixed-point starts (lanes past the chunk's end: any value
+        // in range will do)
+        auto ustart = [&](V Gx) -> float {
+          return valid ? rintf(fmaf((float)Gx, sc, -ftsc)) - (float)(U + 1) : uhi;
+        };
+        const float xa = ustart(GA), xb = ustart(GB), xc = ustart(GC);
+        const bool lowa = xa < ulo, lowb = xb < ulo, lowc = xc < ulo;
+        auto field = [&](float x) -> uint32_t {
+          return (uint32_t)(int32_t)fminf(fmaxf(x, ulo), uhi);
+        };
+        uint32_t g = field(xa) + (field(xb) << kTriShiftB) + (field(xc) << kTriShiftC) + kTriBias;
+#pragma unroll
+        for (int f = 0; f < U - 1; ++f) pk[f] = pk[f] + (rpk[f] - rprev[f]);
+        // the lane's first triple is even: its top-spin lane part is minus
+        // the lane's value
+        pk[U - 1] = (base == 0 && T == 0) ? rpk[U - 1] - pk[U - 1]
+                                          : (rpk[U - 1] + rprev[U - 1]) - pk[U - 1];
+#pragma unroll
+        for (int f = 0; f < U; ++f) rprev[f] = rpk[f];
+        // sixteen 63-step passes in four groups of four, as in the paired walk
+        uint32_t acc = 0xFFFFFFFFu;
+        auto sub = [&](const uint32_t p5) {
+          uint32_t accw = g;  // the pass's first state
+#pragma unroll
+          for (int j = 1; j < 64; ++j) {
+            const int f = __builtin_ctz(j);
+            if (f == 5) g = g + p5;
+            else g = ((j >> (f + 1)) & 1) ? g + pk[f] : g - pk[f];
+            asm volatile("v_and_b32 %0, %0, %1" : "+v"(accw) : "v"(g));
+          }
+          acc &= accw;
+        };
+        uint32_t p5 = 0u - pk[5];
+        uint32_t s7 = 0u - pk[7];
+        uint32_t t0 = 0u - pk[8] - pk[6], t1 = pk[U - 1] - pk[6], t2 = pk[8] - pk[6];
+#pragma nounroll
+        for (int o = 0; o < kSteps / 256; ++o) {
+          uint32_t s0 = 0u - pk[6], s1 = s7, s2 = pk[6];
+#pragma nounroll
+          for (int w = 0; w < 4; ++w) {
+            sub(p5);
+            g = g + s0;
+            s0 = s1;
+            s1 = s2;
+            p5 = 0u - p5;
+          }
+          g = g + t0;  // after the last group g is not used
+          t0 = t1;
+          t1 = t2;
+          s7 = 0u - s7;
+        }
+        uint32_t ma = ((acc >> 10) & 1u) == 0u || lowa ? kAll : 0u;
+        uint32_t mb = ((acc >> 21) & 1u) == 0u || lowb ? kAll : 0u;
+        uint32_t mc = ((acc >> 31) & 1u) == 0u || lowc ? kAll : 0u;
+        if (!armed || !lane_ok) ma = mb = mc = kAll;
+        if (!valid) ma = mb = mc = 0u;
+        const V wl = odd ? WL[U - 1] : -WL[U - 1];
+        auto steps = [&](const uint32_t* rec, V (&W)[U]) {
+#pragma unroll
+          for (int f = 0; f < U - 1; ++f) W[f] = WL[f] + rw(rec, 2 + f);
+          W[U - 1] = wl + rw(rec, 2 + U - 1);
+        };
+        if (__ballot(ma != 0u) != 0ull) {
+          V W[U];
+          steps(recA, W);
+          rewalk_long(TA, W, GA, ma);
+        }
+        if (__ballot(mb != 0u) != 0ull) {
+          V W[U];
+          steps(recB, W);
+          rewalk_long(TB, W, GB, mb);
+        }
+        if (__ballot(mc != 0u) != 0ull) {
+          V W[U];
+          steps(recC, W);
+          rewalk_long(TC, W, GC, mc);
+        }
+        // the blocks end with spin U-1 up and every other low spin back down
+        GA = GA + (wl + rw(recA, 2 + U - 1));
+        GB = GB + (wl + rw(recB, 2 + U - 1));
+        GC = GC + (wl + rw(recC, 2 + U - 1));
+      }
+      base += 3u * Q;
+    }
+    // the 2 or 4 blocks after the last level: walked exactly, from fresh values
+    for (uint32_t T = base; T < nblocks; ++T) {
+      const uint32_t* rec = tab + (size_t)T * kRW;
+      V W[U];
+#pragma unroll
+      for (int f = 0; f < U - 1; ++f) W[f] = WL[f] + (V)__uint_as_float(rec[2 + f]);
+      W[U - 1] = ((T & 1u) ? WL[U - 1] : -WL[U - 1]) + (V)__uint_as_float(rec[2 + U - 1]);
+      const V G0 = valid ? (V)fresh_g(T, (V)__uint_as_float(rec[1])) : G;
+      if (__ballot(valid) != 0ull) {
+        rewalk_long(T, W, G0, valid ? kAll : 0u);
+        --slow;  // not a block that the bound test sent back
+      }
+    }
+  } else if constexpr (kPk) {
     static_assert(!kPk || (kWF && (U == kUWide || U == kUPk) && (!kSplit || kSub == 64)),
                   "paired walk: fp32 walks, blocks of 8 or 10, sub-blocks of 64");
     // ---- paired walk ----------------------------------------------------------
@@ -1625,6 +1860,12 @@ bool enum_paired(int U, int n) {
   return (U == kUWide && n >= kUWide + 2) || (U == kUPk && n >= kUPk + 2);
 }
 
+// Chunks of a single search with blocks of kUPk and n >= kUPk + kTriMinM
+// take the three-field walk (their tables hold packed triples).
+bool enum_tri(bool split, const Batch& bt, int n) {
+  return !split && bt.tri && n >= kUPk + kTriMinM;
+}
+
 // split: test the bound per 64-step sub-block (batched searches)
 hipError_t launch_enum(bool isint, int U, bool split, const Batch& bt, const Chunk& ch, int ninst,
                        hipStream_t st) {
@@ -1632,13 +1873,17 @@ hipError_t launch_enum(bool isint, int U, bool split, const Batch& bt, const Chu
   if (U == kUPk && !enum_paired(U, ch.n)) return hipErrorInvalidValue;
   const int bpi = (int)((ch.lanes + kEnumBlock - 1) / kEnumBlock);
   const dim3 grid((unsigned)((int64_t)bpi * ninst));
-#define SG_ENUM(I, UV, SP, PK)                                                                 \
-  hipLaunchKernelGGL((k_enum<I, UV, SP, PK>), grid, dim3(kEnumBlock), 0, st, bt, bt.J, bt.h,  \
+#define SG_ENUM_T(I, UV, SP, PK, TR)                                                           \
+  hipLaunchKernelGGL((k_enum<I, UV, SP, PK, TR>), grid, dim3(kEnumBlock), 0, st, bt, bt.J, bt.h, \
                      (const uint32_t*)bt.table, (const uint32_t*)bt.qtab, ch, bpi)
+#define SG_ENUM(I, UV, SP, PK) SG_ENUM_T(I, UV, SP, PK, false)
 #define SG_ENUM_U(I, SP)                 \
   if (U == kU) SG_ENUM(I, kU, SP, false); \
   else SG_ENUM(I, kUWide, SP, false)
-  if (U == kUPk) {
+  if (U == kUPk && enum_tri(split, bt, ch.n)) {
+    if (isint) SG_ENUM_T(true, kUPk, false, true, true);
+    else SG_ENUM_T(false, kUPk, false, true, true);
+  } else if (U == kUPk) {
     if (isint) {
       if (split) SG_ENUM(true, kUPk, true, true);
       else SG_ENUM(true, kUPk, false, true);
@@ -1663,6 +1908,7 @@ hipError_t launch_enum(bool isint, int U, bool split, const Batch& bt, const Chu
   }
 #undef SG_ENUM_U
 #undef SG_ENUM
+#undef SG_ENUM_T
   return hipGetLastError();
 }
 
@@ -1723,6 +1969,7 @@ int enum_occupancy_t() {
   take((const void*)k_enum<I, kUWide, true, false>);
   take((const void*)k_enum<I, kUWide, false, true>);
   take((const void*)k_enum<I, kUWide, true, true>);
+  take((const void*)k_enum<I, kUPk, false, true, true>);
   take((const void*)k_enum<I, kUPk, false, true>);
   take((const void*)k_enum<I, kUPk, true, true>);
   return best;

@@ -126,6 +126,35 @@ def test_paired_walk_small_geometries(orc, torch_dev, N, S, lanes, nmax, isint):
                   "paired N=%d lanes %d" % (N, lanes))
 
 
+@pytest.mark.parametrize("N,S,lanes,nmax", [(20, 100, 32, 14), (20, 5000, 8, 16),
+                                            (22, 2000, 32, 16), (21, 100, 8, 17),
+                                            (22, 300, 8, 18), (22, 100, 4, 19)])
+@pytest.mark.parametrize("isint", [False, True])
+def test_three_field_walk(orc, torch_dev, N, S, lanes, nmax, isint):
+    """The three-field walk (chunks with n >= 14 free spins walk three blocks
+    of 10 per word): one level of triples and a tail of four blocks (n = 14),
+    two levels and a tail of two (n = 15, 17), two and three levels with
+    tails of four (n = 16, 18), four levels and a tail of two (n = 19), with
+    and without a threshold yet (S = 5000 keeps the record open into the
+    first chunks of n >= 14)."""
+    from paper_1904_03621_amd import _lib
+    plan = _lib.sg_debug_plan(N, S, 0, 1 << N, lanes)
+    assert max(n for _, n, _ in plan) == nmax, plan
+    if isint:
+        J, h = I.random_int_dense(N, 700 + N + lanes)
+    else:
+        J, h = I.random_f32_dense(N, 700 + N + lanes)
+    with plan_fill(lanes):
+        m, e, info = search(torch_dev, J, h, S)
+    assert info["free_bits_max"] == nmax, info
+    om, oe = orc.low_spectrum(J, h, S)
+    if isint:
+        check_int(m, e, om, oe, "three-field N=%d lanes %d" % (N, lanes))
+    else:
+        check_f32(N, J, m, e, om, oe, lambda x: orc.energy(J, h, x),
+                  "three-field N=%d lanes %d" % (N, lanes))
+
+
 @pytest.mark.parametrize("N,S,seed", [(22, 100, 1), (24, 100, 2), (24, 1000, 3)])
 def test_search_int32_walk_full(orc, torch_dev, N, S, seed):
     """Integer couplings of up to 2^20: the walk runs in int32 (its values
