@@ -31,36 +31,38 @@ SEED = 2
 # instructions issue at half that rate.
 PEAK_LANE_OPS = 256 * 128 * 2.4e9
 # Algorithmic work per configuration of the walk that runs the search (the
-# paired walk): one accumulate and one order test per state, on 16-bit
-# fixed-point fields two to a 32-bit lane -- one integer add and one AND per
-# Gray step and pair of states, i.e. one doubled-rate lane-instruction per
-# configuration.
-OPS_PER_STATE = 1.0
+# three-field walk, on all chunks with 14 or more free spins per lane: more
+# than 99.9% of the states): one accumulate and one order test per state, on
+# fixed-point fields three to a 32-bit lane -- one integer add and one AND
+# per Gray step and triple of states, i.e. 2/3 doubled-rate
+# lane-instruction per configuration.
+OPS_PER_STATE = 2.0 / 3.0
 # The survey's algorithmic figure: two lane-ops per configuration at the base
 # (non-doubled) issue rate, 3.93e13 / 2 configurations/s.
 SURVEY_STATES_PER_S = 256 * 64 * 2.4e9 / 2.0
 # size of the plain device copy that calibrates the HBM byte counters
 COPY_BYTES = 512 << 20
-# HBM bytes per paired-walk k_enum launch from rocprofv3 FETCH_SIZE / WRITE_SIZE
-# passes (KiB per dispatch, averaged over the 486 dispatches of the walk over
-# blocks of 10 in one search), scaled by what the same counters read for the
-# 512 MiB copy (fetch x2.0, write x1.0); valid for the k_enum source with this
-# SHA-256 prefix only
-TRAFFIC = {"kenum_sha256_16": "ab33227a98339046", "fetch_kib": 880124.75 / 486,
-           "write_kib": 2862972.7 / 486, "fetch_factor": 524288.0 / 262172.0, "write_factor": 1.0,
-           "profile": "profiles/k_enum_f32_dense48_counters.md"}
+# HBM bytes per k_enum launch of the three-field walk from rocprofv3
+# FETCH_SIZE / WRITE_SIZE passes (KiB per dispatch, averaged over its 90
+# dispatches in one search, the repeat launches that exit at once included),
+# scaled by what the same counters read for the 512 MiB copy (fetch x2.0,
+# write x1.0); valid for the k_enum source with this SHA-256 prefix only
+TRAFFIC = {"kenum_sha256_16": "26e7118c1de5eacb", "fetch_kib": 1.46479e6 / 90,
+           "write_kib": 6.62777e6 / 90, "fetch_factor": 524288.0 / 262160.5625,
+           "write_factor": 1.0, "profile": "profiles/k_enum_f32_dense48_counters.md"}
 
-# VALU counters of the search's paired-walk launches (rocprofv3 --pmc, one
-# search of this instance, 486 dispatches, 4.879 s of kernel time), valid for
-# the k_enum source with this hash only: SQ_INSTS_VALU (wave instructions) x 64
-# / 2^48 per configuration; the fraction of the doubled-rate issue capacity
-# used, SQ_INSTS_VALU / (1024 SIMDs x cycles x 1/2); the share issued in pairs,
-# 2 SQ_ACTIVE_INST_VALU2 / SQ_INSTS_VALU; and sclk = GRBM_GUI_ACTIVE / 8 XCDs /
-# kernel time.
-COUNTERS = {"kenum_sha256_16": "ab33227a98339046", "valu_insts_per_state": 4.73712e12 * 64 / 2 ** 48,
-            "valu_active": 4.73712e12 / (1024 * 8.67720e10 / 8 * 0.5),
-            "valu_paired": 2 * 2.12849e12 / 4.73712e12,
-            "sclk_ghz": 8.67720e10 / 8 / 4.879 / 1e9,
+# VALU counters of the search's three-field walk launches (rocprofv3 --pmc,
+# one search of this instance, 90 dispatches, 3.0168 s of kernel time), valid
+# for the k_enum source with this hash only: SQ_INSTS_VALU (wave
+# instructions) x 64 / 2^48 per configuration; the fraction of the
+# doubled-rate issue capacity used, SQ_INSTS_VALU / (1024 SIMDs x cycles x
+# 1/2); the share issued in pairs, 2 SQ_ACTIVE_INST_VALU2 / SQ_INSTS_VALU; and
+# sclk = GRBM_GUI_ACTIVE / 8 XCDs / kernel time.
+COUNTERS = {"kenum_sha256_16": "26e7118c1de5eacb",
+            "valu_insts_per_state": 3.25784e12 * 64 / 2 ** 48,
+            "valu_active": 3.25784e12 / (1024 * 5.63965e10 / 8 * 0.5),
+            "valu_paired": 2 * 1.56508e12 / 3.25784e12,
+            "sclk_ghz": 5.63965e10 / 8 / 3.0168 / 1e9,
             "profile": "profiles/k_enum_f32_dense48_counters.md"}
 
 
@@ -496,7 +498,7 @@ def main() -> int:
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
                 "unit": "Tlane-op/s", "frac": achieved / PEAK_LANE_OPS,
                 "traffic": traffic_per_launch(), "traffic_unit": "HBM bytes per launch",
-                "kernel": "k_enum<float> (paired walk)", "avg_launch_ms": avg_ms,
+                "kernel": "k_enum<float> (three-field walk)", "avg_launch_ms": avg_ms,
                 "launches_per_step": enum_launches / max(args.steps, 1),
                 "ops_per_state": OPS_PER_STATE,
                 "measured_mix_peak": mix_peak / 1e12 if mix_peak > 0 else None,

@@ -198,6 +198,7 @@ struct Workspace {
   size_t nlz_coef = 0;
   int64_t fill[2] = {0, 0};      // resident lanes of the walk (fp32, int32)
   int64_t fill_dev[2] = {0, 0};  // the device's values (fill differs only under a test hook)
+  int64_t launch[2] = {0, 0};    // lanes per launch of a single search's chunks
   float margin_scale = 1.0f;     // test hook: factor on the fp32 pruning margin
   int cus = 0;
   // last run
@@ -228,6 +229,13 @@ hipError_t ws_event_pair(Workspace* w, hipEvent_t* a, hipEvent_t* b) {
 std::mutex g_mu;
 std::map<std::pair<int, hipStream_t>, Workspace*> g_ws;
 
+// A single search's chunks launch this many times the device's resident
+// lanes once they are that large: the walk's lanes take unequal times (a lane
+// whose blocks fail the bound test re-walks them), and with several
+// workgroups per slot the device refills a CU as soon as one finishes instead
+// of waiting for the slowest lane of a launch (N = 48 dense search: 3.03 s at
+// 8 times the resident lanes, 3.86 s at once).
+constexpr int64_t kSearchLaunchFills = 8;
 constexpr uint32_t kCandCapMin = 1u << 22;     // single search
 constexpr uint32_t kBatchCandCapMin = 1u << 13;  // per instance of a batch
 constexpr uint64_t kBatchCandBudget = 1ull << 24;  // slots over the whole batch
@@ -279,6 +287,7 @@ sg_status ws_describe(int dev, Workspace* w) {
   for (int k = 0; k < 2; ++k) {
     const int occ = enum_occupancy(k == 1);
     w->fill[k] = w->fill_dev[k] = (int64_t)w->cus * std::max(occ, 1) * kEnumBlock;
+    w->launch[k] = kSearchLaunchFills * w->fill[k];
   }
   return SG_OK;
 }
@@ -434,7 +443,7 @@ sg_status search_on(Workspace* w, bool isint, int N, const void* J, const void* 
   w->last_launches = 0;
   if (N >= U) HIP_TRY(launch_tables(isint, U, bt, ncap, true, st));
   if (use10) HIP_TRY(launch_tables(isint, kUPk, bt, ncap, true, st));
-  const std::vector<PlanChunk> plan = plan_chunks(N, S, lo, hi, w->fill[isint ? 1 : 0], U);
+  const std::vector<PlanChunk> plan = plan_chunks(N, S, lo, hi, w->launch[isint ? 1 : 0], U);
   double states = 0.0;
   for (const PlanChunk& pc : plan) {
     if (pc.n == 0) {
@@ -1143,7 +1152,10 @@ sg_status sg_debug_set_fill(void* stream, long long lanes) {
   const sg_status v = ws_get((hipStream_t)stream, 1, 1, 1, 1, &w);
   if (v != SG_OK) return v;
   std::lock_guard<std::mutex> lk(g_mu);
-  for (int k = 0; k < 2; ++k) w->fill[k] = lanes > 0 ? (int64_t)lanes : w->fill_dev[k];
+  for (int k = 0; k < 2; ++k) {
+    w->fill[k] = lanes > 0 ? (int64_t)lanes : w->fill_dev[k];
+    w->launch[k] = lanes > 0 ? (int64_t)lanes : kSearchLaunchFills * w->fill_dev[k];
+  }
   return SG_OK;
 }
 
