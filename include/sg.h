@@ -376,9 +376,9 @@ double sg_probe_valu(int op, int waves_per_simd);
  *
  * sg_debug_set_fill: the number of lanes the work plans of (current device,
  * stream) assume (lanes >= 1; 0 restores the device's own values): the
- * resident lanes of the density of states and log Z, and the lanes per
- * launch of a single search's chunks (by default 8 times the resident
- * lanes).  The single search, the density of states and log Z give each lane
+ * resident lanes, and the most lanes a single search's chunk launches (by
+ * default 8 times the resident lanes, for chunks of 22 free spins per
+ * lane).  The single search, the density of states and log Z give each lane
  * more free spins when there are fewer lanes to fill: with lanes = 4 a search
  * of N = 24 walks up to 2^21 states per lane (block boundaries, high-spin
  * fields, fp32 re-anchors), and a log Z batch of one N = 20 instance runs 14

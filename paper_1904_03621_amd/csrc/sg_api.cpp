@@ -95,19 +95,24 @@ struct PlanChunk {
 // max(S, 4096) states (it runs with no threshold, so every state is a
 // candidate); each next chunk is as large as everything processed before it,
 // so that the expected number of candidates per chunk stays near S, until
-// the chunk reaches `fill` lanes of 2^nmax states; from then on chunks have
-// fill lanes each.  Every chunk is [first, first + L 2^n) with first a
+// the chunk reaches `launch` lanes of 2^nmax states; from then on chunks have
+// launch lanes each.  A chunk's free spins n are chosen for `fill` resident
+// lanes (n grows once a chunk has more than fill lanes' worth of states), so
+// launch >= fill only lets the chunks of n = nmax grow further.  Every chunk
+// is [first, first + L 2^n) with first a
 // multiple of 2^n, and lanes cover consecutive prefixes.  Ends of the range
 // that are not multiples of a block (2^U states) form chunks with n = 0: one
 // thread per state, every state a candidate.
-std::vector<PlanChunk> plan_chunks(int N, int S, uint64_t lo, uint64_t hi, int64_t fill, int U) {
+std::vector<PlanChunk> plan_chunks(int N, int S, uint64_t lo, uint64_t hi, int64_t fill, int U,
+                                   int64_t launch) {
   std::vector<PlanChunk> out;
   const int nmax = std::min(kMaxFree, N);
   if (fill < 1) fill = 1;
+  if (launch < fill) launch = fill;
   const int fill_log = ilog2_floor((uint64_t)fill);
   uint64_t target = 4096;
   while (target < (uint64_t)S) target <<= 1;
-  const uint64_t big = (uint64_t)fill << nmax;
+  const uint64_t big = (uint64_t)launch << nmax;
   const uint64_t blk = (uint64_t)1 << U;
   uint64_t lo_b = (lo + blk - 1) & ~(blk - 1), hi_b = hi & ~(blk - 1);
   if (lo_b >= hi_b) lo_b = hi_b = hi;  // no whole block: one direct chunk
@@ -124,7 +129,7 @@ std::vector<PlanChunk> plan_chunks(int N, int S, uint64_t lo, uint64_t hi, int64
       int n = nmax;
       while (n > U && (rem >> n) < (uint64_t)fill) --n;
       c.n = n;
-      c.lanes = (int64_t)std::min<uint64_t>((uint64_t)fill, rem >> n);
+      c.lanes = (int64_t)std::min<uint64_t>((uint64_t)launch, rem >> n);
     } else {
       uint64_t size = std::min<uint64_t>(target, big);
       if (cur != 0) size = std::min<uint64_t>(size, cur & (~cur + 1));
@@ -229,9 +234,9 @@ hipError_t ws_event_pair(Workspace* w, hipEvent_t* a, hipEvent_t* b) {
 std::mutex g_mu;
 std::map<std::pair<int, hipStream_t>, Workspace*> g_ws;
 
-// A single search's chunks launch this many times the device's resident
-// lanes once they are that large: the walk's lanes take unequal times (a lane
-// whose blocks fail the bound test re-walks them), and with several
+// A single search's chunks of kMaxFree free spins per lane grow to this many
+// times the device's resident lanes: the walk's lanes take unequal times (a
+// lane whose blocks fail the bound test re-walks them), and with several
 // workgroups per slot the device refills a CU as soon as one finishes instead
 // of waiting for the slowest lane of a launch (N = 48 dense search: 3.03 s at
 // 8 times the resident lanes, 3.86 s at once).
@@ -443,7 +448,8 @@ sg_status search_on(Workspace* w, bool isint, int N, const void* J, const void* 
   w->last_launches = 0;
   if (N >= U) HIP_TRY(launch_tables(isint, U, bt, ncap, true, st));
   if (use10) HIP_TRY(launch_tables(isint, kUPk, bt, ncap, true, st));
-  const std::vector<PlanChunk> plan = plan_chunks(N, S, lo, hi, w->launch[isint ? 1 : 0], U);
+  const std::vector<PlanChunk> plan =
+      plan_chunks(N, S, lo, hi, w->fill[isint ? 1 : 0], U, w->launch[isint ? 1 : 0]);
   double states = 0.0;
   for (const PlanChunk& pc : plan) {
     if (pc.n == 0) {
@@ -1187,7 +1193,8 @@ int sg_debug_plan(int N, int S, uint64_t lo, uint64_t hi, int64_t lanes_fill,
   if (N < 1 || N > SG_MAX_N || S < 1 || lo >= hi || hi > ((uint64_t)1 << N) || (lo % 64) != 0 ||
       lanes_fill < 1)
     return -1;
-  const std::vector<PlanChunk> plan = plan_chunks(N, S, lo, hi, lanes_fill, search_block(N));
+  const std::vector<PlanChunk> plan =
+      plan_chunks(N, S, lo, hi, lanes_fill, search_block(N), lanes_fill);
   for (int i = 0; i < (int)plan.size() && i < cap; ++i) {
     if (first_mask) first_mask[i] = plan[i].first_mask;
     if (free_bits) free_bits[i] = plan[i].n;
