@@ -378,11 +378,13 @@ double sg_probe_valu(int op, int waves_per_simd);
  * stream) assume (lanes >= 1; 0 restores the device's own values): the
  * resident lanes, and the most lanes a single search's chunk launches (by
  * default 8 times the resident lanes, for chunks of 22 free spins per
- * lane).  The single search, the density of states and log Z give each lane
- * more free spins when there are fewer lanes to fill: with lanes = 4 a search
- * of N = 24 walks up to 2^21 states per lane (block boundaries, high-spin
- * fields, fp32 re-anchors), and a log Z batch of one N = 20 instance runs 14
- * free spins per lane at lanes = 64.
+ * lane).  While it is set, every chunk of 14 or more free spins takes the
+ * three-field walk (by default only chunks of 20 or more that launch at
+ * least twice the resident lanes).  The single search, the density of
+ * states and log Z give each lane more free spins when there are fewer lanes
+ * to fill: with lanes = 4 a search of N = 24 walks up to 2^21 states per
+ * lane (block boundaries, high-spin fields, fp32 re-anchors), and a log Z
+ * batch of one N = 20 instance runs 14 free spins per lane at lanes = 64.
  *
  * sg_debug_set_margin_scale: multiplies the fp32 pruning margin of later
  * searches on (current device, stream) by scale, 0 < scale <= 1 (1

@@ -204,6 +204,7 @@ struct Workspace {
   int64_t fill[2] = {0, 0};      // resident lanes of the walk (fp32, int32)
   int64_t fill_dev[2] = {0, 0};  // the device's values (fill differs only under a test hook)
   int64_t launch[2] = {0, 0};    // lanes per launch of a single search's chunks
+  bool tri_all = false;          // test hook: every chunk that can takes the three-field walk
   float margin_scale = 1.0f;     // test hook: factor on the fp32 pruning margin
   int cus = 0;
   // last run
@@ -241,6 +242,16 @@ std::map<std::pair<int, hipStream_t>, Workspace*> g_ws;
 // of waiting for the slowest lane of a launch (N = 48 dense search: 3.03 s at
 // 8 times the resident lanes, 3.86 s at once).
 constexpr int64_t kSearchLaunchFills = 8;
+// The three-field walk (blocks of kUPk, three per word) takes the chunks of
+// at least kTriMinFree free spins that launch at least kTriMinFills times the
+// resident lanes; the others keep the paired walk.  Its coarser fixed point
+// sends more blocks to the exact re-walk, which makes its lanes uneven, and
+// its exactly walked tail (2 or 4 blocks per lane) is a larger share at small
+// n: on dense instances it took 46 ms against 36 ms at N = 40 (n <= 21,
+// launches of one resident wave of workgroups) and 2.96 s against 4.10 s at
+// N = 48 (n = 22, launches of 8).
+constexpr int kTriMinFree = 20;
+constexpr int64_t kTriMinFills = 2;
 constexpr uint32_t kCandCapMin = 1u << 22;     // single search
 constexpr uint32_t kBatchCandCapMin = 1u << 13;  // per instance of a batch
 constexpr uint64_t kBatchCandBudget = 1ull << 24;  // slots over the whole batch
@@ -468,6 +479,9 @@ sg_status search_on(Workspace* w, bool isint, int N, const void* J, const void* 
     const int Uc = use10 && pc.n >= kUPk + 2 ? kUPk : U;
     ch.table_offset = (1 << (pc.n - Uc)) - 1;
     ch.table_offset8 = (1 << (pc.n - U)) - 1;
+    ch.tri = Uc == kUPk && pc.n >= kUPk + kTriMinM &&
+             (w->tri_all || (pc.n >= kTriMinFree &&
+                             pc.lanes >= kTriMinFills * w->fill_dev[isint ? 1 : 0]));
     // a chunk with more states than candidate slots may overflow: it gets
     // up to kRetries repeated passes, each run only if the last overflowed
     const uint64_t cstates = (uint64_t)pc.lanes << pc.n;
@@ -1162,6 +1176,7 @@ sg_status sg_debug_set_fill(void* stream, long long lanes) {
     w->fill[k] = lanes > 0 ? (int64_t)lanes : w->fill_dev[k];
     w->launch[k] = lanes > 0 ? (int64_t)lanes : kSearchLaunchFills * w->fill_dev[k];
   }
+  w->tri_all = lanes > 0;
   return SG_OK;
 }
 

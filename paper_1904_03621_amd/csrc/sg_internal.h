@@ -138,12 +138,14 @@ struct Params {
 };
 
 // Three-field walk: chunks of a single search with n >= kUPk + kTriMinM free
-// spins walk three blocks of kUPk at once, as the fields of one 32-bit word
-// (bits 0-10, 11-21 and 22-31).  A lane's 2^m blocks (m = n - kUPk) are taken
+// spins may walk three blocks of kUPk at once, as the fields of one 32-bit
+// word (bits 0-10, 11-21 and 22-31); the host picks it per chunk (Chunk::tri).
+// A lane's 2^m blocks (m = n - kUPk) are taken
 // in levels: level l holds the triples (b + T, b + Q + T, b + 2Q + T), T < Q,
 // with Q = 2^(m - 2 - 2l) >= 2 and b = 2^m - 4Q; the 2 or 4 blocks left
 // after the last level are walked exactly.  The record of b + T holds the
-// triple's packed record steps.  Every field keeps a margin of kTriRoom
+// triple's packed record steps, from word kPkWordTri (the paired walk's stay
+// in words pk_word(kUPk) ..., so either walk can take the chunk).  Every field keeps a margin of kTriRoom
 // units on both sides of its test bit (the 10-bit field sets the limit).
 constexpr int kTriMinM = 4;
 constexpr int kTriShiftB = 11;
@@ -164,6 +166,8 @@ __host__ __device__ constexpr uint32_t tri_covered(int m) {
 // the record of block T + half holds f = 6, 7 in its words pk_word(U) + 0, 1.
 constexpr int pk_word(int U) { return 2 + U; }
 constexpr int pk_in_a(int U) { return U == kUPk ? U : kRecWords - pk_word(U); }
+constexpr int kPkWordTri = pk_word(kUPk) + kUPk;  // the three-field walk's packed steps
+static_assert(kPkWordTri + kUPk <= rec_words(kUPk), "triple steps exceed the record");
 static_assert(pk_word(kUPk) + kUPk <= rec_words(kUPk), "packed steps exceed the record");
 static_assert(pk_word(kUWide) + kUWide <= 2 * kRecWords - pk_word(kUWide), "packed steps split");
 
@@ -233,6 +237,7 @@ struct Chunk {
   int table_offset8;      // the same in the U = kUWide table, for a chunk of
                           // U = kUPk whose instance takes the int32 walk
   int retry;              // 0: first pass; r >= 1: r-th repeat (only if redo)
+  int tri;                // blocks of kUPk: the three-field walk (n >= kUPk + kTriMinM)
 };
 
 // Orderable 32-bit keys of energies.

@@ -440,7 +440,8 @@ __global__ void k_tables(Batch bt, int ncap, void* out, int paired) {
     for (int f = 0; f < U; ++f) rec[2 + f] = __float_as_uint((float)wu[f]);
     // packed steps of the three-field walk: the record of block T of the
     // first stream of a level (T - b < Q) holds those of the triple
-    // (T, T + Q, T + 2Q), all three of the parity of T
+    // (T, T + Q, T + 2Q), all three of the parity of T, after the paired
+    // walk's (both are written: the host picks the walk per chunk)
     const float s3 = U == kUPk ? bt.P[b].pk_scale3 : 0.0f;
     const bool tri = paired && U == kUPk && bt.tri && n >= U + kTriMinM && s3 > 0.0f;
     if (tri) {
@@ -457,13 +458,13 @@ __global__ void k_tables(Batch bt, int ncap, void* out, int paired) {
           const uint32_t xa = (uint32_t)(int32_t)rintf((float)wu[f] * s3);
           const uint32_t xb = (uint32_t)(int32_t)rintf((float)wb[f] * s3);
           const uint32_t xc = (uint32_t)(int32_t)rintf((float)wc[f] * s3);
-          rec[pk_word(U) + f] = xa + (xb << kTriShiftB) + (xc << kTriShiftC);
+          rec[kPkWordTri + f] = xa + (xb << kTriShiftB) + (xc << kTriShiftC);
         }
       }
     }
     // packed steps of the paired walk: blocks T and T ^ half (same parity)
     const float sc = U == kUPk ? bt.P[b].pk_scale10 : bt.P[b].pk_scale;
-    if (!tri && paired && (U == kUWide || U == kUPk) && n >= U + 2 && sc > 0.0f) {
+    if (paired && (U == kUWide || U == kUPk) && n >= U + 2 && sc > 0.0f) {
       const uint32_t half = 1u << (n - U - 1);
       const uint32_t T2 = T ^ half;
       double wp[U];
@@ -985,7 +986,7 @@ __device__ __forceinline__ void enum_walk(const Batch& bt, const void* __restric
         auto rw = [&](const uint32_t* rec, int k) -> V { return (V)__uint_as_float(rec[k]); };
         uint32_t rpk[U];
 #pragma unroll
-        for (int f = 0; f < U; ++f) rpk[f] = recA[pk_word(U) + f];
+        for (int f = 0; f < U; ++f) rpk[f] = recA[kPkWordTri + f];
         const V ycur = ynext;
         if (T + 1 < Q) ynext = s_y[__builtin_ctz(T + 1) * kEnumBlock + tid];
         const bool odd = T & 1u;
@@ -1860,10 +1861,10 @@ bool enum_paired(int U, int n) {
   return (U == kUWide && n >= kUWide + 2) || (U == kUPk && n >= kUPk + 2);
 }
 
-// Chunks of a single search with blocks of kUPk and n >= kUPk + kTriMinM
-// take the three-field walk (their tables hold packed triples).
-bool enum_tri(bool split, const Batch& bt, int n) {
-  return !split && bt.tri && n >= kUPk + kTriMinM;
+// The chunks the host marks (blocks of kUPk, n >= kUPk + kTriMinM, a single
+// search's tables with packed triples) take the three-field walk.
+bool enum_tri(bool split, const Batch& bt, const Chunk& ch) {
+  return !split && bt.tri && ch.tri && ch.n >= kUPk + kTriMinM;
 }
 
 // split: test the bound per 64-step sub-block (batched searches)
@@ -1880,7 +1881,7 @@ hipError_t launch_enum(bool isint, int U, bool split, const Batch& bt, const Chu
 #define SG_ENUM_U(I, SP)                 \
   if (U == kU) SG_ENUM(I, kU, SP, false); \
   else SG_ENUM(I, kUWide, SP, false)
-  if (U == kUPk && enum_tri(split, bt, ch.n)) {
+  if (U == kUPk && enum_tri(split, bt, ch)) {
     if (isint) SG_ENUM_T(true, kUPk, false, true, true);
     else SG_ENUM_T(false, kUPk, false, true, true);
   } else if (U == kUPk) {
