@@ -243,15 +243,13 @@ std::map<std::pair<int, hipStream_t>, Workspace*> g_ws;
 // 8 times the resident lanes, 3.86 s at once).
 constexpr int64_t kSearchLaunchFills = 8;
 // The three-field walk (blocks of kUPk, three per word) takes the chunks of
-// at least kTriMinFree free spins that launch at least kTriMinFills times the
-// resident lanes; the others keep the paired walk.  Its coarser fixed point
-// sends more blocks to the exact re-walk, which makes its lanes uneven, and
-// its exactly walked tail (2 or 4 blocks per lane) is a larger share at small
-// n: on dense instances it took 46 ms against 36 ms at N = 40 (n <= 21,
-// launches of one resident wave of workgroups) and 2.96 s against 4.10 s at
-// N = 48 (n = 22, launches of 8).
+// at least kTriMinFree free spins; the others keep the paired walk.  Its
+// exactly walked tail (2 or 4 blocks per lane) is a large share at small n,
+// and its coarser fixed point sends more blocks to the exact re-walk: with
+// every chunk of n >= 14 on it, dense searches took 46 ms against 36 ms at
+// N = 40 and 348 ms against 331 ms at N = 44; with n >= 20, 36 ms and 304 ms,
+// and 2.96 s against 4.10 s at N = 48 (J ~ N(0, 1)).
 constexpr int kTriMinFree = 20;
-constexpr int64_t kTriMinFills = 2;
 constexpr uint32_t kCandCapMin = 1u << 22;     // single search
 constexpr uint32_t kBatchCandCapMin = 1u << 13;  // per instance of a batch
 constexpr uint64_t kBatchCandBudget = 1ull << 24;  // slots over the whole batch
@@ -479,9 +477,7 @@ sg_status search_on(Workspace* w, bool isint, int N, const void* J, const void* 
     const int Uc = use10 && pc.n >= kUPk + 2 ? kUPk : U;
     ch.table_offset = (1 << (pc.n - Uc)) - 1;
     ch.table_offset8 = (1 << (pc.n - U)) - 1;
-    ch.tri = Uc == kUPk && pc.n >= kUPk + kTriMinM &&
-             (w->tri_all || (pc.n >= kTriMinFree &&
-                             pc.lanes >= kTriMinFills * w->fill_dev[isint ? 1 : 0]));
+    ch.tri = Uc == kUPk && pc.n >= kUPk + kTriMinM && (w->tri_all || pc.n >= kTriMinFree);
     // a chunk with more states than candidate slots may overflow: it gets
     // up to kRetries repeated passes, each run only if the last overflowed
     const uint64_t cstates = (uint64_t)pc.lanes << pc.n;
