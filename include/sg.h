@@ -379,7 +379,8 @@ double sg_probe_valu(int op, int waves_per_simd);
  * resident lanes, and the most lanes a single search's chunk launches (by
  * default 8 times the resident lanes, for chunks of 22 free spins per
  * lane).  While it is set, every chunk of 14 or more free spins takes the
- * three-field walk (by default only chunks of 20 or more).  The single search, the density of
+ * three-field walk (by default only chunks of 20 or more that launch at
+ * least the resident lanes).  The single search, the density of
  * states and log Z give each lane more free spins when there are fewer lanes
  * to fill: with lanes = 4 a search of N = 24 walks up to 2^21 states per
  * lane (block boundaries, high-spin fields, fp32 re-anchors), and a log Z

@@ -243,12 +243,15 @@ std::map<std::pair<int, hipStream_t>, Workspace*> g_ws;
 // 8 times the resident lanes, 3.86 s at once).
 constexpr int64_t kSearchLaunchFills = 8;
 // The three-field walk (blocks of kUPk, three per word) takes the chunks of
-// at least kTriMinFree free spins; the others keep the paired walk.  Its
-// exactly walked tail (2 or 4 blocks per lane) is a large share at small n,
-// and its coarser fixed point sends more blocks to the exact re-walk: with
-// every chunk of n >= 14 on it, dense searches took 46 ms against 36 ms at
-// N = 40 and 348 ms against 331 ms at N = 44; with n >= 20, 36 ms and 304 ms,
-// and 2.96 s against 4.10 s at N = 48 (J ~ N(0, 1)).
+// at least kTriMinFree free spins that launch at least the resident lanes;
+// the others keep the paired walk.  Its exactly walked tail (2 or 4 blocks
+// per lane) is a large share at small n, and its coarser fixed point sends
+// more blocks to the exact re-walk, which makes lanes uneven where a launch
+// cannot balance them: with every chunk of n >= 14 on it, dense searches
+// took 46 ms against 36 ms at N = 40 and 348 ms against 331 ms at N = 44;
+// with n >= 20 and at least the resident lanes 36, 93 and 304 ms at N = 40,
+// 42 and 44 (n >= 20 alone: 38, 109 and 335 ms), and 2.96 s against 4.10 s
+// at N = 48 (J ~ N(0, 1)).
 constexpr int kTriMinFree = 20;
 constexpr uint32_t kCandCapMin = 1u << 22;     // single search
 constexpr uint32_t kBatchCandCapMin = 1u << 13;  // per instance of a batch
@@ -477,7 +480,8 @@ sg_status search_on(Workspace* w, bool isint, int N, const void* J, const void* 
     const int Uc = use10 && pc.n >= kUPk + 2 ? kUPk : U;
     ch.table_offset = (1 << (pc.n - Uc)) - 1;
     ch.table_offset8 = (1 << (pc.n - U)) - 1;
-    ch.tri = Uc == kUPk && pc.n >= kUPk + kTriMinM && (w->tri_all || pc.n >= kTriMinFree);
+    ch.tri = Uc == kUPk && pc.n >= kUPk + kTriMinM &&
+             (w->tri_all || (pc.n >= kTriMinFree && pc.lanes >= w->fill_dev[isint ? 1 : 0]));
     // a chunk with more states than candidate slots may overflow: it gets
     // up to kRetries repeated passes, each run only if the last overflowed
     const uint64_t cstates = (uint64_t)pc.lanes << pc.n;

@@ -1541,6 +1541,46 @@ __device__ inline bool in_record(const uint32_t* rkey, const uint64_t* rmask, ui
   return r < rn && rkey[r] == key && rmask[r] == m;
 }
 
+// k-th smallest (1-based) of keys[0..cnt) for the whole workgroup: four
+// passes of 8-bit digits, most significant first, each a histogram in LDS and
+// a scan of its 256 bins by the first 256 threads.  Needs blockDim.x a
+// multiple of 256.
+__device__ uint32_t radix_select(const uint32_t* keys, uint32_t cnt, uint32_t k, uint32_t* hist,
+                                 uint32_t* state) {
+  const uint32_t t = threadIdx.x;
+  const bool bin = t < 256u;
+  uint32_t prefix = 0u, pmask = 0u, rem = k;
+  for (int shift = 24; shift >= 0; shift -= 8) {
+    if (bin) hist[t] = 0u;
+    __syncthreads();
+    for (uint32_t j = t; j < cnt; j += blockDim.x) {
+      const uint32_t key = keys[j];
+      if ((key & pmask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    // inclusive scan of the 256 bins (Hillis-Steele)
+    uint32_t v = bin ? hist[t] : 0u;
+    for (uint32_t o = 1; o < 256u; o <<= 1) {
+      const uint32_t add = bin && t >= o ? hist[t - o] : 0u;
+      __syncthreads();
+      v += add;
+      if (bin) hist[t] = v;
+      __syncthreads();
+    }
+    const uint32_t before = t == 0 || !bin ? 0u : hist[t - 1];
+    if (bin && before < rem && rem <= v) {
+      state[0] = prefix | (t << shift);
+      state[1] = rem - before;
+    }
+    __syncthreads();
+    prefix = state[0];
+    rem = state[1];
+    pmask |= 255u << shift;
+    __syncthreads();
+  }
+  return prefix;
+}
+
 // The whole workgroup: merge the ns survivors (skey, smask) with the sorted
 // record, keeping the first S, and publish the S-th key as the threshold.
 // Keys are distinct because masks are, so an entry's place is its rank among
@@ -1548,11 +1588,16 @@ __device__ inline bool in_record(const uint32_t* rkey, const uint64_t* rmask, ui
 // survivors are put side by side in LDS and every rank is counted directly;
 // beyond, the survivors are sorted (bitonic, in LDS when they fit, in global
 // memory otherwise) and an element's rank is its index plus the number of
-// smaller elements in the other list.
+// smaller elements in the other list.  With `sel` (hist: 256 words, state:
+// 3), more survivors than LDS holds are first cut to those at or below the
+// S-th smallest survivor key: no other survivor can enter the record, since
+// S survivors precede it.  They are sorted in LDS when they fit (ties at
+// that key can exceed it; then all are sorted in global memory).
 __device__ void merge_body(Params* P, int S, uint32_t cap, bool last_pass, uint32_t ns,
                            uint32_t* skey, uint64_t* smask, uint32_t* rkey, uint64_t* rmask,
                            uint32_t* tkey, uint64_t* tmask, uint32_t* l_key, uint64_t* l_mask,
-                           uint32_t lds_cap) {
+                           uint32_t lds_cap, uint32_t* sel_hist = nullptr,
+                           uint32_t* sel_state = nullptr) {
   const uint32_t rn = P->rec_count;
   __syncthreads();
   if (ns > 0) {
@@ -1575,11 +1620,42 @@ __device__ void merge_body(Params* P, int S, uint32_t cap, bool last_pass, uint3
         if (r < nn) { tkey[r] = kx; tmask[r] = mx; }
       }
     } else {
+      uint32_t nsort = ns;  // survivors that enter the sort
+      bool gathered = false;
+      if (sel_hist && ns > lds_cap && (uint32_t)S < lds_cap) {
+        const uint32_t kS = radix_select(skey, ns, (uint32_t)S, sel_hist, sel_state);
+        if (threadIdx.x == 0) sel_state[2] = 0u;
+        __syncthreads();
+        for (uint32_t c = threadIdx.x; c < ns; c += blockDim.x) {
+          const uint32_t key = skey[c];
+          if (key <= kS) {
+            const uint32_t slot = atomicAdd(&sel_state[2], 1u);
+            if (slot < lds_cap) {
+              l_key[slot] = key;
+              l_mask[slot] = smask[c];
+            }
+          }
+        }
+        __syncthreads();
+        const uint32_t ng = sel_state[2];
+        if (ng <= lds_cap) {
+          gathered = true;
+          nsort = ng;
+        }
+        __syncthreads();
+      }
       uint32_t P2 = 1;
-      while (P2 < ns) P2 <<= 1;
+      while (P2 < nsort) P2 <<= 1;
       uint32_t* ks;
       uint64_t* ms;
-      if (P2 <= lds_cap) {
+      if (gathered) {
+        for (uint32_t t = nsort + threadIdx.x; t < P2; t += blockDim.x) {
+          l_key[t] = 0xFFFFFFFFu;
+          l_mask[t] = ~0ull;
+        }
+        ks = l_key;
+        ms = l_mask;
+      } else if (P2 <= lds_cap) {
         for (uint32_t t = threadIdx.x; t < P2; t += blockDim.x) {
           l_key[t] = t < ns ? skey[t] : 0xFFFFFFFFu;
           l_mask[t] = t < ns ? smask[t] : ~0ull;
@@ -1597,10 +1673,10 @@ __device__ void merge_body(Params* P, int S, uint32_t cap, bool last_pass, uint3
       __syncthreads();
       bitonic_sort(ks, ms, P2);
       for (uint32_t a = threadIdx.x; a < rn; a += blockDim.x) {
-        const uint32_t r = a + rank_in(ks, ms, ns, rkey[a], rmask[a]);
+        const uint32_t r = a + rank_in(ks, ms, nsort, rkey[a], rmask[a]);
         if (r < nn) { tkey[r] = rkey[a]; tmask[r] = rmask[a]; }
       }
-      for (uint32_t c = threadIdx.x; c < ns; c += blockDim.x) {
+      for (uint32_t c = threadIdx.x; c < nsort; c += blockDim.x) {
         const uint32_t r = c + rank_in(rkey, rmask, rn, ks[c], ms[c]);
         if (r < nn) { tkey[r] = ks[c]; tmask[r] = ms[c]; }
       }
@@ -1638,51 +1714,16 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge(Batch bt, int b, int re
                                                         int last_pass) {
   __shared__ uint32_t l_key[kLdsSortCap];
   __shared__ uint64_t l_mask[kLdsSortCap];
+  __shared__ uint32_t sel_hist[256];
+  __shared__ uint32_t sel_state[3];
   Params* P = bt.P + b;
   if (retry && !P->redo) return;
   const uint32_t ns = P->surv_count;
-  merge_body(P, bt.S, bt.cap, last_pass != 0, ns, bt.skey + (size_t)b * bt.cap, bt.smask + (size_t)b * bt.cap,
-             bt.rkey + (size_t)b * bt.S, bt.rmask + (size_t)b * bt.S,
-             bt.tkey + (size_t)b * bt.S, bt.tmask + (size_t)b * bt.S, l_key, l_mask,
-             (uint32_t)kLdsSortCap);
-}
-
-// k-th smallest (1-based) of keys[0..cnt) for the whole workgroup: four
-// passes of 8-bit digits, most significant first, each a histogram in LDS and
-// a scan of its 256 bins.  Needs blockDim.x == 256.
-__device__ uint32_t radix_select(const uint32_t* keys, uint32_t cnt, uint32_t k, uint32_t* hist,
-                                 uint32_t* state) {
-  const uint32_t t = threadIdx.x;
-  uint32_t prefix = 0u, pmask = 0u, rem = k;
-  for (int shift = 24; shift >= 0; shift -= 8) {
-    hist[t] = 0u;
-    __syncthreads();
-    for (uint32_t j = t; j < cnt; j += blockDim.x) {
-      const uint32_t key = keys[j];
-      if ((key & pmask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
-    }
-    __syncthreads();
-    // inclusive scan of the 256 bins (Hillis-Steele)
-    uint32_t v = hist[t];
-    for (uint32_t o = 1; o < 256u; o <<= 1) {
-      const uint32_t add = t >= o ? hist[t - o] : 0u;
-      __syncthreads();
-      v += add;
-      hist[t] = v;
-      __syncthreads();
-    }
-    const uint32_t before = t == 0 ? 0u : hist[t - 1];
-    if (before < rem && rem <= v) {
-      state[0] = prefix | (t << shift);
-      state[1] = rem - before;
-    }
-    __syncthreads();
-    prefix = state[0];
-    rem = state[1];
-    pmask |= 255u << shift;
-    __syncthreads();
-  }
-  return prefix;
+  merge_body(P, bt.S, bt.cap, last_pass != 0, ns, bt.skey + (size_t)b * bt.cap,
+             bt.smask + (size_t)b * bt.cap, bt.rkey + (size_t)b * bt.S,
+             bt.rmask + (size_t)b * bt.S, bt.tkey + (size_t)b * bt.S,
+             bt.tmask + (size_t)b * bt.S, l_key, l_mask, (uint32_t)kLdsSortCap, sel_hist,
+             sel_state);
 }
 
 // Batch: one workgroup per instance scores its own candidates of the chunk

@@ -152,6 +152,38 @@ def test_pow2_fields_closed_form(torch_dev):
     assert np.array_equal(e.astype(np.int64), -((1 << N) - 1) + 2 * k)
 
 
+@pytest.mark.parametrize("S,dtype", [(1, np.int32), (100, np.int32), (4095, np.int32),
+                                     (100, np.float32)])
+def test_pow2_fields_many_survivors(torch_dev, S, dtype):
+    """J = 0, h_i = 2^i: energies fall with the mask, so every state of a later
+    chunk beats the record and the merge receives whole chunks of survivors
+    (far more than its LDS holds): it keeps only those at or below the S-th
+    smallest survivor key.  Closed form as above."""
+    N = 22
+    J, h = I.free_spins_pow2_fields(N, dtype=dtype)
+    m, e = gpu_search(torch_dev, J, h, S)
+    k = np.arange(S)
+    assert np.array_equal(m.astype(np.int64), ((1 << N) - 1) ^ k)
+    assert np.array_equal(e.astype(np.int64), -((1 << N) - 1) + 2 * k)
+
+
+def test_merge_ties_beyond_lds(torch_dev):
+    """h_i = 2^i for spins 13..21 only: every energy is shared by the 8192
+    masks of one setting of the top spins, and later chunks again beat the
+    record, so the survivors at the S-th smallest key (8192 of them) exceed the
+    merge's LDS and it sorts them all; the S lowest are the S smallest masks
+    with every top spin up (ties go by mask)."""
+    N, lo = 22, 13
+    J = np.zeros((N, N), dtype=np.int32)
+    h = np.zeros(N, dtype=np.int32)
+    h[lo:] = 2 ** np.arange(lo, N)
+    S = 100
+    m, e = gpu_search(torch_dev, J, h, S)
+    top = ((1 << (N - lo)) - 1) << lo
+    assert np.array_equal(m.astype(np.int64), top | np.arange(S))
+    assert np.all(e.astype(np.int64) == -int(h.sum()))
+
+
 def test_prefix_monotone_and_deterministic(torch_dev):
     J, h = I.random_int_dense(26, 5)
     m1, e1 = gpu_search(torch_dev, J, h, 10)
