@@ -43,29 +43,29 @@ SURVEY_STATES_PER_S = 256 * 64 * 2.4e9 / 2.0
 # size of the plain device copy that calibrates the HBM byte counters
 COPY_BYTES = 512 << 20
 # HBM bytes per enumeration launch of the N=48 search from rocprofv3
-# FETCH_SIZE / WRITE_SIZE passes (KiB summed over all 126 k_enum dispatches of
+# FETCH_SIZE / WRITE_SIZE passes (KiB summed over all 153 k_enum dispatches of
 # one search -- 60 of the three-field walk, the paired and plain walks of the
 # first chunks, the repeat launches that exit at once -- per dispatch, as
 # `achieved` counts launches), scaled by what the same counters read for the
 # 512 MiB copy (fetch x2.0, write x1.0); valid for the k_enum source with
 # this SHA-256 prefix only
-TRAFFIC = {"kenum_sha256_16": "9d1dc0d780cdb845", "fetch_kib": 1.26072e6 / 126,
-           "write_kib": 4.76168e6 / 126, "fetch_factor": 524288.0 / 262160.75,
+TRAFFIC = {"kenum_sha256_16": "9d1dc0d780cdb845", "fetch_kib": 1.30584e6 / 153,
+           "write_kib": 5.81140e6 / 153, "fetch_factor": 524288.0 / 262161.125,
            "write_factor": 1.0, "profile": "profiles/k_enum_f32_dense48_counters.md"}
 
 # VALU counters of the search's three-field walk launches (rocprofv3 --pmc,
-# one search of this instance: 60 dispatches, 2.9888 s of kernel time, its
-# 20 chunks, 2.79276e14 configurations = 99.2% of them),
+# one search of this instance: 60 dispatches, 2.9372 s of kernel time, its
+# 20 chunks, 2.759774e14 configurations = 98.0% of them),
 # valid for the k_enum source with this hash only: SQ_INSTS_VALU (wave
 # instructions) x 64 per configuration; the fraction of the doubled-rate
 # issue capacity used, SQ_INSTS_VALU / (1024 SIMDs x cycles x 1/2); the share
 # issued in pairs, 2 SQ_ACTIVE_INST_VALU2 / SQ_INSTS_VALU; and sclk =
 # GRBM_GUI_ACTIVE / 8 XCDs / kernel time.
 COUNTERS = {"kenum_sha256_16": "9d1dc0d780cdb845",
-            "valu_insts_per_state": 3.22298e12 * 64 / 2.79276e14,
-            "valu_active": 3.22298e12 / (1024 * 5.59009e10 / 8 * 0.5),
-            "valu_paired": 2 * 1.54765e12 / 3.22298e12,
-            "sclk_ghz": 5.59009e10 / 8 / 2.9888 / 1e9,
+            "valu_insts_per_state": 3.18537e12 * 64 / 2.759774e14,
+            "valu_active": 3.18537e12 / (1024 * 5.47279e10 / 8 * 0.5),
+            "valu_paired": 2 * 1.53047e12 / 3.18537e12,
+            "sclk_ghz": 5.47279e10 / 8 / 2.9372 / 1e9,
             "profile": "profiles/k_enum_f32_dense48_counters.md"}
 
 

@@ -376,9 +376,8 @@ double sg_probe_valu(int op, int waves_per_simd);
  *
  * sg_debug_set_fill: the number of lanes the work plans of (current device,
  * stream) assume (lanes >= 1; 0 restores the device's own values): the
- * resident lanes, and the most lanes a single search's chunk launches (by
- * default 8 times the resident lanes, for chunks of 22 free spins per
- * lane).  While it is set, every chunk of 14 or more free spins takes the
+ * resident lanes of the density of states and log Z, and the lanes a single
+ * search plans its chunks for (by default 8 times the resident lanes).  While it is set, every chunk of 14 or more free spins takes the
  * three-field walk (by default only chunks of 20 or more that launch at
  * least the resident lanes).  The single search, the density of
  * states and log Z give each lane more free spins when there are fewer lanes

@@ -235,12 +235,12 @@ hipError_t ws_event_pair(Workspace* w, hipEvent_t* a, hipEvent_t* b) {
 std::mutex g_mu;
 std::map<std::pair<int, hipStream_t>, Workspace*> g_ws;
 
-// A single search's chunks of kMaxFree free spins per lane grow to this many
-// times the device's resident lanes: the walk's lanes take unequal times (a
-// lane whose blocks fail the bound test re-walks them), and with several
-// workgroups per slot the device refills a CU as soon as one finishes instead
-// of waiting for the slowest lane of a launch (N = 48 dense search: 3.03 s at
-// 8 times the resident lanes, 3.86 s at once).
+// A single search's chunks launch this many times the device's resident
+// lanes: the walk's lanes take unequal times (a lane whose blocks fail the
+// bound test re-walks them), and with several workgroups per slot the device
+// refills a CU as soon as one finishes instead of waiting for the slowest lane
+// of a launch (N = 48 dense search: 3.03 s at 8 times the resident lanes,
+// 3.86 s at once).
 constexpr int64_t kSearchLaunchFills = 8;
 // The three-field walk (blocks of kUPk, three per word) takes the chunks of
 // at least kTriMinFree free spins that launch at least the resident lanes;
@@ -460,8 +460,12 @@ sg_status search_on(Workspace* w, bool isint, int N, const void* J, const void* 
   w->last_launches = 0;
   if (N >= U) HIP_TRY(launch_tables(isint, U, bt, ncap, true, st));
   if (use10) HIP_TRY(launch_tables(isint, kUPk, bt, ncap, true, st));
-  const std::vector<PlanChunk> plan =
-      plan_chunks(N, S, lo, hi, w->fill[isint ? 1 : 0], U, w->launch[isint ? 1 : 0]);
+  // chunks planned for the lanes of a launch (free spins included), not the
+  // resident lanes: more, shorter lanes per chunk let the device balance them
+  // (dense searches at N = 40, 42, 44: 23, 70 and 255 ms against 33, 91 and
+  // 299 ms planned for the resident lanes; N = 48 unchanged)
+  const int64_t launch = w->launch[isint ? 1 : 0];
+  const std::vector<PlanChunk> plan = plan_chunks(N, S, lo, hi, launch, U, launch);
   double states = 0.0;
   for (const PlanChunk& pc : plan) {
     if (pc.n == 0) {
