@@ -85,10 +85,11 @@ typedef enum {
  *   energies_out device float[S]   energies of those states
  *
  * The enumeration accumulates energies incrementally in fp32 (block-start
- * values, with the states of a block in 16-bit fixed point relative to the
- * pruning bound where a lane walks at least 10 spins), re-anchors from
- * scratch every 2^10 Gray-code flips (2^14 in the fixed-point walk, whose
- * fp32 part rounds far less often), prunes with a margin that bounds the
+ * values, with the states of a block in fixed point relative to the pruning
+ * bound where a lane walks at least 10 spins: 16-bit fields, or 11/11/10-bit
+ * fields from 20 spins on), re-anchors from scratch every 2^10 Gray-code
+ * flips (2^14 in the fixed-point walks, whose fp32 part rounds far less
+ * often), prunes with a margin that bounds the
  * accumulated rounding, and rescores every surviving candidate from scratch
  * in fp64; the returned energies are those fp64 values rounded to fp32 (-0
  * is returned as +0).
