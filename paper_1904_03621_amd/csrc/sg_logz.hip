@@ -334,6 +334,10 @@ __global__ __launch_bounds__(256, (lz_min_blocks<kMode, NB>())) void k_logz(LzAr
   // blocks; blocks of 8 read their 3 KB with scalar loads)
   constexpr bool kBqLds = kMode == 1 || U > kLzUF;
   __shared__ float s_bq[kBqLds ? NB * kQ : 1];
+  // the partition sums over records of 10 walk their blocks in pairs (below)
+  // and keep the lane's fields of the low spins in LDS
+  constexpr bool kPairs = kMode == 0 && kBqLds;
+  __shared__ double s_yl[kPairs ? U * 256 : 1];
 
   const int b = blockIdx.x / bpi;
   const int blk = blockIdx.x - b * bpi;
@@ -363,6 +367,7 @@ __global__ __launch_bounds__(256, (lz_min_blocks<kMode, NB>())) void k_logz(LzAr
       acc += ((p >> (q - n)) & 1ull) ? jq : -jq;
     }
     y[f] = acc;
+    if (kPairs) s_yl[f * 256 + tid] = acc;
   }
   for (int f = U; f < n; ++f) {
     double acc = 0.0;
@@ -426,79 +431,85 @@ __global__ __launch_bounds__(256, (lz_min_blocks<kMode, NB>())) void k_logz(LzAr
   for (int k = 0; k < H; ++k) gh += s_y[k * 256 + tid];
 
   const uint32_t nblocks = 1u << (n - U);
-  for (uint32_t T = 0; T < nblocks; ++T) {
-    // the bq tables are re-read from LDS every block instead of being held in
-    // registers for the whole lane
-    asm volatile("" ::: "memory");
-    const double* rec = tab + (size_t)T * (2 + U);
-    const bool odd = T & 1u;
-    const uint32_t xh = T ^ (T >> 1);  // high spins of this block (bit k: spin U + k)
-    if (T) {
-      const int kb = __builtin_ctz(T);  // the high spin that flipped
-      const double yb = 2.0 * s_y[kb * 256 + tid];
-      gh = ((xh >> kb) & 1u) ? gh - yb : gh + yb;
-    }
-    // energy at the block start without the low-low part
-    const double G0 = (odd ? epa1 : epa0) + rec[1] + gh;
-    // phi_f: coefficient of s_f (f < U) in the block's energy
-    double phi[U];
+  // Records of 10 (bq in LDS): the blocks go in pairs (T, T + 1) and every
+  // bq entry read from LDS enters the contractions of both.  A broadcast
+  // read of four entries occupies the LDS for four cycles, once per four
+  // fused multiply-adds of one block: with one block per read the LDS was
+  // the bound (busy nine cycles in ten), not the VALU.
+  if constexpr (kPairs) {
+    // block T's lower bound Lb of E - E0 and its fields phi_f (fp32: only
+    // their magnitudes and signs enter the factors), the high spins' field
+    // energy being gh (the same steps as the single-block walk below)
+    auto block_consts = [&](uint32_t T, double ghT, double& Lb, float (&ph)[U]) {
+      const double* rec = tab + (size_t)T * (2 + U);
+      const bool odd = T & 1u;
+      const double G0 = (odd ? epa1 : epa0) + rec[1] + ghT;
+      double phi[U];
 #pragma unroll
-    for (int f = 0; f < U - 1; ++f) phi[f] = -(y[f] + 0.5 * rec[2 + f]);
-    phi[U - 1] = -(y[U - 1] + 0.5 * (odd ? rec[2 + U - 1] : -rec[2 + U - 1]));
-    double K = odd ? G0 - phi[U - 1] : G0 + phi[U - 1];
-    double sabs = 0.0;
-#pragma unroll
-    for (int f = 0; f < U; ++f) {
-      if (f < U - 1) K += phi[f];
-      sabs += fabs(phi[f]);
-    }
-    const double Lb = K - sabs + base;  // lower bound of E - E0 over the block
-
-    float pa[U];
-    bool up[U];  // the exponential factor goes with s_f = +1 (cp) rather than -1
-#pragma unroll
-    for (int f = 0; f < U; ++f) {
-      pa[f] = (float)fabs(phi[f]);
-      up[f] = phi[f] > 0.0;
-    }
-    // the gradient walk indexes spin U-1 by the bits of its Gray steps, which
-    // flip that spin in odd blocks: exchange its two factors there
-    if (kMode == 1 && odd) up[U - 1] = !up[U - 1];
-    // c_f(s_f) at beta k: 1 for the sign that lowers phi_f s_f, 2^(2 c2 |phi_f|)
-    // for the other (cp: s_f = +1, cm: s_f = -1)
-    auto factors = [&](int k, float* cp, float* cm) {
+      for (int f = 0; f < U - 1; ++f) phi[f] = -(s_yl[f * 256 + tid] + 0.5 * rec[2 + f]);
+      phi[U - 1] = -(s_yl[(U - 1) * 256 + tid] + 0.5 * (odd ? rec[2 + U - 1] : -rec[2 + U - 1]));
+      double K = odd ? G0 - phi[U - 1] : G0 + phi[U - 1];
+      double sabs = 0.0;
 #pragma unroll
       for (int f = 0; f < U; ++f) {
-        const float af = __builtin_amdgcn_exp2f(c2f2[k] * pa[f]);
-        cp[f] = up[f] ? af : 1.0f;
-        cm[f] = up[f] ? 1.0f : af;
+        if (f < U - 1) K += phi[f];
+        sabs += fabs(phi[f]);
+        ph[f] = (float)phi[f];
+      }
+      Lb = K - sabs + base;
+    };
+    // one flip of a high spin from block T - 1 to block T
+    auto step_gh = [&](uint32_t T) {
+      const uint32_t xh = T ^ (T >> 1);
+      const int kb = __builtin_ctz(T);
+      const double yb = 2.0 * s_y[kb * 256 + tid];
+      gh = ((xh >> kb) & 1u) ? gh - yb : gh + yb;
+    };
+    // c_f(s_f) at beta k: 1 for the sign that lowers phi_f s_f, 2^(2 c2 |phi_f|)
+    // for the other (cp: s_f = +1, cm: s_f = -1)
+    auto factors = [&](int k, const float (&ph)[U], float* cp, float* cm) {
+#pragma unroll
+      for (int f = 0; f < U; ++f) {
+        const float af = __builtin_amdgcn_exp2f(c2f2[k] * fabsf(ph[f]));
+        cp[f] = ph[f] > 0.0f ? af : 1.0f;
+        cm[f] = ph[f] > 0.0f ? 1.0f : af;
       }
     };
-
-    if constexpr (kMode == 0) {
-      // one beta at a time: sum_x A(x_lo) B(x_hi) bq(x) over the 2^U
-      // configurations, x_lo the spins below U/2
+    for (uint32_t T = 0; T < nblocks; T += 2) {
+      asm volatile("" ::: "memory");
+      // a lane of a single block (n = U) gives the second block zero weight
+      const bool two = T + 1 < nblocks;
+      double Lb0, Lb1;
+      float ph0[U], ph1[U];
+      if (T) step_gh(T);
+      block_consts(T, gh, Lb0, ph0);
+      if (two) step_gh(T + 1);
+      block_consts(two ? T + 1 : T, gh, Lb1, ph1);
 #pragma unroll
       for (int k = 0; k < NB; ++k) {
-        const double P = valid ? exp2_wide(c2[k] * Lb) : 0.0;
-        float cp[U], cm[U], Af[kM], Bf[kM];
-        factors(k, cp, cm);
-        factor_products<U / 2>(cp, cm, Af);
-        factor_products<U / 2>(cp + U / 2, cm + U / 2, Bf);
-        // bq by configuration (wave-uniform: scalar loads into SGPRs for
-        // blocks of 8, broadcast LDS reads for blocks of 10), in chunks of
-        // kC = min(2^(U/2), 16) entries, each read one chunk ahead of its
-        // products.  The empty asm after each chunk ties its products
-        // (through u) to the reads (memory clobber), so later chunks are not
-        // fetched early.
-        const float* q =
-            kBqLds ? s_bq + k * kQ : lzq + ((size_t)b * kMaxBeta + k) * lz_q_stride(U);
-        constexpr int kC = kM < 16 ? kM : 16;
+        const double P0 = valid ? exp2_wide(c2[k] * Lb0) : 0.0;
+        const double P1 = valid && two ? exp2_wide(c2[k] * Lb1) : 0.0;
+        // A: the factor products of spins 0-4; B(r) for spins 5-9 is
+        // B4(spins 5, 6) x B8(spins 7-9), applied to the row sums in two steps
+        float cp[U], cm[U], A0[kM], A1[kM], B40[4], B41[4], B80[8], B81[8];
+        factors(k, ph0, cp, cm);
+        factor_products<U / 2>(cp, cm, A0);
+        factor_products<2>(cp + U / 2, cm + U / 2, B40);
+        factor_products<3>(cp + U / 2 + 2, cm + U / 2 + 2, B80);
+        factors(k, ph1, cp, cm);
+        factor_products<U / 2>(cp, cm, A1);
+        factor_products<2>(cp + U / 2, cm + U / 2, B41);
+        factor_products<3>(cp + U / 2 + 2, cm + U / 2 + 2, B81);
+        // bq by configuration (x = x_lo + 2^(U/2) r) in chunks of kC
+        // entries, each read one chunk ahead of its products; the empty asm
+        // after each chunk keeps later chunks from being fetched early
+        const float* q = s_bq + k * kQ;
+        constexpr int kC = 8;
         constexpr int kPer = kM / kC;  // chunks per row
         float qc[kC], qn[kC];
 #pragma unroll
         for (int i = 0; i < kC; ++i) qc[i] = q[i];
-        float S = 0.0f, u = 0.0f;
+        float S0 = 0.0f, S1 = 0.0f, W0 = 0.0f, W1 = 0.0f, u0 = 0.0f, u1 = 0.0f;
 #pragma unroll
         for (int c = 0; c < kM * kPer; ++c) {
           if (c + 1 < kM * kPer) {
@@ -507,84 +518,191 @@ __global__ __launch_bounds__(256, (lz_min_blocks<kMode, NB>())) void k_logz(LzAr
           }
           const int x1 = kC * (c % kPer);
 #pragma unroll
-          for (int i = 0; i < kC; ++i) u = fmaf(Af[x1 + i], qc[i], u);
-          if (c % kPer == kPer - 1) {
-            S = fmaf(Bf[c / kPer], u, S);
-            u = 0.0f;
+          for (int i = 0; i < kC; ++i) {
+            u0 = fmaf(A0[x1 + i], qc[i], u0);
+            u1 = fmaf(A1[x1 + i], qc[i], u1);
           }
-          asm volatile("" : "+v"(S), "+v"(u) : : "memory");
+          if (c % kPer == kPer - 1) {
+            const int r = c / kPer;
+            W0 = fmaf(B40[r & 3], u0, W0);
+            W1 = fmaf(B41[r & 3], u1, W1);
+            u0 = 0.0f;
+            u1 = 0.0f;
+            if ((r & 3) == 3) {
+              S0 = fmaf(B80[r >> 2], W0, S0);
+              S1 = fmaf(B81[r >> 2], W1, S1);
+              W0 = 0.0f;
+              W1 = 0.0f;
+            }
+          }
+          asm volatile("" : "+v"(S0), "+v"(S1), "+v"(W0), "+v"(W1), "+v"(u0), "+v"(u1) : : "memory");
 #pragma unroll
           for (int i = 0; i < kC; ++i) qc[i] = qn[i];
         }
-        L[k] += P * (double)S;
+        L[k] += P0 * (double)S0 + P1 * (double)S1;
       }
-    } else {
-      // A: factor products of spins 0-2 times the beta's weight (folded into
-      // spin 0's two factors); B: spins 3-5, indexed by the Gray step's bits
-      // (block parity folded in through up[])
-      float Af[NB][8], Bf[NB][8];
-      const float* bqs[NB];
-#pragma unroll
-      for (int k = 0; k < NB; ++k) {
-        const double P = valid ? exp2_wide(c2[k] * Lb) : 0.0;
-        const float sk = (float)(a.coef[(size_t)b * 2 * kMaxBeta + k] * P);
-        float cp[U], cm[U];
-        factors(k, cp, cm);
-        cp[0] *= sk;
-        cm[0] *= sk;
-        factor_products<3>(cp, cm, Af[k]);
-        factor_products<3>(cp + 3, cm + 3, Bf[k]);
-        bqs[k] = s_bq + k * kQ + kSteps * (odd ? 2 : 1);
+    }
+  } else {
+    for (uint32_t T = 0; T < nblocks; ++T) {
+      // the bq tables are re-read from LDS every block instead of being held in
+      // registers for the whole lane
+      asm volatile("" ::: "memory");
+      const double* rec = tab + (size_t)T * (2 + U);
+      const bool odd = T & 1u;
+      const uint32_t xh = T ^ (T >> 1);  // high spins of this block (bit k: spin U + k)
+      if (T) {
+        const int kb = __builtin_ctz(T);  // the high spin that flipped
+        const double yb = 2.0 * s_y[kb * 256 + tid];
+        gh = ((xh >> kb) & 1u) ? gh - yb : gh + yb;
       }
-      BlockWalk<NB, false> bw{Af, Bf, bqs, nullptr, odd ? 1.0f : -1.0f};
-      const Coefs C = bw.template walk<U, 0>();
-      // per-lane totals for the prefix-involving moments
-      Om += (double)C.o;
+      // energy at the block start without the low-low part
+      const double G0 = (odd ? epa1 : epa0) + rec[1] + gh;
+      // phi_f: coefficient of s_f (f < U) in the block's energy
+      double phi[U];
 #pragma unroll
-      for (int f = 0; f < U; ++f) A[f] += (double)C.s[f];
+      for (int f = 0; f < U - 1; ++f) phi[f] = -(y[f] + 0.5 * rec[2 + f]);
+      phi[U - 1] = -(y[U - 1] + 0.5 * (odd ? rec[2 + U - 1] : -rec[2 + U - 1]));
+      double K = odd ? G0 - phi[U - 1] : G0 + phi[U - 1];
+      double sabs = 0.0;
 #pragma unroll
-      for (int k = 0; k < kLzHigh; ++k)
-        if (k < H) M[k] += ((xh >> k) & 1u) ? (double)C.o : -(double)C.o;
-      // wave sums of the 22 coefficients: each is first summed over the 16
-      // lanes of its row by DPP shifts (the row's last lane ends with the
-      // total), the 4 row totals go through LDS (one 24-float row each), and
-      // lane c < 22 adds the four totals of coefficient c
-      float cv[kCoefStride];
-      cv[0] = row_total(C.o);
-#pragma unroll
-      for (int f = 0; f < U; ++f) cv[1 + f] = row_total(C.s[f]);
-#pragma unroll
-      for (int k = 0; k < 15; ++k) cv[1 + U + k] = row_total(C.p[k]);
-      cv[kNCoef] = 0.0f;
-      cv[kNCoef + 1] = 0.0f;
-      if ((ln & 15) == 15) {
-        float* cw = s_c + (wv * 4 + (ln >> 4)) * kCoefStride;
-#pragma unroll
-        for (int j = 0; j < kCoefStride; j += 4)
-          *(float4*)(cw + j) = make_float4(cv[j], cv[j + 1], cv[j + 2], cv[j + 3]);
+      for (int f = 0; f < U; ++f) {
+        if (f < U - 1) K += phi[f];
+        sabs += fabs(phi[f]);
       }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      if (ln < kNCoef) {
-        const float* col = s_c + wv * 4 * kCoefStride + ln;
-        s_t[wv * kNCoef + ln] = (col[0] + col[kCoefStride]) +
-                                (col[2 * kCoefStride] + col[3 * kCoefStride]);
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const double Lb = K - sabs + base;  // lower bound of E - E0 over the block
+
+      float pa[U];
+      bool up[U];  // the exponential factor goes with s_f = +1 (cp) rather than -1
 #pragma unroll
-      for (int r = 0; r < 2; ++r) {
-        if (ln + 64 * r < nslots) {
-          const float v = s_t[wv * kNCoef + sc[r]];
-          // product of the high signs in the mask: -1 per high spin that is down
-          const int downs = __popc(sm[r]) - __popc(sm[r] & xh);
-          dacc[r] += (downs & 1) ? -(double)v : (double)v;
+      for (int f = 0; f < U; ++f) {
+        pa[f] = (float)fabs(phi[f]);
+        up[f] = phi[f] > 0.0;
+      }
+      // the gradient walk indexes spin U-1 by the bits of its Gray steps, which
+      // flip that spin in odd blocks: exchange its two factors there
+      if (kMode == 1 && odd) up[U - 1] = !up[U - 1];
+      // c_f(s_f) at beta k: 1 for the sign that lowers phi_f s_f, 2^(2 c2 |phi_f|)
+      // for the other (cp: s_f = +1, cm: s_f = -1)
+      auto factors = [&](int k, float* cp, float* cm) {
+#pragma unroll
+        for (int f = 0; f < U; ++f) {
+          const float af = __builtin_amdgcn_exp2f(c2f2[k] * pa[f]);
+          cp[f] = up[f] ? af : 1.0f;
+          cm[f] = up[f] ? 1.0f : af;
         }
+      };
+
+      if constexpr (kMode == 0) {
+        // one beta at a time: sum_x A(x_lo) B(x_hi) bq(x) over the 2^U
+        // configurations, x_lo the spins below U/2
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+          const double P = valid ? exp2_wide(c2[k] * Lb) : 0.0;
+          float cp[U], cm[U], Af[kM], Bf[kM];
+          factors(k, cp, cm);
+          factor_products<U / 2>(cp, cm, Af);
+          factor_products<U / 2>(cp + U / 2, cm + U / 2, Bf);
+          // bq by configuration (wave-uniform: scalar loads into SGPRs for
+          // blocks of 8, broadcast LDS reads for blocks of 10), in chunks of
+          // kC = min(2^(U/2), 16) entries, each read one chunk ahead of its
+          // products.  The empty asm after each chunk ties its products
+          // (through u) to the reads (memory clobber), so later chunks are not
+          // fetched early.
+          const float* q =
+              kBqLds ? s_bq + k * kQ : lzq + ((size_t)b * kMaxBeta + k) * lz_q_stride(U);
+          constexpr int kC = kM < 16 ? kM : 16;
+          constexpr int kPer = kM / kC;  // chunks per row
+          float qc[kC], qn[kC];
+#pragma unroll
+          for (int i = 0; i < kC; ++i) qc[i] = q[i];
+          float S = 0.0f, u = 0.0f;
+#pragma unroll
+          for (int c = 0; c < kM * kPer; ++c) {
+            if (c + 1 < kM * kPer) {
+#pragma unroll
+              for (int i = 0; i < kC; ++i) qn[i] = q[kC * (c + 1) + i];
+            }
+            const int x1 = kC * (c % kPer);
+#pragma unroll
+            for (int i = 0; i < kC; ++i) u = fmaf(Af[x1 + i], qc[i], u);
+            if (c % kPer == kPer - 1) {
+              S = fmaf(Bf[c / kPer], u, S);
+              u = 0.0f;
+            }
+            asm volatile("" : "+v"(S), "+v"(u) : : "memory");
+#pragma unroll
+            for (int i = 0; i < kC; ++i) qc[i] = qn[i];
+          }
+          L[k] += P * (double)S;
+        }
+      } else {
+        // A: factor products of spins 0-2 times the beta's weight (folded into
+        // spin 0's two factors); B: spins 3-5, indexed by the Gray step's bits
+        // (block parity folded in through up[])
+        float Af[NB][8], Bf[NB][8];
+        const float* bqs[NB];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+          const double P = valid ? exp2_wide(c2[k] * Lb) : 0.0;
+          const float sk = (float)(a.coef[(size_t)b * 2 * kMaxBeta + k] * P);
+          float cp[U], cm[U];
+          factors(k, cp, cm);
+          cp[0] *= sk;
+          cm[0] *= sk;
+          factor_products<3>(cp, cm, Af[k]);
+          factor_products<3>(cp + 3, cm + 3, Bf[k]);
+          bqs[k] = s_bq + k * kQ + kSteps * (odd ? 2 : 1);
+        }
+        BlockWalk<NB, false> bw{Af, Bf, bqs, nullptr, odd ? 1.0f : -1.0f};
+        const Coefs C = bw.template walk<U, 0>();
+        // per-lane totals for the prefix-involving moments
+        Om += (double)C.o;
+#pragma unroll
+        for (int f = 0; f < U; ++f) A[f] += (double)C.s[f];
+#pragma unroll
+        for (int k = 0; k < kLzHigh; ++k)
+          if (k < H) M[k] += ((xh >> k) & 1u) ? (double)C.o : -(double)C.o;
+        // wave sums of the 22 coefficients: each is first summed over the 16
+        // lanes of its row by DPP shifts (the row's last lane ends with the
+        // total), the 4 row totals go through LDS (one 24-float row each), and
+        // lane c < 22 adds the four totals of coefficient c
+        float cv[kCoefStride];
+        cv[0] = row_total(C.o);
+#pragma unroll
+        for (int f = 0; f < U; ++f) cv[1 + f] = row_total(C.s[f]);
+#pragma unroll
+        for (int k = 0; k < 15; ++k) cv[1 + U + k] = row_total(C.p[k]);
+        cv[kNCoef] = 0.0f;
+        cv[kNCoef + 1] = 0.0f;
+        if ((ln & 15) == 15) {
+          float* cw = s_c + (wv * 4 + (ln >> 4)) * kCoefStride;
+#pragma unroll
+          for (int j = 0; j < kCoefStride; j += 4)
+            *(float4*)(cw + j) = make_float4(cv[j], cv[j + 1], cv[j + 2], cv[j + 3]);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (ln < kNCoef) {
+          const float* col = s_c + wv * 4 * kCoefStride + ln;
+          s_t[wv * kNCoef + ln] = (col[0] + col[kCoefStride]) +
+                                  (col[2 * kCoefStride] + col[3 * kCoefStride]);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+          if (ln + 64 * r < nslots) {
+            const float v = s_t[wv * kNCoef + sc[r]];
+            // product of the high signs in the mask: -1 per high spin that is down
+            const int downs = __popc(sm[r]) - __popc(sm[r] & xh);
+            dacc[r] += (downs & 1) ? -(double)v : (double)v;
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
       }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
     }
   }
 

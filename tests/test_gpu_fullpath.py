@@ -325,9 +325,10 @@ def check_against_moments(lz, gJ, gh, J, h, betas, orc, what):
 
 @pytest.mark.parametrize("N", [16, 20])
 def test_logz_high_spin_walk(orc, torch_dev, N):
-    """14 free spins per lane (as at the 256 x N = 28 workload): both walks take
-    records of 8 low spins with 6 high spins; the gradient walk's sub-blocks of
-    6 give its low-high and high-high pair slots 8 high spins."""
+    """14 free spins per lane (as at the 256 x N = 28 workload): the partition
+    sums take records of 10 low spins with 4 high spins, two blocks at a time;
+    the gradient walk takes records of 8 with 6 high spins, and its sub-blocks
+    of 6 give its low-high and high-high pair slots 8 high spins."""
     B = 2
     J, h = I.logz_batch(B, N, 500 + N)
     with plan_fill(1):
@@ -337,11 +338,33 @@ def test_logz_high_spin_walk(orc, torch_dev, N):
                               "N=%d b=%d" % (N, b))
 
 
+@pytest.mark.parametrize("N,betas", [(11, [1.0]), (12, [0.5, 2.0]), (13, [0.5, 1.0, 2.0]),
+                                     (18, [0.7]), (22, [0.5, 1.5])])
+def test_logz_paired_blocks(orc, torch_dev, N, betas):
+    """The partition sums over records of 10 walk a lane's blocks in pairs:
+    2, 4, 8 and 16 blocks per lane (N = 11, 12, 13 and N >= 14 with every
+    spin from 10 up free), for one, two and three beta, against the oracle's
+    log Z (1e-6 relative)."""
+    import paper_1904_03621_amd as sg
+    B = 2
+    J, h = I.logz_batch(B, N, 700 + N)
+    bt = np.asarray(betas, dtype=np.float32)
+    Jt, ht, btt = to_dev(torch_dev, J, h, bt)
+    with plan_fill(1):
+        lz, _, _, _ = sg.logz_forward(Jt, ht, btt, 4)
+    lz = lz.cpu().numpy()
+    for b in range(B):
+        ref, _ = orc.logz(J[b], h[b], bt)
+        for k in range(len(bt)):
+            assert abs(lz[b, k] - ref[k]) <= 1e-6 * abs(ref[k]), (N, b, k, lz[b, k], ref[k])
+
+
 @pytest.mark.timeout(900)
 def test_logz_workload_instance0(orc, torch_dev):
     """The 256 x N = 28 workload as run by the benchmark (14 free spins per
-    lane, records of 8 with 6 high spins): instance 0's log Z and both
-    gradients at each beta against the oracle, entry by entry."""
+    lane; the partition sums over pairs of records of 10, the gradient walk
+    over records of 8): instance 0's log Z and both gradients at each beta
+    against the oracle, entry by entry."""
     w = I.workload("logz256")
     lz, gJ, gh = gpu_logz_per_beta(torch_dev, w["J"], w["h"], w["beta"])
     check_against_moments(lz[0], gJ[:, 0], gh[:, 0], w["J"][0], w["h"][0], w["beta"], orc,
