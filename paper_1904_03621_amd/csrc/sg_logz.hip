@@ -436,45 +436,49 @@ __global__ __launch_bounds__(256, (lz_min_blocks<kMode, NB>())) void k_logz(LzAr
   // read of four entries occupies the LDS for four cycles, once per four
   // fused multiply-adds of one block: with one block per read the LDS was
   // the bound (busy nine cycles in ten), not the VALU.
+  // Block T's lower bound Lb of E - E0 over its configurations and the
+  // coefficients phi_f of its low spins (fp32: only their magnitudes and
+  // signs enter the factors), ghT being the high spins' field energy there.
+  auto block_consts = [&](uint32_t T, double ghT, double& Lb, float (&ph)[U]) {
+    const double* rec = tab + (size_t)T * (2 + U);
+    const bool odd = T & 1u;
+    // energy at the block start without the low-low part
+    const double G0 = (odd ? epa1 : epa0) + rec[1] + ghT;
+    double phi[U];
+#pragma unroll
+    for (int f = 0; f < U; ++f) {
+      const double yf = kPairs ? s_yl[f * 256 + tid] : y[f];
+      const double wf = f < U - 1 || odd ? rec[2 + f] : -rec[2 + f];
+      phi[f] = -(yf + 0.5 * wf);
+    }
+    double K = odd ? G0 - phi[U - 1] : G0 + phi[U - 1];
+    double sabs = 0.0;
+#pragma unroll
+    for (int f = 0; f < U; ++f) {
+      if (f < U - 1) K += phi[f];
+      sabs += fabs(phi[f]);
+      ph[f] = (float)phi[f];
+    }
+    Lb = K - sabs + base;
+  };
+  // one flip of a high spin from block T - 1 to block T (T > 0)
+  auto step_gh = [&](uint32_t T) {
+    const uint32_t xh = T ^ (T >> 1);
+    const int kb = __builtin_ctz(T);
+    const double yb = 2.0 * s_y[kb * 256 + tid];
+    gh = ((xh >> kb) & 1u) ? gh - yb : gh + yb;
+  };
+  // c_f(s_f) at beta k: 1 for the sign that lowers phi_f s_f, 2^(2 c2 |phi_f|)
+  // for the other (cp: s_f = +1, cm: s_f = -1)
+  auto factors = [&](int k, const float (&ph)[U], float* cp, float* cm) {
+#pragma unroll
+    for (int f = 0; f < U; ++f) {
+      const float af = __builtin_amdgcn_exp2f(c2f2[k] * fabsf(ph[f]));
+      cp[f] = ph[f] > 0.0f ? af : 1.0f;
+      cm[f] = ph[f] > 0.0f ? 1.0f : af;
+    }
+  };
   if constexpr (kPairs) {
-    // block T's lower bound Lb of E - E0 and its fields phi_f (fp32: only
-    // their magnitudes and signs enter the factors), the high spins' field
-    // energy being gh (the same steps as the single-block walk below)
-    auto block_consts = [&](uint32_t T, double ghT, double& Lb, float (&ph)[U]) {
-      const double* rec = tab + (size_t)T * (2 + U);
-      const bool odd = T & 1u;
-      const double G0 = (odd ? epa1 : epa0) + rec[1] + ghT;
-      double phi[U];
-#pragma unroll
-      for (int f = 0; f < U - 1; ++f) phi[f] = -(s_yl[f * 256 + tid] + 0.5 * rec[2 + f]);
-      phi[U - 1] = -(s_yl[(U - 1) * 256 + tid] + 0.5 * (odd ? rec[2 + U - 1] : -rec[2 + U - 1]));
-      double K = odd ? G0 - phi[U - 1] : G0 + phi[U - 1];
-      double sabs = 0.0;
-#pragma unroll
-      for (int f = 0; f < U; ++f) {
-        if (f < U - 1) K += phi[f];
-        sabs += fabs(phi[f]);
-        ph[f] = (float)phi[f];
-      }
-      Lb = K - sabs + base;
-    };
-    // one flip of a high spin from block T - 1 to block T
-    auto step_gh = [&](uint32_t T) {
-      const uint32_t xh = T ^ (T >> 1);
-      const int kb = __builtin_ctz(T);
-      const double yb = 2.0 * s_y[kb * 256 + tid];
-      gh = ((xh >> kb) & 1u) ? gh - yb : gh + yb;
-    };
-    // c_f(s_f) at beta k: 1 for the sign that lowers phi_f s_f, 2^(2 c2 |phi_f|)
-    // for the other (cp: s_f = +1, cm: s_f = -1)
-    auto factors = [&](int k, const float (&ph)[U], float* cp, float* cm) {
-#pragma unroll
-      for (int f = 0; f < U; ++f) {
-        const float af = __builtin_amdgcn_exp2f(c2f2[k] * fabsf(ph[f]));
-        cp[f] = ph[f] > 0.0f ? af : 1.0f;
-        cm[f] = ph[f] > 0.0f ? 1.0f : af;
-      }
-    };
     for (uint32_t T = 0; T < nblocks; T += 2) {
       asm volatile("" ::: "memory");
       // a lane of a single block (n = U) gives the second block zero weight
@@ -547,50 +551,15 @@ __global__ __launch_bounds__(256, (lz_min_blocks<kMode, NB>())) void k_logz(LzAr
       // the bq tables are re-read from LDS every block instead of being held in
       // registers for the whole lane
       asm volatile("" ::: "memory");
-      const double* rec = tab + (size_t)T * (2 + U);
       const bool odd = T & 1u;
       const uint32_t xh = T ^ (T >> 1);  // high spins of this block (bit k: spin U + k)
-      if (T) {
-        const int kb = __builtin_ctz(T);  // the high spin that flipped
-        const double yb = 2.0 * s_y[kb * 256 + tid];
-        gh = ((xh >> kb) & 1u) ? gh - yb : gh + yb;
-      }
-      // energy at the block start without the low-low part
-      const double G0 = (odd ? epa1 : epa0) + rec[1] + gh;
-      // phi_f: coefficient of s_f (f < U) in the block's energy
-      double phi[U];
-#pragma unroll
-      for (int f = 0; f < U - 1; ++f) phi[f] = -(y[f] + 0.5 * rec[2 + f]);
-      phi[U - 1] = -(y[U - 1] + 0.5 * (odd ? rec[2 + U - 1] : -rec[2 + U - 1]));
-      double K = odd ? G0 - phi[U - 1] : G0 + phi[U - 1];
-      double sabs = 0.0;
-#pragma unroll
-      for (int f = 0; f < U; ++f) {
-        if (f < U - 1) K += phi[f];
-        sabs += fabs(phi[f]);
-      }
-      const double Lb = K - sabs + base;  // lower bound of E - E0 over the block
-
-      float pa[U];
-      bool up[U];  // the exponential factor goes with s_f = +1 (cp) rather than -1
-#pragma unroll
-      for (int f = 0; f < U; ++f) {
-        pa[f] = (float)fabs(phi[f]);
-        up[f] = phi[f] > 0.0;
-      }
+      if (T) step_gh(T);
+      double Lb;
+      float ph[U];
+      block_consts(T, gh, Lb, ph);
       // the gradient walk indexes spin U-1 by the bits of its Gray steps, which
       // flip that spin in odd blocks: exchange its two factors there
-      if (kMode == 1 && odd) up[U - 1] = !up[U - 1];
-      // c_f(s_f) at beta k: 1 for the sign that lowers phi_f s_f, 2^(2 c2 |phi_f|)
-      // for the other (cp: s_f = +1, cm: s_f = -1)
-      auto factors = [&](int k, float* cp, float* cm) {
-#pragma unroll
-        for (int f = 0; f < U; ++f) {
-          const float af = __builtin_amdgcn_exp2f(c2f2[k] * pa[f]);
-          cp[f] = up[f] ? af : 1.0f;
-          cm[f] = up[f] ? 1.0f : af;
-        }
-      };
+      if (kMode == 1 && odd) ph[U - 1] = -ph[U - 1];
 
       if constexpr (kMode == 0) {
         // one beta at a time: sum_x A(x_lo) B(x_hi) bq(x) over the 2^U
@@ -599,7 +568,7 @@ __global__ __launch_bounds__(256, (lz_min_blocks<kMode, NB>())) void k_logz(LzAr
         for (int k = 0; k < NB; ++k) {
           const double P = valid ? exp2_wide(c2[k] * Lb) : 0.0;
           float cp[U], cm[U], Af[kM], Bf[kM];
-          factors(k, cp, cm);
+          factors(k, ph, cp, cm);
           factor_products<U / 2>(cp, cm, Af);
           factor_products<U / 2>(cp + U / 2, cm + U / 2, Bf);
           // bq by configuration (wave-uniform: scalar loads into SGPRs for
@@ -646,7 +615,7 @@ __global__ __launch_bounds__(256, (lz_min_blocks<kMode, NB>())) void k_logz(LzAr
           const double P = valid ? exp2_wide(c2[k] * Lb) : 0.0;
           const float sk = (float)(a.coef[(size_t)b * 2 * kMaxBeta + k] * P);
           float cp[U], cm[U];
-          factors(k, cp, cm);
+          factors(k, ph, cp, cm);
           cp[0] *= sk;
           cm[0] *= sk;
           factor_products<3>(cp, cm, Af[k]);
